@@ -1,0 +1,169 @@
+/*
+ * vbuf.h -- C ABI of libvbuf.so: the local Verlet buffer DEM step on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method (Mainassara Checkaraou, Besseron, Rousset, Qi, Peters, "Local Verlet
+ * buffer approach for broad-phase interaction detection in Discrete Element
+ * Method"):
+ *   - every particle p carries a skin  skin_p = K |v_p| dt        (Sec. 4.1, Eq. skin_formulus1)
+ *   - its broad-phase sphere is  R_NL,p = R_C,p + skin_p          (Sec. 4, Eq. bounding_sphere)
+ *     capped by the cell size                                     (Sec. 5.1, Eq. skin_formulus_mincell)
+ *   - the linked-cell broad phase on those spheres builds the Verlet list
+ *                                                                 (Sec. 3.2, Alg. 1)
+ *   - the list is reused while every particle's straight-line displacement since
+ *     the last broad phase is within its skin, and rebuilt otherwise
+ *                                                                 (Sec. 4.2, Eq. update, Def. autoverlet)
+ *   - the narrow phase tests each listed pair for overlap         (Sec. 3.2, Eq. delta)
+ *   - contact forces (normal linear spring-dashpot) and velocity-Verlet integration
+ *                                                                 (Sec. 3.1, Sec. 5.1)
+ * By the theorem of Sec. 4.2 the results equal those of running the broad phase
+ * at every step; this library reproduces that bit for bit (forces are summed in
+ * ascending original partner index whatever the list holds).
+ *
+ * Conventions common to every call:
+ *   - Pointers named d_* are device pointers on the context's device (for example
+ *     the data_ptr() of a PyTorch tensor); pointers named h_* are host pointers.
+ *     The caller owns every pointer it passes; the library never frees them and
+ *     keeps none of them after the call returns.
+ *   - The library owns its workspace (state buffers, cell arrays, Verlet lists),
+ *     allocated at create and grown when a list row overflows.
+ *   - Particle order at the boundary is always the caller's original order, with
+ *     the systems of a batch concatenated in creation order.  The internal
+ *     cell-sorted order is invisible.
+ *   - Every call returns a vb_status; on failure vb_last_error() gives a message
+ *     for that context.  No exception or abort crosses the ABI.
+ *   - All work of a context is queued on the HIP stream given at create; calls
+ *     that return host data synchronise that stream.  One context is not safe to
+ *     use from several host threads at once.
+ *   - Units are the caller's; the synthetic workloads use box units (the longest
+ *     box side is 1).
+ */
+#ifndef VBUF_H
+#define VBUF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vb_status;
+#define VB_OK 0
+#define VB_EINVAL (-1)      /* invalid argument or parameter                       */
+#define VB_ENOMEM (-2)      /* device or host allocation failed                    */
+#define VB_EDEVICE (-3)     /* a HIP call failed                                   */
+#define VB_ECAPACITY (-4)   /* a list row overflowed and could not be grown        */
+#define VB_ENONFINITE (-5)  /* NaN or Inf in the state                             */
+
+/* How the broad-phase sphere of each particle is extended. */
+#define VB_SKIN_LOCAL 0     /* skin_p = K |v_p| dt, the paper's local skin (Eq. skin_formulus1)  */
+#define VB_SKIN_UNIFORM 1   /* skin_p = skin_uniform, the classic global Verlet skin (Eq. skin_val) */
+#define VB_NO_BUFFER 2      /* broad phase at every step with R_NL = R_C, "without Verlet buffer" */
+#define VB_FIXED_INTERVAL 3 /* broad phase every fixed_interval steps with the uniform skin; the  */
+                            /* fixed-update practice the automatic scheme replaces (Sec. 1, 4.2)  */
+
+/* Parameters of one particle system.  Float fields are read as given; positions,
+ * velocities and the contact law are evaluated in FP64. */
+typedef struct vb_params {
+  int32_t skin_mode;      /* VB_SKIN_LOCAL, VB_SKIN_UNIFORM, VB_NO_BUFFER or VB_FIXED_INTERVAL   */
+  int32_t cap_mode;       /* 0: R_NL <= L_C/2, one-ring cell search (default);                   */
+                          /* 1: R_NL <= L_C as printed in Eq. skin_formulus_mincell, two-ring    */
+  double K;               /* skin factor, "the prescribed number of skipped steps" (Sec. 4.1)   */
+  double dt;              /* time step                                                            */
+  double cell_size;       /* L_C: the uniform cell edge of the linked-cell grid (Sec. 3.2)        */
+  double skin_uniform;    /* skin of VB_SKIN_UNIFORM and VB_FIXED_INTERVAL                        */
+  double eps;             /* absolute margin of the FP32 broad-phase inclusion test (>= 0)        */
+  double lo[3], hi[3];    /* box corners; a planar wall on each face                               */
+  double kn, gamma_n;     /* normal spring stiffness and dashpot coefficient                       */
+  double gravity[3];      /* gravitational acceleration                                            */
+  int32_t max_neighbors;  /* initial width of a Verlet-list row (grown on overflow), 1..1024      */
+  int32_t fixed_interval; /* broad-phase period of VB_FIXED_INTERVAL (>= 1)                        */
+} vb_params;
+
+/* Diagnostics of one time step n of one system (the state x^n whose forces the
+ * step evaluates, then its advance to x^{n+1}). */
+typedef struct vb_step_record {
+  int32_t step;           /* n                                                                    */
+  int32_t rebuilt;        /* 1 if a broad phase ran at x^n (Def. autoverlet)                       */
+  int64_t list_pairs;     /* unique pairs in the Verlet list used at x^n                           */
+  int64_t contacts;       /* unique pairs with positive overlap at x^n (Eq. delta)                 */
+  int64_t violators;      /* particles with |x^{n+1} - x0| > skin after the step (Eq. update)      */
+  float max_excess;       /* max over particles of |x^{n+1} - x0| - skin (FP32)                    */
+  int32_t reserved;
+  double kinetic_energy;  /* sum of m |v^n|^2 / 2 with the full-step velocity v^n                 */
+} vb_step_record;
+
+typedef struct vb_ctx vb_ctx;
+
+/* Create a context for one system of n particles (n >= 0).  stream is a
+ * hipStream_t (NULL for the default stream); *out receives the context.
+ * Errors: VB_EINVAL for a bad parameter, VB_ENOMEM, VB_EDEVICE. */
+vb_status vb_create(const vb_params *h_params, int64_t n, void *stream, vb_ctx **out);
+
+/* Create a context for n_sys independent systems solved together, one launch per
+ * phase for the whole batch.  h_params[s] and h_n[s] describe system s. */
+vb_status vb_batch_create(const vb_params *h_params, const int64_t *h_n, int32_t n_sys,
+                          void *stream, vb_ctx **out);
+
+/* Load the state, in original order, all systems concatenated:
+ *   d_x    [N][3] FP64 positions x^n
+ *   d_v    [N][3] FP64 velocities: the full-step velocity v^0 when v_is_half_step
+ *                 is 0 (a fresh start: the first step applies half a kick), or the
+ *                 half-step velocity v^{n-1/2} when 1 (a resume from vb_get_state)
+ *   d_rc   [N]    FP32 cut-off (contact) radius R_C > 0, with 2 R_C <= L_C (cap 0)
+ *                 or R_C <= L_C (cap 1)
+ *   d_invm [N]    FP32 inverse mass > 0
+ * The step counter restarts at 0 and the next step runs a broad phase (R7: the
+ * method assumes an initial broad phase).  Synchronises the stream.
+ * Errors: VB_ENONFINITE for NaN/Inf, VB_EINVAL for a radius or mass out of range. */
+vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const float *d_rc,
+                       const float *d_invm, int32_t v_is_half_step);
+
+/* Advance every system n_steps time steps.  h_hist, if not NULL, receives
+ * [n_sys][n_steps] records.  A list row that overflows is grown and the call's
+ * steps are run again from the call's starting state (results unchanged).
+ * Synchronises the stream.  Errors: VB_ECAPACITY if a row exceeds 1024 entries,
+ * VB_ENOMEM, VB_EDEVICE. */
+vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
+
+/* Copy the state out, original order: d_x [N][3] positions x^n and d_v [N][3]
+ * velocities (v^{n-1/2} after at least one step, else the loaded velocities).
+ * Either pointer may be NULL.  *h_v_is_half_step (if not NULL) tells which. */
+vb_status vb_get_state(vb_ctx *ctx, double *d_x, double *d_v, int32_t *h_v_is_half_step);
+
+/* The canonical unique list of one system as pairs (i, j), i < j, in original
+ * indices local to the system, sorted lexicographically:
+ *   which = 0: the Verlet list of the last broad phase (Def. verletlist);
+ *   which = 1: the contacts (overlap > 0) at the current positions, after the
+ *              broad phase that the next step would run if the list is invalid.
+ * d_pairs [cap][2] int32, d_delta [cap] FP64 overlaps (may be NULL).  *h_n receives
+ * the full count even if it exceeds cap (then only cap pairs are written).
+ * Synchronises the stream. */
+vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs,
+                       double *d_delta, int64_t cap, int64_t *h_n);
+
+/* Request a broad phase at the next step (all systems). */
+vb_status vb_force_rebuild(vb_ctx *ctx);
+
+/* Enable (1) or disable (0) per-kernel HIP-event timing of vb_run, and read the
+ * totals since timing was enabled: milliseconds spent in the broad-phase kernel
+ * launches and in the step-kernel launches, the number of steps timed and the
+ * number of steps at which any system ran a broad phase. */
+vb_status vb_set_timing(vb_ctx *ctx, int32_t on);
+vb_status vb_phase_times(vb_ctx *ctx, double *h_ms_rebuild, double *h_ms_step,
+                         int64_t *h_steps, int64_t *h_rebuild_steps);
+
+/* Sizes: total particles N, systems, current row width, current step counter. */
+vb_status vb_get_info(vb_ctx *ctx, int64_t *h_n_total, int32_t *h_n_sys,
+                      int32_t *h_row_width, int64_t *h_step);
+
+/* Message of the last failed call on ctx (ctx may be NULL for a failed create). */
+const char *vb_last_error(const vb_ctx *ctx);
+
+/* Release every resource of ctx (NULL is ignored).  Synchronises the stream. */
+void vb_destroy(vb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VBUF_H */

@@ -1,0 +1,47 @@
+"""Mutation check of the oracle's pins (test infrastructure).
+
+Copies the repository to a temporary directory, plants one plausible mistake at
+a time in oracle/orc.c (a flipped sign, a dropped term, a wrong index or
+inequality), and runs tests/test_oracle_pins.py against the mutant.  Every
+mutant must make at least one pin fail.  Usage: python oracle/mutation_check.py
+"""
+import os, shutil, subprocess, sys, tempfile
+SRC = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MUT = [
+ ("dashpot sign", "double fm = p->kn * delta - p->gamma_n * vn;", "double fm = p->kn * delta + p->gamma_n * vn;"),
+ ("normal flipped", "double nrm[3] = {(xi[0] - xj[0]) / d, (xi[1] - xj[1]) / d, (xi[2] - xj[2]) / d};", "double nrm[3] = {(xj[0] - xi[0]) / d, (xj[1] - xi[1]) / d, (xj[2] - xi[2]) / d};"),
+ ("full kick at first half", "vfull[a] = step == 0 ? vh[3 * i + a] : vh[3 * i + a] + hdt * acc;", "vfull[a] = step == 0 ? vh[3 * i + a] : vh[3 * i + a] + p->dt * acc;"),
+ ("skin without dt", "skin = p->K * norm3(v + 3 * i) * p->dt;", "skin = p->K * norm3(v + 3 * i);"),
+ ("no cap", "rnl[i] = r < cap ? r : cap;", "rnl[i] = r;"),
+ ("validity >=", "if (disp > skin_test[i]) viol++;", "if (disp >= skin_test[i]) viol++;"),
+ ("skip same cell", "if (cb == ca && pb >= pa) continue;", "if (cb == ca) continue;"),
+ ("hi wall sign", "if (dhi > 0.0) f[ax] -= p->kn * dhi - p->gamma_n * (-vi[ax]);", "if (dhi > 0.0) f[ax] += p->kn * dhi - p->gamma_n * (-vi[ax]);"),
+ ("contact >=", "if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(&C, i, j);", "if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) >= 0.0) pv_push(&C, i, j);"),
+ ("drift with vfull", "x[3 * i + a] = x[3 * i + a] + p->dt * vh[3 * i + a];", "x[3 * i + a] = x[3 * i + a] + p->dt * vfull[a];"),
+ ("x0 not refreshed", "memcpy(x0, x, n3 * sizeof(double));", ";"),
+ ("damping uses vi only", "double vn = (vi[0] - vj[0]) * nrm[0] + (vi[1] - vj[1]) * nrm[1] + (vi[2] - vj[2]) * nrm[2];", "double vn = (vi[0]) * nrm[0] + (vi[1]) * nrm[1] + (vi[2]) * nrm[2];"),
+ ("gravity dropped", "double acc = F[3 * i + a] * invm[i] + p->g[a];", "double acc = F[3 * i + a] * invm[i];"),
+ ("invm ignored", "double acc = F[3 * i + a] * invm[i] + p->g[a];", "double acc = F[3 * i + a] + p->g[a];"),
+ ("cell ring off by one", "for (int64_t dz = -ring; dz <= ring; dz++)", "for (int64_t dz = -ring + 1; dz <= ring; dz++)"),
+ ("broad brute strict", "if (dist3(x + 3 * i, x + 3 * j) <= r[i] + r[j] + eps) pv_push(out, (int32_t)i, (int32_t)j);", "if (dist3(x + 3 * i, x + 3 * j) < r[i] + r[j] + eps) pv_push(out, (int32_t)i, (int32_t)j);"),
+ ("skin from speed squared", "static double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }", "static double norm3(const double *a) { return (a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }"),
+ ("eps dropped in linked cell", "if (dist3(x + 3 * pa, x + 3 * pb) <= r[pa] + r[pb] + eps) {", "if (dist3(x + 3 * pa, x + 3 * pb) <= r[pa] + r[pb]) {"),
+]
+dst = os.path.join(tempfile.mkdtemp(prefix='orc_mut_'), 'repo')
+results = []
+survivors = 0
+for name, a, b in MUT:
+    if os.path.exists(dst): shutil.rmtree(os.path.dirname(dst))
+sys.exit(1 if survivors else 0)
+    shutil.copytree(SRC, dst, ignore=shutil.ignore_patterns('.git', '_work', 'gpurun_out', '*.so', '__pycache__'))
+    p = os.path.join(dst, 'oracle/orc.c')
+    s = open(p).read()
+    assert a in s, name
+    open(p, 'w').write(s.replace(a, b, 1))
+    r = subprocess.run([sys.executable, '-m', 'pytest', '-q', '-x', 'tests/test_oracle_pins.py', '-p', 'no:cacheprovider'], cwd=dst, capture_output=True, text=True)
+    last = [l for l in r.stdout.splitlines() if 'failed' in l or 'passed' in l][-1:]
+    results.append((name, r.returncode != 0, last))
+    survivors += r.returncode == 0
+    print(f"{name:28s} {'CAUGHT' if r.returncode else 'SURVIVED'} {last}", flush=True)
+shutil.rmtree(os.path.dirname(dst))
+sys.exit(1 if survivors else 0)
