@@ -76,7 +76,7 @@ typedef struct vb_params {
   double lo[3], hi[3];    /* box corners; a planar wall on each face                               */
   double kn, gamma_n;     /* normal spring stiffness and dashpot coefficient                       */
   double gravity[3];      /* gravitational acceleration                                            */
-  int32_t max_neighbors;  /* initial width of a Verlet-list row (grown on overflow), 1..1024      */
+  int32_t max_neighbors;  /* initial width of a Verlet-list row (grown on overflow), 1..128       */
   int32_t fixed_interval; /* broad-phase period of VB_FIXED_INTERVAL (>= 1)                        */
 } vb_params;
 
@@ -122,7 +122,7 @@ vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const 
 /* Advance every system n_steps time steps.  h_hist, if not NULL, receives
  * [n_sys][n_steps] records.  A list row that overflows is grown and the call's
  * steps are run again from the call's starting state (results unchanged).
- * Synchronises the stream.  Errors: VB_ECAPACITY if a row exceeds 1024 entries,
+ * Synchronises the stream.  Errors: VB_ECAPACITY if a row exceeds 128 entries,
  * VB_ENOMEM, VB_EDEVICE. */
 vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 

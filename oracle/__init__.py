@@ -23,6 +23,8 @@ class Params(ctypes.Structure):
         ("fixed_interval", ctypes.c_int32),
         ("check_superset", ctypes.c_int32),
         ("validity_uses_uncapped_skin", ctypes.c_int32),
+        ("v_in_is_half_step", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
         ("K", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("cell_size", ctypes.c_double),
@@ -92,6 +94,7 @@ def make_params(p: dict) -> Params:
     q.fixed_interval = int(p.get("fixed_interval", 1))
     q.check_superset = int(p.get("check_superset", 0))
     q.validity_uses_uncapped_skin = int(p.get("validity_uses_uncapped_skin", 0))
+    q.v_in_is_half_step = int(p.get("v_in_is_half_step", 0))
     for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n"):
         setattr(q, k, float(p.get(k, 0.0)))
     for k in ("lo", "hi", "g"):

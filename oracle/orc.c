@@ -414,7 +414,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
       double vfull[3];
       for (int a = 0; a < 3; a++) {
         double acc = F[3 * i + a] * invm[i] + p->g[a];
-        vfull[a] = step == 0 ? vh[3 * i + a] : vh[3 * i + a] + hdt * acc;
+        vfull[a] = (step == 0 && !p->v_in_is_half_step) ? vh[3 * i + a] : vh[3 * i + a] + hdt * acc;
         vh[3 * i + a] = vfull[a] + hdt * acc;
         x[3 * i + a] = x[3 * i + a] + p->dt * vh[3 * i + a];
       }

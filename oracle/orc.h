@@ -41,6 +41,9 @@ typedef struct {
   int32_t fixed_interval;  /* period for ORC_FIXED_INTERVAL                                   */
   int32_t check_superset;  /* 1: every step, count brute-force contacts missing from the list */
   int32_t validity_uses_uncapped_skin; /* planted mistake for a negative test; 0 normally    */
+  int32_t v_in_is_half_step; /* 1: v_in is a half-step velocity v^{n-1/2} (a resumed run): */
+                             /*    the first step applies both half kicks                  */
+  int32_t pad_;
   double K, dt, cell_size, skin_uniform, eps;
   double lo[3], hi[3];     /* box; a planar wall on each of the six faces                     */
   double kn, gamma_n;      /* normal linear spring-dashpot                                    */
@@ -86,7 +89,8 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
                const double *rc, int64_t ncontacts, const int32_t *contacts, double *F);
 
-/* Run n_steps steps from (x_in, v_in) where v_in is the full-step velocity v^0.
+/* Run n_steps steps from (x_in, v_in) where v_in is the full-step velocity v^0
+ * (or the half-step velocity v^{n-1/2} when v_in_is_half_step is set).
  * Outputs x^S and the half-step velocity v^{S-1/2} (v^0 if n_steps == 0).
  * hist (n_steps records) and the final list (list_out, cap, *list_n) are optional.
  * Returns 0, -1 bad parameters, -2 out of memory, -3 list_out too small. */

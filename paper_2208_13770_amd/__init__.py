@@ -1,0 +1,221 @@
+"""Local Verlet buffer DEM step on AMD Instinct MI355X: Python binding of libvbuf.so.
+
+The functions below carry the names of the C ABI in include/vbuf.h and only
+marshal arguments: every step of the method runs in the library's HIP kernels.
+Device buffers are PyTorch tensors (their data_ptr()), the stream is PyTorch's
+current stream.  A missing library is an error, never a fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvbuf.so")
+
+VB_OK, VB_EINVAL, VB_ENOMEM, VB_EDEVICE, VB_ECAPACITY, VB_ENONFINITE = 0, -1, -2, -3, -4, -5
+VB_SKIN_LOCAL, VB_SKIN_UNIFORM, VB_NO_BUFFER, VB_FIXED_INTERVAL = 0, 1, 2, 3
+
+
+class vb_params(ctypes.Structure):
+    _fields_ = [
+        ("skin_mode", ctypes.c_int32),
+        ("cap_mode", ctypes.c_int32),
+        ("K", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("cell_size", ctypes.c_double),
+        ("skin_uniform", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("kn", ctypes.c_double),
+        ("gamma_n", ctypes.c_double),
+        ("gravity", ctypes.c_double * 3),
+        ("max_neighbors", ctypes.c_int32),
+        ("fixed_interval", ctypes.c_int32),
+    ]
+
+
+STEP_RECORD_DTYPE = np.dtype([
+    ("step", np.int32), ("rebuilt", np.int32), ("list_pairs", np.int64),
+    ("contacts", np.int64), ("violators", np.int64), ("max_excess", np.float32),
+    ("reserved", np.int32), ("kinetic_energy", np.float64),
+])
+assert STEP_RECORD_DTYPE.itemsize == 48
+
+# name -> (restype, argtypes), in the order of include/vbuf.h
+_P = ctypes.c_void_p
+_SIGNATURES = {
+    "vb_create": (ctypes.c_int32, [ctypes.POINTER(vb_params), ctypes.c_int64, _P,
+                                   ctypes.POINTER(_P)]),
+    "vb_batch_create": (ctypes.c_int32, [ctypes.POINTER(vb_params), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "vb_set_state": (ctypes.c_int32, [_P, _P, _P, _P, _P, ctypes.c_int32]),
+    "vb_run": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    "vb_get_state": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "vb_get_pairs": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64)]),
+    "vb_force_rebuild": (ctypes.c_int32, [_P]),
+    "vb_set_timing": (ctypes.c_int32, [_P, ctypes.c_int32]),
+    "vb_phase_times": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "vb_get_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "vb_last_error": (ctypes.c_char_p, [_P]),
+    "vb_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+class VbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libvbuf error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """The loaded library.  PyTorch is imported first so that the library binds
+    to the HIP runtime PyTorch already loaded (one runtime per process)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the library must share)
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "python -c 'import __graft_entry__ as g; g.build()'")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, ctx=None):
+    if code != VB_OK:
+        msg = lib().vb_last_error(ctx)
+        raise VbError(code, msg.decode() if msg else "")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_params(p: dict) -> vb_params:
+    """vb_params from a plain dict (the synthetic generator's parameter dicts)."""
+    q = vb_params()
+    q.skin_mode = int(p.get("skin_mode", VB_SKIN_LOCAL))
+    q.cap_mode = int(p.get("cap_mode", 0))
+    for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n"):
+        setattr(q, k, float(p.get(k, 0.0)))
+    q.lo[:] = [float(t) for t in p.get("lo", (0.0, 0.0, 0.0))]
+    q.hi[:] = [float(t) for t in p.get("hi", (1.0, 1.0, 1.0))]
+    q.gravity[:] = [float(t) for t in p.get("g", p.get("gravity", (0.0, 0.0, 0.0)))]
+    q.max_neighbors = int(p.get("max_neighbors", 32))
+    q.fixed_interval = int(p.get("fixed_interval", 1))
+    return q
+
+
+def vb_create(params, n, stream=None):
+    ctx = ctypes.c_void_p()
+    q = params if isinstance(params, vb_params) else make_params(params)
+    _check(lib().vb_create(ctypes.byref(q), int(n), stream if stream is not None else _stream(),
+                           ctypes.byref(ctx)))
+    return ctx
+
+
+def vb_batch_create(params_list, n_list, stream=None):
+    arr = (vb_params * len(params_list))(
+        *[p if isinstance(p, vb_params) else make_params(p) for p in params_list])
+    ns = (ctypes.c_int64 * len(n_list))(*[int(n) for n in n_list])
+    ctx = ctypes.c_void_p()
+    _check(lib().vb_batch_create(arr, ns, len(params_list),
+                                 stream if stream is not None else _stream(), ctypes.byref(ctx)))
+    return ctx
+
+
+def vb_set_state(ctx, x, v, rc, invm, v_is_half_step=False):
+    """x, v: float64 [N,3] device tensors; rc, invm: float32 [N] device tensors."""
+    _check(lib().vb_set_state(ctx, x.data_ptr(), v.data_ptr(), rc.data_ptr(), invm.data_ptr(),
+                              int(bool(v_is_half_step))), ctx)
+
+
+def vb_run(ctx, n_steps, want_history=True):
+    """Advance n_steps; returns the [n_sys, n_steps] step records (or None)."""
+    n_sys = vb_get_info(ctx)["n_sys"] if want_history else 0
+    hist = np.zeros((n_sys, max(n_steps, 0)), dtype=STEP_RECORD_DTYPE) if want_history else None
+    ptr = hist.ctypes.data_as(ctypes.c_void_p) if want_history and n_steps > 0 else None
+    _check(lib().vb_run(ctx, int(n_steps), ptr), ctx)
+    return hist
+
+
+def vb_get_state(ctx, x=None, v=None):
+    half = ctypes.c_int32(0)
+    _check(lib().vb_get_state(ctx, x.data_ptr() if x is not None else None,
+                              v.data_ptr() if v is not None else None, ctypes.byref(half)), ctx)
+    return bool(half.value)
+
+
+def vb_get_pairs(ctx, sys, which, pairs=None, delta=None):
+    """Fills pairs (int32 [cap,2]) and delta (float64 [cap]) device tensors; returns
+    the total count.  Call with pairs=None to get the count only."""
+    n = ctypes.c_int64(0)
+    cap = int(pairs.shape[0]) if pairs is not None else 0
+    _check(lib().vb_get_pairs(ctx, int(sys), int(which),
+                              pairs.data_ptr() if pairs is not None else None,
+                              delta.data_ptr() if delta is not None else None, cap,
+                              ctypes.byref(n)), ctx)
+    return int(n.value)
+
+
+def vb_force_rebuild(ctx):
+    _check(lib().vb_force_rebuild(ctx), ctx)
+
+
+def vb_set_timing(ctx, on):
+    _check(lib().vb_set_timing(ctx, int(bool(on))), ctx)
+
+
+def vb_phase_times(ctx):
+    a, b = ctypes.c_double(0), ctypes.c_double(0)
+    c, d = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().vb_phase_times(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                ctypes.byref(d)), ctx)
+    return {"ms_rebuild": a.value, "ms_step": b.value, "steps": c.value,
+            "rebuild_steps": d.value}
+
+
+def vb_get_info(ctx):
+    n, s, w, st = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int64(0)
+    _check(lib().vb_get_info(ctx, ctypes.byref(n), ctypes.byref(s), ctypes.byref(w),
+                             ctypes.byref(st)), ctx)
+    return {"n_total": n.value, "n_sys": s.value, "row_width": w.value, "step": st.value}
+
+
+def vb_last_error(ctx=None):
+    m = lib().vb_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def vb_destroy(ctx):
+    if ctx is not None:
+        lib().vb_destroy(ctx)
+
+
+def state_tensors(systems, device="cuda"):
+    """Concatenate synthetic systems into the device tensors vb_set_state takes:
+    x, v float64 [N,3]; rc, invm float32 [N]."""
+    import torch
+    pos = np.concatenate([s.pos_r for s in systems], axis=0)
+    vel = np.concatenate([s.vel_m for s in systems], axis=0)
+    x = torch.from_numpy(pos[:, :3].astype(np.float64)).to(device)
+    v = torch.from_numpy(vel[:, :3].astype(np.float64)).to(device)
+    rc = torch.from_numpy(np.ascontiguousarray(pos[:, 3])).to(device)
+    invm = torch.from_numpy(np.ascontiguousarray(vel[:, 3])).to(device)
+    return x, v, rc, invm

@@ -1,0 +1,630 @@
+// vb_abi.hip -- host implementation of the C ABI declared in include/vbuf.h.
+//
+// A context holds one batch of independent particle systems.  Each step queues
+// two launches on the context's stream: the cooperative broad-phase kernel
+// (which returns at once unless some system's list went invalid at the previous
+// step, Def. autoverlet) and the fused step kernel.  The host never reads the
+// validity flag; it synchronises once per vb_run call, to collect the per-step
+// records and to check that no Verlet-list row overflowed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vbuf.h"
+#include "vb_device.h"
+
+namespace vb {
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, hipStream_t st);
+hipError_t rebuild_occupancy(int width, int *blocks_per_cu);
+hipError_t launch_rebuild(const RebuildArgs &a, int grid, hipStream_t st);
+hipError_t launch_log_rebuilt(const int32_t *rebuilt_at, int32_t n_sys, int32_t step,
+                              int32_t *ring, hipStream_t st);
+hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
+                               int64_t n_tiles, int32_t n_sys, int32_t step0, int32_t nsteps,
+                               RecordDev *out, hipStream_t st);
+hipError_t launch_set_state(const SysDev &S, PX *px, PV *pv, const double *x, const double *v,
+                            const float *rc, const float *invm, int32_t *err, hipStream_t st);
+hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                            const PX *px, const PV *pv, double *x, double *v, hipStream_t st);
+hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const int32_t *nbr,
+                        int64_t stride, int32_t contacts_only, int32_t *counts, int64_t *offsets,
+                        int64_t *total, int64_t cap, int32_t *pairs, double *delta,
+                        hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+}  // namespace vb
+
+using namespace vb;
+
+static_assert(sizeof(vb_step_record) == sizeof(RecordDev), "record layouts match");
+
+struct vb_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 0;
+  int32_t n_sys = 0;
+  int64_t n_total = 0, slots = 0, n_tiles = 0, n_cells = 0;
+  int32_t max_n = 0;
+  std::vector<SysDev> sys_h;
+  SysDev *sys_d = nullptr;
+  int32_t *tile_sys = nullptr;
+  PX *px[2] = {nullptr, nullptr};
+  PV *pv[2] = {nullptr, nullptr};
+  PX *px_tmp = nullptr;
+  PV *pv_tmp = nullptr;
+  PX *snap_px = nullptr;
+  PV *snap_pv = nullptr;
+  float4 *bp = nullptr;
+  int32_t *cnt = nullptr, *nbr = nullptr;
+  int32_t width = 0;
+  int32_t *cell_count = nullptr, *cell_start = nullptr, *block_sum = nullptr;
+  int32_t *cellid = nullptr, *cellid_new = nullptr, *inslot = nullptr;
+  int32_t *perm0 = nullptr, *perm = nullptr, *inv = nullptr;
+  int32_t *rebuilt_at = nullptr, *flags = nullptr, *overflow = nullptr, *err = nullptr;
+  TileStats *stats = nullptr;
+  int32_t *rebuilt_ring = nullptr;
+  RecordDev *hist_d = nullptr;
+  int64_t hist_cap = 0;
+  int32_t *pair_counts = nullptr;
+  int64_t *pair_offsets = nullptr, *pair_total = nullptr;
+  int rebuild_grid = 0;
+  int cur = 0;
+  int64_t step = 0;
+  int first = 1;
+  int force_pending = 1;
+  int loaded = 0;
+  int xcd_remap = 1;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  double ms_rebuild = 0.0, ms_step = 0.0;
+  int64_t t_steps = 0, t_rebuild_steps = 0;
+  std::string msg;
+};
+
+static thread_local std::string g_create_error;
+
+static vb_status fail(vb_ctx *c, vb_status code, const std::string &m) {
+  if (c) c->msg = m;
+  else g_create_error = m;
+  return code;
+}
+
+#define HIP_OK(ctx, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((ctx), e_ == hipErrorOutOfMemory ? VB_ENOMEM : VB_EDEVICE,          \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+template <typename T>
+static hipError_t dalloc(T **p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  return hipMalloc(reinterpret_cast<void **>(p), (size_t)count * sizeof(T));
+}
+
+static void free_all(vb_ctx *c) {
+  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->px_tmp,
+                  c->pv_tmp, c->snap_px, c->snap_pv, c->bp, c->cnt, c->nbr, c->cell_count,
+                  c->cell_start, c->block_sum, c->cellid, c->cellid_new, c->inslot, c->perm0,
+                  c->perm, c->inv, c->rebuilt_at, c->flags, c->overflow, c->err, c->stats,
+                  c->rebuilt_ring, c->hist_d, c->pair_counts, c->pair_offsets, c->pair_total};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+}
+
+static std::string check_params(const vb_params &p, int64_t n) {
+  if (n < 0) return "n < 0";
+  if (n > (int64_t)INT32_MAX - TILE) return "n too large for one system";
+  if (p.skin_mode < 0 || p.skin_mode > 3) return "skin_mode must be 0..3";
+  if (p.cap_mode != 0 && p.cap_mode != 1) return "cap_mode must be 0 or 1";
+  if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return "dt must be positive";
+  if (!(p.cell_size > 0.0) || !std::isfinite(p.cell_size)) return "cell_size must be positive";
+  if (!(p.K >= 0.0) || !std::isfinite(p.K)) return "K must be >= 0";
+  if (!(p.eps >= 0.0) || !std::isfinite(p.eps)) return "eps must be >= 0";
+  if (!(p.skin_uniform >= 0.0) || !std::isfinite(p.skin_uniform)) return "skin_uniform must be >= 0";
+  if (!(p.kn >= 0.0) || !(p.gamma_n >= 0.0) || !std::isfinite(p.kn) || !std::isfinite(p.gamma_n))
+    return "kn and gamma_n must be finite and >= 0";
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(p.lo[a]) || !std::isfinite(p.hi[a]) || !(p.hi[a] > p.lo[a]))
+      return "box must satisfy lo < hi";
+    if (!std::isfinite(p.gravity[a])) return "gravity must be finite";
+  }
+  if (p.max_neighbors < 1 || p.max_neighbors > MAX_ROW) return "max_neighbors must be 1..128";
+  if (p.skin_mode == VB_FIXED_INTERVAL && p.fixed_interval < 1) return "fixed_interval must be >= 1";
+  return "";
+}
+
+// Cell grid of one system: cells of edge at least L_C (1 + 2^-10) + 2 eps per
+// axis, so that every pair the FP32 inclusion test may accept lies in cells at
+// most `ring` apart (Sec. 3.2: cells not smaller than the bounding spheres).
+static void make_grid(const vb_params &p, SysDev &S) {
+  const double edge_min = p.cell_size * (1.0 + 1.0 / 1024.0) + 2.0 * p.eps;
+  int64_t ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    const double len = p.hi[a] - p.lo[a];
+    double k = std::floor(len / edge_min);
+    if (k < 1) k = 1;
+    if (k > 1 << 20) k = 1 << 20;
+    S.nc[a] = (int32_t)k;
+    S.inv_edge[a] = k / len;
+    ncell *= (int64_t)k;
+  }
+  S.ncell = (int32_t)std::min<int64_t>(ncell, INT32_MAX);
+}
+
+static vb_status alloc_rows(vb_ctx *c, int32_t width) {
+  if (c->nbr) (void)hipFree(c->nbr);
+  c->nbr = nullptr;
+  HIP_OK(c, dalloc(&c->nbr, c->slots * (int64_t)width));
+  c->width = width;
+  int bpc = 0;
+  HIP_OK(c, rebuild_occupancy(width, &bpc));
+  if (bpc < 1) return fail(c, VB_ECAPACITY, "row width too large for the broad-phase kernel");
+  // the cooperative grid: every workgroup resident at once, no more than there is work
+  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(c->n_tiles, (int64_t)bpc * c->n_cu));
+  c->rebuild_grid = (int)want;
+  if (c->block_sum) (void)hipFree(c->block_sum);
+  c->block_sum = nullptr;
+  HIP_OK(c, dalloc(&c->block_sum, c->rebuild_grid));
+  return VB_OK;
+}
+
+static vb_status alloc_hist(vb_ctx *c, int64_t steps) {
+  const int64_t need = std::max<int64_t>(steps, STATS_RING) * c->n_sys;
+  if (need <= c->hist_cap) return VB_OK;
+  if (c->hist_d) (void)hipFree(c->hist_d);
+  c->hist_d = nullptr;
+  HIP_OK(c, dalloc(&c->hist_d, need));
+  c->hist_cap = need;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h_n,
+                                     int32_t n_sys, void *stream, vb_ctx **out) {
+  if (!out) return fail(nullptr, VB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!h_params || !h_n) return fail(nullptr, VB_EINVAL, "params or sizes NULL");
+  if (n_sys < 1 || n_sys > MAX_SYS) return fail(nullptr, VB_EINVAL, "n_sys must be 1..1024");
+  for (int s = 0; s < n_sys; ++s) {
+    std::string m = check_params(h_params[s], h_n[s]);
+    if (!m.empty()) return fail(nullptr, VB_EINVAL, "system " + std::to_string(s) + ": " + m);
+  }
+  vb_ctx *c = new (std::nothrow) vb_ctx();
+  if (!c) return fail(nullptr, VB_ENOMEM, "host allocation failed");
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  const char *env = std::getenv("VBUF_XCD_REMAP");
+  if (env) c->xcd_remap = std::atoi(env) != 0;
+  vb_status st = VB_OK;
+  auto bail = [&](vb_status code) {
+    g_create_error = c->msg;
+    free_all(c);
+    delete c;
+    return code;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    c->msg = "hipGetDevice failed";
+    return bail(VB_EDEVICE);
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+    c->msg = "hipGetDeviceProperties failed";
+    return bail(VB_EDEVICE);
+  }
+  c->n_cu = prop.multiProcessorCount;
+  c->n_sys = n_sys;
+  c->sys_h.resize(n_sys);
+  int64_t p_off = 0, t_off = 0, c_off = 0, o_off = 0;
+  int32_t width = 1;
+  for (int s = 0; s < n_sys; ++s) {
+    const vb_params &p = h_params[s];
+    SysDev &S = c->sys_h[s];
+    std::memset(&S, 0, sizeof(S));
+    S.n = (int32_t)h_n[s];
+    S.n_tiles = (int32_t)((h_n[s] + TILE - 1) / TILE);
+    S.p_off = p_off;
+    S.tile_off = t_off;
+    S.c_off = c_off;
+    S.o_off = o_off;
+    make_grid(p, S);
+    if ((int64_t)S.nc[0] * S.nc[1] * S.nc[2] > (1LL << 30)) {
+      c->msg = "system " + std::to_string(s) + ": cell grid too fine for the box";
+      return bail(VB_EINVAL);
+    }
+    S.dt = p.dt;
+    S.K = p.K;
+    S.kn = p.kn;
+    S.gamma_n = p.gamma_n;
+    S.skin_uniform = p.skin_uniform;
+    S.cap = p.cap_mode == 0 ? 0.5 * p.cell_size : p.cell_size;
+    for (int a = 0; a < 3; ++a) {
+      S.lo[a] = p.lo[a];
+      S.hi[a] = p.hi[a];
+      S.g[a] = p.gravity[a];
+    }
+    S.eps = (float)p.eps;
+    S.skin_mode = p.skin_mode;
+    S.fixed_interval = p.fixed_interval < 1 ? 1 : p.fixed_interval;
+    S.ring = p.cap_mode == 0 ? 1 : 2;
+    p_off += (int64_t)S.n_tiles * TILE;
+    t_off += S.n_tiles;
+    c_off += S.ncell;
+    o_off += S.n;
+    width = std::max(width, p.max_neighbors);
+    c->max_n = std::max(c->max_n, S.n);
+  }
+  c->slots = p_off;
+  c->n_tiles = t_off;
+  c->n_cells = c_off;
+  c->n_total = o_off;
+  if (c->slots > (int64_t)INT32_MAX) {
+    c->msg = "batch too large";
+    return bail(VB_EINVAL);
+  }
+  std::vector<int32_t> ts(std::max<int64_t>(c->n_tiles, 1), 0);
+  for (int s = 0; s < n_sys; ++s)
+    for (int t = 0; t < c->sys_h[s].n_tiles; ++t) ts[c->sys_h[s].tile_off + t] = s;
+
+#define ALLOC(ptr, count)                                         \
+  if (dalloc(&(ptr), (count)) != hipSuccess) {                    \
+    c->msg = "device allocation failed: " #ptr;                   \
+    return bail(VB_ENOMEM);                                       \
+  }
+  ALLOC(c->sys_d, n_sys);
+  ALLOC(c->tile_sys, c->n_tiles);
+  for (int b = 0; b < 2; ++b) {
+    ALLOC(c->px[b], c->slots);
+    ALLOC(c->pv[b], c->slots);
+  }
+  ALLOC(c->px_tmp, c->slots);
+  ALLOC(c->pv_tmp, c->slots);
+  ALLOC(c->bp, c->slots);
+  ALLOC(c->cnt, c->slots);
+  ALLOC(c->cell_count, c->n_cells);
+  ALLOC(c->cell_start, c->n_cells + 1);
+  ALLOC(c->cellid, c->slots);
+  ALLOC(c->cellid_new, c->slots);
+  ALLOC(c->inslot, c->slots);
+  ALLOC(c->perm0, c->slots);
+  ALLOC(c->perm, c->slots);
+  ALLOC(c->inv, c->slots);
+  ALLOC(c->rebuilt_at, n_sys);
+  ALLOC(c->flags, 2 * n_sys);
+  ALLOC(c->overflow, 1);
+  ALLOC(c->err, 1);
+  ALLOC(c->stats, (int64_t)STATS_RING * std::max<int64_t>(c->n_tiles, 1));
+  ALLOC(c->rebuilt_ring, (int64_t)STATS_RING * n_sys);
+  ALLOC(c->pair_counts, std::max<int32_t>(c->max_n, 1));
+  ALLOC(c->pair_offsets, std::max<int32_t>(c->max_n, 1));
+  ALLOC(c->pair_total, 1);
+#undef ALLOC
+  if ((st = alloc_rows(c, width)) != VB_OK) return bail(st);
+  if ((st = alloc_hist(c, STATS_RING)) != VB_OK) return bail(st);
+  if (hipMemcpy(c->sys_d, c->sys_h.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->tile_sys, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(c->cell_count, 0, sizeof(int32_t) * std::max<int64_t>(c->n_cells, 1)) !=
+          hipSuccess ||
+      hipMemset(c->cnt, 0, sizeof(int32_t) * c->slots) != hipSuccess ||
+      hipMemset(c->flags, 0, sizeof(int32_t) * 2 * n_sys) != hipSuccess ||
+      hipMemset(c->overflow, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(c->rebuilt_ring, 0, sizeof(int32_t) * STATS_RING * n_sys) != hipSuccess ||
+      hipMemset(c->rebuilt_at, 0xFF, sizeof(int32_t) * n_sys) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    c->msg = "device initialisation failed";
+    return bail(VB_EDEVICE);
+  }
+  *out = c;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_create(const vb_params *h_params, int64_t n, void *stream,
+                               vb_ctx **out) {
+  return vb_batch_create(h_params, &n, 1, stream, out);
+}
+
+// Clears the per-run control state on the stream: no pending violation, no
+// broad phase recorded, no overflow.
+static vb_status reset_control(vb_ctx *c) {
+  HIP_OK(c, launch_fill_i32(c->flags, 2 * c->n_sys, 0, c->stream));
+  HIP_OK(c, launch_fill_i32(c->rebuilt_at, c->n_sys, -1, c->stream));
+  HIP_OK(c, launch_fill_i32(c->overflow, 1, 0, c->stream));
+  return VB_OK;
+}
+
+extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_v,
+                                  const float *d_rc, const float *d_invm,
+                                  int32_t v_is_half_step) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (c->n_total > 0 && (!d_x || !d_v || !d_rc || !d_invm))
+    return fail(c, VB_EINVAL, "state pointers must not be NULL");
+  HIP_OK(c, launch_fill_i32(c->err, 1, 0, c->stream));
+  for (int s = 0; s < c->n_sys; ++s)
+    HIP_OK(c, launch_set_state(c->sys_h[s], c->px[0], c->pv[0], d_x, d_v, d_rc, d_invm, c->err,
+                               c->stream));
+  HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
+  vb_status st = reset_control(c);
+  if (st != VB_OK) return st;
+  int32_t err = 0;
+  HIP_OK(c, hipMemcpyAsync(&err, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->loaded = 0;
+  if (err & 1) return fail(c, VB_ENONFINITE, "state holds NaN or Inf");
+  if (err & 2) return fail(c, VB_EINVAL, "a radius is <= 0 or exceeds the cap of R_NL");
+  if (err & 4) return fail(c, VB_EINVAL, "an inverse mass is <= 0");
+  c->cur = 0;
+  c->step = 0;
+  c->first = v_is_half_step ? 0 : 1;
+  c->force_pending = 1;
+  c->loaded = 1;
+  return VB_OK;
+}
+
+static RebuildArgs rebuild_args(vb_ctx *c, int force) {
+  RebuildArgs a;
+  a.sys = c->sys_d;
+  a.tile_sys = c->tile_sys;
+  a.n_sys = c->n_sys;
+  a.n_tiles = c->n_tiles;
+  a.n_cells = c->n_cells;
+  a.px_cur = c->px[c->cur];
+  a.pv_cur = c->pv[c->cur];
+  a.px_tmp = c->px_tmp;
+  a.pv_tmp = c->pv_tmp;
+  a.bp = c->bp;
+  a.cnt = c->cnt;
+  a.nbr = c->nbr;
+  a.stride = c->slots;
+  a.width = c->width;
+  a.cell_count = c->cell_count;
+  a.cell_start = c->cell_start;
+  a.block_sum = c->block_sum;
+  a.cellid = c->cellid;
+  a.cellid_new = c->cellid_new;
+  a.inslot = c->inslot;
+  a.perm0 = c->perm0;
+  a.perm = c->perm;
+  a.inv = c->inv;
+  a.rebuilt_at = c->rebuilt_at;
+  a.flags = c->flags;
+  a.overflow = c->overflow;
+  a.step = (int32_t)c->step;
+  a.force = force;
+  return a;
+}
+
+// Queues the broad-phase launch of the current step (a no-op on the device
+// unless a system needs one).
+static vb_status queue_rebuild(vb_ctx *c) {
+  const RebuildArgs a = rebuild_args(c, c->force_pending);
+  HIP_OK(c, launch_rebuild(a, c->rebuild_grid, c->stream));
+  c->force_pending = 0;
+  return VB_OK;
+}
+
+static vb_status queue_step(vb_ctx *c) {
+  StepArgs a;
+  a.sys = c->sys_d;
+  a.tile_sys = c->tile_sys;
+  a.px_cur = c->px[c->cur];
+  a.pv_cur = c->pv[c->cur];
+  a.px_tmp = c->px_tmp;
+  a.pv_tmp = c->pv_tmp;
+  a.px_dst = c->px[c->cur ^ 1];
+  a.pv_dst = c->pv[c->cur ^ 1];
+  a.bp = c->bp;
+  a.cnt = c->cnt;
+  a.nbr = c->nbr;
+  a.stride = c->slots;
+  a.rebuilt_at = c->rebuilt_at;
+  a.flags = c->flags;
+  a.n_sys = c->n_sys;
+  a.stats = c->stats;
+  a.n_tiles = c->n_tiles;
+  a.step = (int32_t)c->step;
+  a.first = c->first;
+  a.xcd_remap = c->xcd_remap;
+  HIP_OK(c, launch_step(a, c->n_tiles, c->stream));
+  HIP_OK(c, launch_log_rebuilt(c->rebuilt_at, c->n_sys, (int32_t)c->step, c->rebuilt_ring,
+                               c->stream));
+  return VB_OK;
+}
+
+static vb_status ensure_events(vb_ctx *c, size_t n) {
+  while (c->ev.size() < n) {
+    hipEvent_t e;
+    HIP_OK(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  return VB_OK;
+}
+
+// Runs n_steps steps; records go to hist_d[r * n_sys + s].
+static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
+  vb_status st;
+  if (c->timing && (st = ensure_events(c, 3 * (size_t)n_steps)) != VB_OK) return st;
+  int32_t pending = 0;
+  for (int32_t i = 0; i < n_steps; ++i) {
+    if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i], c->stream));
+    if ((st = queue_rebuild(c)) != VB_OK) return st;
+    if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i + 1], c->stream));
+    if ((st = queue_step(c)) != VB_OK) return st;
+    if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i + 2], c->stream));
+    c->first = 0;
+    c->cur ^= 1;
+    c->step += 1;
+    ++pending;
+    if (pending == STATS_RING || i == n_steps - 1) {
+      HIP_OK(c, launch_stats_reduce(c->sys_d, c->stats, c->rebuilt_ring, c->n_tiles, c->n_sys,
+                                    (int32_t)(c->step - pending), pending,
+                                    c->hist_d + (int64_t)(i + 1 - pending) * c->n_sys,
+                                    c->stream));
+      pending = 0;
+    }
+  }
+  return VB_OK;
+}
+
+extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded (vb_set_state)");
+  if (n_steps < 0) return fail(c, VB_EINVAL, "n_steps < 0");
+  if (n_steps == 0) return VB_OK;
+  if (c->step + n_steps > (int64_t)INT32_MAX) return fail(c, VB_EINVAL, "step counter overflow");
+  vb_status st;
+  if ((st = alloc_hist(c, n_steps)) != VB_OK) return st;
+  if (!c->snap_px) {
+    HIP_OK(c, dalloc(&c->snap_px, c->slots));
+    HIP_OK(c, dalloc(&c->snap_pv, c->slots));
+  }
+  // starting state, to run the call again if a list row overflows
+  HIP_OK(c, hipMemcpyAsync(c->snap_px, c->px[c->cur], sizeof(PX) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->snap_pv, c->pv[c->cur], sizeof(PV) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  const int64_t step0 = c->step;
+  const int first0 = c->first, force0 = c->force_pending;
+  for (int attempt = 0;; ++attempt) {
+    if ((st = run_steps(c, n_steps)) != VB_OK) return st;
+    int32_t ovf = 0;
+    HIP_OK(c, hipMemcpyAsync(&ovf, c->overflow, sizeof(int32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (ovf <= c->width) break;
+    if (ovf > MAX_ROW || attempt >= 4) {
+      c->loaded = 0;
+      return fail(c, VB_ECAPACITY,
+                  "a Verlet-list row needs " + std::to_string(ovf) + " entries (limit 128)");
+    }
+    // grow the rows and start again from the call's first step; the forced
+    // broad phase changes the schedule, not the results (theorem of Sec. 4.2)
+    const int32_t w = std::min<int32_t>(MAX_ROW, (ovf + ovf / 4 + 7) / 8 * 8);
+    if ((st = alloc_rows(c, w)) != VB_OK) return st;
+    HIP_OK(c, hipMemcpyAsync(c->px[0], c->snap_px, sizeof(PX) * c->slots,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
+    if ((st = reset_control(c)) != VB_OK) return st;
+    c->cur = 0;
+    c->step = step0;
+    c->first = first0;
+    c->force_pending = 1;
+    (void)force0;
+  }
+  std::vector<vb_step_record> rec((size_t)n_steps * c->n_sys);
+  HIP_OK(c, hipMemcpy(rec.data(), c->hist_d, sizeof(vb_step_record) * rec.size(),
+                      hipMemcpyDeviceToHost));
+  if (h_hist)
+    for (int s = 0; s < c->n_sys; ++s)
+      for (int32_t r = 0; r < n_steps; ++r)
+        h_hist[(int64_t)s * n_steps + r] = rec[(size_t)r * c->n_sys + s];
+  if (c->timing) {
+    for (int32_t i = 0; i < n_steps; ++i) {
+      float a = 0.f, b = 0.f;
+      HIP_OK(c, hipEventElapsedTime(&a, c->ev[3 * i], c->ev[3 * i + 1]));
+      HIP_OK(c, hipEventElapsedTime(&b, c->ev[3 * i + 1], c->ev[3 * i + 2]));
+      c->ms_rebuild += a;
+      c->ms_step += b;
+      int any = 0;
+      for (int s = 0; s < c->n_sys; ++s) any |= rec[(size_t)i * c->n_sys + s].rebuilt;
+      c->t_rebuild_steps += any;
+    }
+    c->t_steps += n_steps;
+  }
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_state(vb_ctx *c, double *d_x, double *d_v,
+                                  int32_t *h_v_is_half_step) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded");
+  HIP_OK(c, launch_get_state(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], c->pv[c->cur],
+                             d_x, d_v, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (h_v_is_half_step) *h_v_is_half_step = c->first ? 0 : 1;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_pairs(vb_ctx *c, int32_t sys, int32_t which, int32_t *d_pairs,
+                                  double *d_delta, int64_t cap, int64_t *h_n) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded");
+  if (sys < 0 || sys >= c->n_sys) return fail(c, VB_EINVAL, "sys out of range");
+  if (which != 0 && which != 1) return fail(c, VB_EINVAL, "which must be 0 or 1");
+  if (cap < 0 || (cap > 0 && !d_pairs)) return fail(c, VB_EINVAL, "bad output buffer");
+  vb_status st;
+  if (which == 1 && (st = queue_rebuild(c)) != VB_OK) return st;
+  int32_t ra = -1;
+  HIP_OK(c, hipMemcpyAsync(&ra, c->rebuilt_at + sys, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  // rows follow the slot order of the last broad phase: the permuted copy if it
+  // ran at this step, else the current state (which keeps that order)
+  const PX *src = (ra == (int32_t)c->step) ? c->px_tmp : c->px[c->cur];
+  HIP_OK(c, launch_pairs(c->sys_h[sys], src, c->cnt, c->nbr, c->slots, which, c->pair_counts,
+                         c->pair_offsets, c->pair_total, cap, cap > 0 ? d_pairs : nullptr,
+                         cap > 0 ? d_delta : nullptr, c->stream));
+  int64_t total = 0;
+  HIP_OK(c, hipMemcpyAsync(&total, c->pair_total, sizeof(int64_t), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->sys_h[sys].n == 0) total = 0;
+  if (h_n) *h_n = total;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_force_rebuild(vb_ctx *c) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  c->force_pending = 1;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_set_timing(vb_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  c->timing = on != 0;
+  c->ms_rebuild = c->ms_step = 0.0;
+  c->t_steps = c->t_rebuild_steps = 0;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_phase_times(vb_ctx *c, double *h_ms_rebuild, double *h_ms_step,
+                                    int64_t *h_steps, int64_t *h_rebuild_steps) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (h_ms_rebuild) *h_ms_rebuild = c->ms_rebuild;
+  if (h_ms_step) *h_ms_step = c->ms_step;
+  if (h_steps) *h_steps = c->t_steps;
+  if (h_rebuild_steps) *h_rebuild_steps = c->t_rebuild_steps;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_info(vb_ctx *c, int64_t *h_n_total, int32_t *h_n_sys,
+                                 int32_t *h_row_width, int64_t *h_step) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (h_n_total) *h_n_total = c->n_total;
+  if (h_n_sys) *h_n_sys = c->n_sys;
+  if (h_row_width) *h_row_width = c->width;
+  if (h_step) *h_step = c->step;
+  return VB_OK;
+}
+
+extern "C" const char *vb_last_error(const vb_ctx *c) {
+  return c ? c->msg.c_str() : g_create_error.c_str();
+}
+
+extern "C" void vb_destroy(vb_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}

@@ -1,0 +1,739 @@
+// vb_kernels.hip -- gfx950 kernels of the local Verlet buffer DEM step.
+//
+// k_step     fused narrow phase + contact forces + velocity-Verlet integration
+//            + displacement validity test (Sec. 3.2 Eq. delta, Sec. 5.1 model and
+//            integrator, Sec. 4.2 Eq. update), one thread per particle, rows of
+//            the Verlet list gathered in ascending original partner index.
+// k_rebuild  the conditional broad phase (Def. autoverlet): local skin and cap
+//            (Eq. skin_formulus1, bounding_sphere, skin_formulus_mincell), cell
+//            binning by counting sort, cell-sorted permutation of the state, and
+//            the linked-cell pair search of Alg. 1 on the extended spheres.  One
+//            cooperative launch per step; it returns at once when no system of
+//            the batch needs a broad phase, so the host never waits on the flag.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "vb_device.h"
+
+namespace cg = cooperative_groups;
+
+namespace vb {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+// Inclusive prefix sum over a TILE-thread block; *total receives the block sum.
+__device__ __forceinline__ int block_inclusive_scan(int v, int *total) {
+  __shared__ int wsum[TILE / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int u = __shfl_up(v, o, WAVE);
+    if (lane >= o) v += u;
+  }
+  if (lane == WAVE - 1) wsum[w] = v;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < TILE / WAVE; ++i) {
+    if (i < w) before += wsum[i];
+    all += wsum[i];
+  }
+  __syncthreads();
+  *total = all;
+  return v + before;
+}
+
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v) {
+  __shared__ int64_t part[TILE / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  int64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < TILE / WAVE; ++i) s += part[i];
+  __syncthreads();
+  return s;
+}
+
+// Overlap of two spheres, Eq. delta: delta = R_i + R_j - |x_i - x_j|, in FP64.
+// Returns true iff delta > 0 (contact, Sec. 3.2), with the separation vector
+// and distance for the force.  The cheap test on the squared distance only
+// skips pairs whose overlap is certainly negative.
+__device__ __forceinline__ bool overlap_positive(const PX &a, const PX &b, double &dx, double &dy,
+                                                 double &dz, double &d, double &delta) {
+  dx = a.x - b.x;
+  dy = a.y - b.y;
+  dz = a.z - b.z;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double rs = (double)a.rc + (double)b.rc;
+  if (!(d2 < rs * rs * (1.0 + 1e-12))) return false;
+  d = sqrt(d2);
+  delta = rs - d;
+  return delta > 0.0;
+}
+
+// Maps a workgroup index to a tile so that each of the 8 XCDs (which receive
+// workgroups round-robin) walks a contiguous range of tiles: neighbouring tiles
+// share neighbour particles, and each XCD has its own L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n) {
+  const int64_t x = i & 7, k = i >> 3;
+  const int64_t q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// ------------------------------------------------------------------ k_step
+
+__global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
+  const int64_t t = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int s = a.tile_sys[t];
+  const SysDev &S = a.sys[s];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  const bool active = local < S.n;
+  const int64_t k = S.p_off + local;
+  const bool fresh = a.rebuilt_at[s] == a.step;
+  const PX *__restrict__ px = fresh ? a.px_tmp : a.px_cur;
+  const PV *__restrict__ pv = fresh ? a.pv_tmp : a.pv_cur;
+
+  double ke = 0.0;
+  int rowlen = 0, ncon = 0, viol = 0;
+  float excess = -INFINITY;
+  if (active) {
+    const PX me = px[k];
+    const PV mv = pv[k];
+    const float4 b = a.bp[k];
+    rowlen = a.cnt[k];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    const int32_t *row = a.nbr + k;
+    for (int q = 0; q < rowlen; ++q) {
+      const int64_t j = S.p_off + row[(int64_t)q * a.stride];
+      const PX o = px[j];
+      double dx, dy, dz, d, delta;
+      if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
+        const PV ov = pv[j];
+        const double inv = 1.0 / d;
+        const double nx = dx * inv, ny = dy * inv, nz = dz * inv;
+        const double vn = (mv.vx - ov.vx) * nx + (mv.vy - ov.vy) * ny + (mv.vz - ov.vz) * nz;
+        const double fm = S.kn * delta - S.gamma_n * vn;
+        fx += fm * nx;
+        fy += fm * ny;
+        fz += fm * nz;
+        ++ncon;
+      }
+    }
+    // walls: half-spaces of infinite mass at rest, normals into the box,
+    // in the order -x, +x, -y, +y, -z, +z
+    const double pos[3] = {me.x, me.y, me.z};
+    const double vel[3] = {mv.vx, mv.vy, mv.vz};
+    double f[3] = {fx, fy, fz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double dlo = (double)me.rc - (pos[ax] - S.lo[ax]);
+      if (dlo > 0.0) f[ax] += S.kn * dlo - S.gamma_n * vel[ax];
+      const double dhi = (double)me.rc - (S.hi[ax] - pos[ax]);
+      if (dhi > 0.0) f[ax] -= S.kn * dhi - S.gamma_n * (-vel[ax]);
+    }
+    // velocity Verlet: v^n = v^{n-1/2} + dt/2 a^n, v^{n+1/2} = v^n + dt/2 a^n,
+    // x^{n+1} = x^n + dt v^{n+1/2}
+    const double hdt = 0.5 * S.dt, im = (double)mv.invm;
+    double vf[3], vn[3], xn[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double acc = f[ax] * im + S.g[ax];
+      vf[ax] = a.first ? vel[ax] : vel[ax] + hdt * acc;
+      vn[ax] = vf[ax] + hdt * acc;
+      xn[ax] = pos[ax] + S.dt * vn[ax];
+    }
+    PX outx;
+    outx.x = xn[0];
+    outx.y = xn[1];
+    outx.z = xn[2];
+    outx.rc = me.rc;
+    outx.orig = me.orig;
+    PV outv;
+    outv.vx = vn[0];
+    outv.vy = vn[1];
+    outv.vz = vn[2];
+    outv.invm = mv.invm;
+    outv.pad = 0;
+    a.px_dst[k] = outx;
+    a.pv_dst[k] = outv;
+    ke = 0.5 * (vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2]) / im;
+    // Eq. update for the next step: straight-line displacement since the last
+    // broad phase against the skin left after the cap (R_NL - R_C)
+    const float ddx = (float)(xn[0] - (double)b.x);
+    const float ddy = (float)(xn[1] - (double)b.y);
+    const float ddz = (float)(xn[2] - (double)b.z);
+    const float disp = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+    const float skin_eff = b.w - me.rc;
+    viol = disp > skin_eff ? 1 : 0;
+    excess = disp - skin_eff;
+  }
+  // per-tile statistics, reduced in a fixed order
+  __shared__ double s_ke[TILE / WAVE];
+  __shared__ int s_i[3][TILE / WAVE];
+  __shared__ float s_x[TILE / WAVE];
+  ke = wave_sum(ke);
+  rowlen = wave_sum(rowlen);
+  ncon = wave_sum(ncon);
+  viol = wave_sum(viol);
+  excess = wave_max(excess);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  if (lane == 0) {
+    s_ke[w] = ke;
+    s_i[0][w] = rowlen;
+    s_i[1][w] = ncon;
+    s_i[2][w] = viol;
+    s_x[w] = excess;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    TileStats st;
+    st.ke = 0.0;
+    st.rowsum = st.contacts2 = st.violators = 0;
+    st.max_excess = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < TILE / WAVE; ++i) {
+      st.ke += s_ke[i];
+      st.rowsum += s_i[0][i];
+      st.contacts2 += s_i[1][i];
+      st.violators += s_i[2][i];
+      st.max_excess = fmaxf(st.max_excess, s_x[i]);
+    }
+    a.stats[(int64_t)(a.step % STATS_RING) * a.n_tiles + t] = st;
+    if (st.violators > 0 && (S.skin_mode == 0 || S.skin_mode == 1))
+      atomicOr(&a.flags[((a.step + 1) & 1) * a.n_sys + s], 1);
+  }
+}
+
+// ------------------------------------------------------------------ k_rebuild
+
+__device__ __forceinline__ void grid_barrier(cg::grid_group &grid) {
+  __threadfence();
+  grid.sync();
+  __threadfence();
+}
+
+__device__ __forceinline__ int cell_of(const SysDev &S, double x, double y, double z) {
+  const double p[3] = {x, y, z};
+  int c[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    double f = floor((p[ax] - S.lo[ax]) * S.inv_edge[ax]);
+    f = fmin(fmax(f, 0.0), (double)(S.nc[ax] - 1));  // NaN -> 0, clamp to the grid
+    c[ax] = (int)f;
+  }
+  return (c[2] * S.nc[1] + c[1]) * S.nc[0] + c[0];
+}
+
+__global__ __launch_bounds__(TILE) void k_rebuild(RebuildArgs a) {
+  extern __shared__ int32_t s_row[];  // TILE * width, column t is thread t's row
+  __shared__ uint8_t need[MAX_SYS];
+  __shared__ int any_need;
+  cg::grid_group grid = cg::this_grid();
+  const int tid = threadIdx.x;
+
+  // P0: which systems run a broad phase at this step (Def. autoverlet: the list
+  // is rebuilt when Eq. update failed at the end of the previous step)
+  if (tid == 0) any_need = 0;
+  __syncthreads();
+  for (int s = tid; s < a.n_sys; s += TILE) {
+    const SysDev &S = a.sys[s];
+    int nd = a.force;
+    if (S.skin_mode == 2) nd = 1;                                             // no buffer
+    else if (S.skin_mode == 3) nd |= (a.step % S.fixed_interval) == 0;       // fixed interval
+    else nd |= a.flags[(a.step & 1) * a.n_sys + s] != 0;                    // automatic
+    need[s] = (uint8_t)nd;
+    if (nd) atomicOr(&any_need, 1);
+  }
+  __syncthreads();
+  if (!any_need) return;  // the same decision in every workgroup
+  const int64_t G = gridDim.x;
+
+  // P1: cell of every particle; arrival slot inside the cell
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+    const int s = a.tile_sys[t];
+    if (!need[s]) continue;
+    const SysDev &S = a.sys[s];
+    const int local = (int)(t - S.tile_off) * TILE + tid;
+    if (local < S.n) {
+      const int64_t k = S.p_off + local;
+      const PX p = a.px_cur[k];
+      const int c = cell_of(S, p.x, p.y, p.z);
+      a.cellid[k] = c;
+      a.inslot[k] = atomicAdd(&a.cell_count[S.c_off + c], 1);
+    }
+  }
+  grid_barrier(grid);
+
+  // P2: exclusive prefix sum of the cell counts over the whole batch
+  const int64_t C = a.n_cells;
+  const int64_t ch = (C + G - 1) / G;
+  const int64_t c0 = blockIdx.x * ch, c1 = c0 + ch < C ? c0 + ch : C;
+  {
+    int64_t part = 0;
+    for (int64_t c = c0 + tid; c < c1; c += TILE) part += a.cell_count[c];
+    part = block_sum_i64(part);
+    if (tid == 0) a.block_sum[blockIdx.x] = (int32_t)part;
+  }
+  grid_barrier(grid);
+  {
+    int64_t pre = 0;
+    for (int64_t b = tid; b < blockIdx.x; b += TILE) pre += a.block_sum[b];
+    int carry = (int)block_sum_i64(pre);
+    for (int64_t base = c0; base < c1; base += TILE) {
+      const int64_t c = base + tid;
+      const int v = c < c1 ? a.cell_count[c] : 0;
+      int tot;
+      const int incl = block_inclusive_scan(v, &tot);
+      if (c < c1) a.cell_start[c] = carry + incl - v;
+      carry += tot;
+    }
+    if (c0 < C && c1 == C && tid == 0) a.cell_start[C] = carry;
+  }
+  grid_barrier(grid);
+
+  // P3: counting-sort scatter into a provisional cell order; clear the counts
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+    const int s = a.tile_sys[t];
+    if (!need[s]) continue;
+    const SysDev &S = a.sys[s];
+    const int local = (int)(t - S.tile_off) * TILE + tid;
+    if (local < S.n) {
+      const int64_t k = S.p_off + local;
+      const int32_t base = a.cell_start[S.c_off];
+      const int64_t pos = S.p_off + (a.cell_start[S.c_off + a.cellid[k]] - base) + a.inslot[k];
+      a.perm0[pos] = local;
+    }
+  }
+  for (int s = 0; s < a.n_sys; ++s) {
+    if (!need[s]) continue;
+    const SysDev &S = a.sys[s];
+    for (int64_t c = blockIdx.x * (int64_t)TILE + tid; c < S.ncell; c += G * TILE)
+      a.cell_count[S.c_off + c] = 0;
+  }
+  grid_barrier(grid);
+
+  // P4: inside each cell, order the particles by original index (deterministic)
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+    const int s = a.tile_sys[t];
+    if (!need[s]) continue;
+    const SysDev &S = a.sys[s];
+    const int local = (int)(t - S.tile_off) * TILE + tid;
+    if (local < S.n) {
+      const int64_t p = S.p_off + local;
+      const int32_t q = a.perm0[p];
+      const int c = a.cellid[S.p_off + q];
+      const int32_t base = a.cell_start[S.c_off];
+      const int64_t cs = S.p_off + (a.cell_start[S.c_off + c] - base);
+      const int64_t ce = S.p_off + (a.cell_start[S.c_off + c + 1] - base);
+      const uint32_t my = a.px_cur[S.p_off + q].orig;
+      int rank = 0;
+      for (int64_t m = cs; m < ce; ++m) rank += a.px_cur[S.p_off + a.perm0[m]].orig < my;
+      a.perm[cs + rank] = q;
+    }
+  }
+  grid_barrier(grid);
+
+  // P5: permute the state into cell order; extended spheres of the broad phase:
+  // skin_p = K |v_p| dt (Eq. skin_formulus1), R_NL = min(R_C + skin, cap)
+  // (Eq. bounding_sphere, Eq. skin_formulus_mincell); reference positions x0
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+    const int s = a.tile_sys[t];
+    if (!need[s]) continue;
+    const SysDev &S = a.sys[s];
+    const int local = (int)(t - S.tile_off) * TILE + tid;
+    if (local < S.n) {
+      const int64_t p = S.p_off + local;
+      const int64_t src = S.p_off + a.perm[p];
+      const PX x = a.px_cur[src];
+      const PV v = a.pv_cur[src];
+      a.px_tmp[p] = x;
+      a.pv_tmp[p] = v;
+      double skin;
+      if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
+      else if (S.skin_mode == 2) skin = 0.0;
+      else skin = S.skin_uniform;
+      const double r = (double)x.rc + skin;
+      const double rnl = r < S.cap ? r : S.cap;
+      a.bp[p] = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
+      a.cellid_new[p] = a.cellid[src];
+      a.inv[S.p_off + x.orig] = local;
+    }
+  }
+  grid_barrier(grid);
+
+  // P6: linked-cell pair search (Alg. 1) on the extended spheres: every particle
+  // of the cells within `ring` cells whose sphere meets this one (plus eps), kept
+  // as a row sorted by original index
+  const int W = a.width;
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+    const int s = a.tile_sys[t];
+    if (!need[s]) continue;
+    const SysDev &S = a.sys[s];
+    const int local = (int)(t - S.tile_off) * TILE + tid;
+    if (local >= S.n) continue;
+    const int64_t p = S.p_off + local;
+    const float4 me = a.bp[p];
+    const int c = a.cellid_new[p];
+    const int nx = S.nc[0], ny = S.nc[1], nz = S.nc[2];
+    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+    const int32_t base = a.cell_start[S.c_off];
+    int count = 0;
+    for (int dz = -S.ring; dz <= S.ring; ++dz) {
+      const int bz = cz + dz;
+      if (bz < 0 || bz >= nz) continue;
+      for (int dy = -S.ring; dy <= S.ring; ++dy) {
+        const int by = cy + dy;
+        if (by < 0 || by >= ny) continue;
+        for (int dx = -S.ring; dx <= S.ring; ++dx) {
+          const int bx = cx + dx;
+          if (bx < 0 || bx >= nx) continue;
+          const int cc = (bz * ny + by) * nx + bx;
+          const int64_t cs = S.p_off + (a.cell_start[S.c_off + cc] - base);
+          const int64_t ce = S.p_off + (a.cell_start[S.c_off + cc + 1] - base);
+          for (int64_t m = cs; m < ce; ++m) {
+            if (m == p) continue;
+            const float4 o = a.bp[m];
+            const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
+            const float d = sqrtf(ex * ex + ey * ey + ez * ez);
+            if (d <= me.w + o.w + S.eps) {
+              if (count < W) {
+                const int32_t key = (int32_t)a.px_tmp[m].orig;
+                int i = count;
+                while (i > 0 && s_row[(i - 1) * TILE + tid] > key) {
+                  s_row[i * TILE + tid] = s_row[(i - 1) * TILE + tid];
+                  --i;
+                }
+                s_row[i * TILE + tid] = key;
+              }
+              ++count;
+            }
+          }
+        }
+      }
+    }
+    const int kept = count < W ? count : W;
+    for (int q = 0; q < kept; ++q) a.nbr[(int64_t)q * a.stride + p] = a.inv[S.p_off + s_row[q * TILE + tid]];
+    a.cnt[p] = kept;
+    if (count > W) atomicMax(a.overflow, count);
+  }
+  // every workgroup passed P0 before the first barrier: the flags can be consumed
+  if (blockIdx.x == 0) {
+    for (int s = tid; s < a.n_sys; s += TILE) {
+      if (!need[s]) continue;
+      a.flags[(a.step & 1) * a.n_sys + s] = 0;
+      a.rebuilt_at[s] = a.step;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ statistics
+
+// One workgroup per (system, step): sums the system's tile statistics of that
+// step in a fixed order.
+__global__ __launch_bounds__(TILE) void k_stats_reduce(const SysDev *sys, const TileStats *stats,
+                                                       const int32_t *rebuilt_ring, int64_t n_tiles,
+                                                       int32_t n_sys, int32_t step0,
+                                                       RecordDev *out) {
+  const int s = blockIdx.x;
+  const int r = blockIdx.y;
+  const int step = step0 + r;
+  const SysDev &S = sys[s];
+  const TileStats *st = stats + (int64_t)(step % STATS_RING) * n_tiles + S.tile_off;
+  double ke = 0.0;
+  int64_t rows = 0, con = 0, vio = 0;
+  float mx = -INFINITY;
+  for (int i = threadIdx.x; i < S.n_tiles; i += TILE) {
+    const TileStats q = st[i];
+    ke += q.ke;
+    rows += q.rowsum;
+    con += q.contacts2;
+    vio += q.violators;
+    mx = fmaxf(mx, q.max_excess);
+  }
+  __shared__ double s_ke[TILE / WAVE];
+  __shared__ float s_mx[TILE / WAVE];
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  ke = wave_sum(ke);
+  mx = wave_max(mx);
+  if (lane == 0) {
+    s_ke[w] = ke;
+    s_mx[w] = mx;
+  }
+  rows = block_sum_i64(rows);
+  con = block_sum_i64(con);
+  vio = block_sum_i64(vio);
+  if (threadIdx.x == 0) {
+    double k2 = 0.0;
+    float m2 = -INFINITY;
+    for (int i = 0; i < TILE / WAVE; ++i) {
+      k2 += s_ke[i];
+      m2 = fmaxf(m2, s_mx[i]);
+    }
+    RecordDev rec;
+    rec.step = step;
+    rec.rebuilt = rebuilt_ring[(step % STATS_RING) * n_sys + s];
+    rec.list_pairs = rows / 2;
+    rec.contacts = con / 2;
+    rec.violators = vio;
+    rec.max_excess = S.n > 0 ? m2 : 0.0f;
+    rec.reserved = 0;
+    rec.kinetic_energy = k2;
+    out[(int64_t)r * n_sys + s] = rec;
+  }
+}
+
+// Whether a broad phase ran at this step, per system (read by the reduction).
+__global__ void k_log_rebuilt(const int32_t *rebuilt_at, int32_t n_sys, int32_t step,
+                              int32_t *rebuilt_ring) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_sys) rebuilt_ring[(step % STATS_RING) * n_sys + s] = rebuilt_at[s] == step;
+}
+
+// ------------------------------------------------------------------ state I/O
+
+// Load one system from the caller's original order; flags bad values in *err:
+// bit 0 non-finite, bit 1 radius out of range, bit 2 non-positive inverse mass.
+__global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const double *v,
+                            const float *rc, const float *invm, int32_t *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t padded = (int64_t)S.n_tiles * TILE;
+  if (i >= padded) return;
+  PX p;
+  PV q;
+  if (i < S.n) {
+    const int64_t g = S.o_off + i;
+    p.x = x[3 * g];
+    p.y = x[3 * g + 1];
+    p.z = x[3 * g + 2];
+    p.rc = rc[g];
+    p.orig = (uint32_t)i;
+    q.vx = v[3 * g];
+    q.vy = v[3 * g + 1];
+    q.vz = v[3 * g + 2];
+    q.invm = invm[g];
+    q.pad = 0;
+    int e = 0;
+    if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z) || !isfinite(q.vx) ||
+        !isfinite(q.vy) || !isfinite(q.vz) || !isfinite(p.rc) || !isfinite(q.invm))
+      e |= 1;
+    else {
+      if (!(p.rc > 0.0f) || (double)p.rc > S.cap) e |= 2;
+      if (!(q.invm > 0.0f)) e |= 4;
+    }
+    if (e) atomicOr(err, e);
+  } else {
+    p.x = p.y = p.z = 0.0;
+    p.rc = 0.0f;
+    p.orig = 0xFFFFFFFFu;
+    q.vx = q.vy = q.vz = 0.0;
+    q.invm = 0.0f;
+    q.pad = 0;
+  }
+  px[S.p_off + i] = p;
+  pv[S.p_off + i] = q;
+}
+
+// Copy the state back to the caller's original order.
+__global__ void k_get_state(const SysDev *sys, const int32_t *tile_sys, const PX *px, const PV *pv,
+                            double *x, double *v) {
+  const int64_t t = blockIdx.x;
+  const SysDev &S = sys[tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const PX p = px[k];
+  const int64_t g = S.o_off + p.orig;
+  if (x) {
+    x[3 * g] = p.x;
+    x[3 * g + 1] = p.y;
+    x[3 * g + 2] = p.z;
+  }
+  if (v) {
+    const PV q = pv[k];
+    v[3 * g] = q.vx;
+    v[3 * g + 1] = q.vy;
+    v[3 * g + 2] = q.vz;
+  }
+}
+
+// ------------------------------------------------------------------ pair export
+
+// Per original index i of system S: how many row entries j have orig(j) > i
+// (and positive overlap when contacts_only).
+__global__ void k_pairs_count(SysDev S, const PX *px, const int32_t *cnt, const int32_t *nbr,
+                              int64_t stride, int32_t contacts_only, int32_t *counts) {
+  const int local = blockIdx.x * blockDim.x + threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const PX me = px[k];
+  int c = 0;
+  const int len = cnt[k];
+  for (int q = 0; q < len; ++q) {
+    const PX o = px[S.p_off + nbr[(int64_t)q * stride + k]];
+    if (o.orig <= me.orig) continue;
+    if (contacts_only) {
+      double dx, dy, dz, d, delta;
+      if (!overlap_positive(me, o, dx, dy, dz, d, delta)) continue;
+    }
+    ++c;
+  }
+  counts[me.orig] = c;
+}
+
+__global__ void k_pairs_write(SysDev S, const PX *px, const int32_t *cnt, const int32_t *nbr,
+                              int64_t stride, int32_t contacts_only, const int64_t *offsets,
+                              int64_t cap, int32_t *pairs, double *delta_out) {
+  const int local = blockIdx.x * blockDim.x + threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const PX me = px[k];
+  int64_t off = offsets[me.orig];
+  const int len = cnt[k];
+  for (int q = 0; q < len; ++q) {
+    const PX o = px[S.p_off + nbr[(int64_t)q * stride + k]];
+    if (o.orig <= me.orig) continue;
+    double dx, dy, dz, d = 0.0, delta = 0.0;
+    const bool touch = overlap_positive(me, o, dx, dy, dz, d, delta);
+    if (contacts_only && !touch) continue;
+    if (!touch) {
+      dx = me.x - o.x;
+      dy = me.y - o.y;
+      dz = me.z - o.z;
+      delta = ((double)me.rc + (double)o.rc) - sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    if (off < cap) {
+      pairs[2 * off] = (int32_t)me.orig;
+      pairs[2 * off + 1] = (int32_t)o.orig;
+      if (delta_out) delta_out[off] = delta;
+    }
+    ++off;
+  }
+}
+
+// Exclusive prefix sum of n int32 counts into int64 offsets, one workgroup.
+__global__ __launch_bounds__(TILE) void k_scan_single(const int32_t *in, int64_t n, int64_t *out,
+                                                      int64_t *total) {
+  __shared__ int64_t carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += TILE) {
+    const int64_t i = base + threadIdx.x;
+    const int v = i < n ? in[i] : 0;
+    int tot;
+    const int incl = block_inclusive_scan(v, &tot);
+    const int64_t carry = carry_s;
+    if (i < n) out[i] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry_s;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace vb
+
+// ------------------------------------------------------------------ launchers
+// Host entry points of the kernels above (C++ linkage, internal to the library).
+namespace vb {
+
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_step, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t rebuild_occupancy(int width, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, reinterpret_cast<const void *>(k_rebuild), TILE,
+      (size_t)TILE * (size_t)width * sizeof(int32_t));
+}
+
+hipError_t launch_rebuild(const RebuildArgs &a, int grid, hipStream_t st) {
+  RebuildArgs copy = a;
+  void *args[] = {&copy};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rebuild), dim3(grid),
+                                    dim3(TILE), args,
+                                    (unsigned)((size_t)TILE * (size_t)a.width * sizeof(int32_t)),
+                                    st);
+}
+
+hipError_t launch_log_rebuilt(const int32_t *rebuilt_at, int32_t n_sys, int32_t step,
+                              int32_t *ring, hipStream_t st) {
+  hipLaunchKernelGGL(k_log_rebuilt, dim3((n_sys + 255) / 256), dim3(256), 0, st, rebuilt_at,
+                     n_sys, step, ring);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
+                               int64_t n_tiles, int32_t n_sys, int32_t step0, int32_t nsteps,
+                               RecordDev *out, hipStream_t st) {
+  if (nsteps <= 0 || n_sys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stats_reduce, dim3(n_sys, nsteps), dim3(TILE), 0, st, sys, stats, ring,
+                     n_tiles, n_sys, step0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const SysDev &S, PX *px, PV *pv, const double *x, const double *v,
+                            const float *rc, const float *invm, int32_t *err, hipStream_t st) {
+  const int64_t padded = (int64_t)S.n_tiles * TILE;
+  if (padded == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_state, dim3((unsigned)((padded + 255) / 256)), dim3(256), 0, st, S, px,
+                     pv, x, v, rc, invm, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                            const PX *px, const PV *pv, double *x, double *v, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_get_state, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
+                     pv, x, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const int32_t *nbr,
+                        int64_t stride, int32_t contacts_only, int32_t *counts, int64_t *offsets,
+                        int64_t *total, int64_t cap, int32_t *pairs, double *delta,
+                        hipStream_t st) {
+  if (S.n <= 0) return hipSuccess;
+  const unsigned g = (unsigned)((S.n + 255) / 256);
+  hipLaunchKernelGGL(k_pairs_count, dim3(g), dim3(256), 0, st, S, px, cnt, nbr, stride,
+                     contacts_only, counts);
+  hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(TILE), 0, st, counts, (int64_t)S.n, offsets,
+                     total);
+  if (pairs)
+    hipLaunchKernelGGL(k_pairs_write, dim3(g), dim3(256), 0, st, S, px, cnt, nbr, stride,
+                       contacts_only, offsets, cap, pairs, delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace vb

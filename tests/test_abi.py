@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+function include/vbuf.h declares, and the binding's struct layouts equal the C
+compiler's."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+import paper_2208_13770_amd as vb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vbuf.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vb_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    assert "vb_create" in names and "vb_run" in names and len(names) == 12
+
+
+@pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(vb.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(vb._SIGNATURES)
+
+
+def test_struct_layouts_match_c():
+    prog = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "vbuf.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(vb_params), offsetof(vb_params, K),
+         offsetof(vb_params, lo), offsetof(vb_params, gravity),
+         offsetof(vb_params, max_neighbors), offsetof(vb_params, fixed_interval));
+  printf("%zu %zu %zu %zu\n", sizeof(vb_step_record), offsetof(vb_step_record, list_pairs),
+         offsetof(vb_step_record, max_excess), offsetof(vb_step_record, kinetic_energy));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-std=c99", "-I" + os.path.dirname(HEADER), c, "-o", exe],
+                       check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    P = vb.vb_params
+    want = [ctypes.sizeof(P), P.K.offset, P.lo.offset, P.gravity.offset,
+            P.max_neighbors.offset, P.fixed_interval.offset]
+    assert [int(t) for t in out[:6]] == want
+    R = vb.STEP_RECORD_DTYPE
+    want_r = [R.itemsize, R.fields["list_pairs"][1], R.fields["max_excess"][1],
+              R.fields["kinetic_energy"][1]]
+    assert [int(t) for t in out[6:]] == want_r
+
+
+def test_params_from_generator_dict():
+    import synth
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    q = vb.make_params(s.params)
+    assert q.K == 200.0 and q.max_neighbors == 32 and q.hi[2] == s.params["hi"][2]
+    assert q.cell_size == s.params["cell_size"]

@@ -398,3 +398,17 @@ def test_summary_table_formulas():
         assert abs(report.improvement(t0, t_opt) - i_opt) <= 0.025, name
         assert abs(report.improvement(t0, t_def) - i_def) <= 0.025, name
         assert abs(report.overhead_to_optimum(t_def, t_opt) - ovh) <= 0.01, name
+
+
+def test_resume_from_half_step_state(orc):
+    """A run split in two (the second part resumed from x^n and the half-step
+    velocity v^{n-1/2}) equals the uninterrupted run; the resumed method run starts
+    with a broad phase (R7), which by the theorem of Sec. 4.2 changes nothing."""
+    s = colliding(6)
+    x, v, rc, invm = arrays(s)
+    for mode in (orc.NAIVE, orc.SKIN_LOCAL):
+        p = dict(s.params, skin_mode=mode)
+        xa, va, _, _ = orc.run(p, x, v, rc, invm, 200)
+        x1, v1, _, _ = orc.run(p, x, v, rc, invm, 120)
+        xb, vb, _, _ = orc.run(dict(p, v_in_is_half_step=1), x1, v1, rc, invm, 80)
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
