@@ -78,6 +78,9 @@ typedef struct vb_params {
   double gravity[3];      /* gravitational acceleration                                            */
   int32_t max_neighbors;  /* initial width of a Verlet-list row (grown on overflow), 1..128       */
   int32_t fixed_interval; /* broad-phase period of VB_FIXED_INTERVAL (>= 1)                        */
+  int32_t reorder_interval; /* steps between re-sorts of the particle storage by cell, for memory */
+                          /* locality (0: only after vb_set_state); the batch uses system 0's     */
+  int32_t bin_capacity;   /* initial particles per cell bin (grown on overflow), 1..256; 0 = 16   */
 } vb_params;
 
 /* Diagnostics of one time step n of one system (the state x^n whose forces the
@@ -120,10 +123,11 @@ vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const 
                        const float *d_invm, int32_t v_is_half_step);
 
 /* Advance every system n_steps time steps.  h_hist, if not NULL, receives
- * [n_sys][n_steps] records.  A list row that overflows is grown and the call's
- * steps are run again from the call's starting state (results unchanged).
- * Synchronises the stream.  Errors: VB_ECAPACITY if a row exceeds 128 entries,
- * VB_ENOMEM, VB_EDEVICE. */
+ * [n_sys][n_steps] records.  A Verlet-list row or a cell bin that overflows is
+ * grown and the call's steps are run again from the call's starting state
+ * (results unchanged).  Synchronises the stream once, at the end.
+ * Errors: VB_ECAPACITY if a row needs more than 128 entries or a bin more than
+ * 256, VB_ENOMEM, VB_EDEVICE. */
 vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 
 /* Copy the state out, original order: d_x [N][3] positions x^n and d_v [N][3]
@@ -146,9 +150,10 @@ vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs
 vb_status vb_force_rebuild(vb_ctx *ctx);
 
 /* Enable (1) or disable (0) per-kernel HIP-event timing of vb_run, and read the
- * totals since timing was enabled: milliseconds spent in the broad-phase kernel
- * launches and in the step-kernel launches, the number of steps timed and the
- * number of steps at which any system ran a broad phase. */
+ * totals since timing was enabled: milliseconds spent in the broad-phase launches
+ * of every step (including the storage re-sorts, and the launches that found no
+ * system to rebuild), milliseconds in the step-kernel launches, the number of
+ * steps timed and the number of steps at which any system ran a broad phase. */
 vb_status vb_set_timing(vb_ctx *ctx, int32_t on);
 vb_status vb_phase_times(vb_ctx *ctx, double *h_ms_rebuild, double *h_ms_step,
                          int64_t *h_steps, int64_t *h_rebuild_steps);

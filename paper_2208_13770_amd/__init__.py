@@ -33,6 +33,8 @@ class vb_params(ctypes.Structure):
         ("gravity", ctypes.c_double * 3),
         ("max_neighbors", ctypes.c_int32),
         ("fixed_interval", ctypes.c_int32),
+        ("reorder_interval", ctypes.c_int32),
+        ("bin_capacity", ctypes.c_int32),
     ]
 
 
@@ -119,6 +121,8 @@ def make_params(p: dict) -> vb_params:
     q.gravity[:] = [float(t) for t in p.get("g", p.get("gravity", (0.0, 0.0, 0.0)))]
     q.max_neighbors = int(p.get("max_neighbors", 32))
     q.fixed_interval = int(p.get("fixed_interval", 1))
+    q.reorder_interval = int(p.get("reorder_interval", 0))
+    q.bin_capacity = int(p.get("bin_capacity", 0))
     return q
 
 

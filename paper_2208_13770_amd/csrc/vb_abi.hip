@@ -1,11 +1,13 @@
 // vb_abi.hip -- host implementation of the C ABI declared in include/vbuf.h.
 //
 // A context holds one batch of independent particle systems.  Each step queues
-// two launches on the context's stream: the cooperative broad-phase kernel
-// (which returns at once unless some system's list went invalid at the previous
-// step, Def. autoverlet) and the fused step kernel.  The host never reads the
+// three launches on the context's stream: the two broad-phase kernels, which
+// return at once unless some system's list went invalid at the previous step
+// (Def. autoverlet), and the fused step kernel.  The host never reads the
 // validity flag; it synchronises once per vb_run call, to collect the per-step
-// records and to check that no Verlet-list row overflowed.
+// records and to check that no Verlet-list row or cell bin overflowed.  Every
+// reorder_interval steps (and after a state is loaded) the host also queues a
+// counting sort of the particle storage by cell, followed by a broad phase.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,11 +22,10 @@
 #include "vb_device.h"
 
 namespace vb {
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, hipStream_t st);
-hipError_t rebuild_occupancy(int width, int *blocks_per_cu);
-hipError_t launch_rebuild(const RebuildArgs &a, int grid, hipStream_t st);
-hipError_t launch_log_rebuilt(const int32_t *rebuilt_at, int32_t n_sys, int32_t step,
-                              int32_t *ring, hipStream_t st);
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st);
+hipError_t launch_broad_phase(const BroadArgs &a, int grid, hipStream_t st);
+hipError_t launch_sort(const SortArgs &a, hipStream_t st);
+int64_t scan_blocks(int64_t n_cells);
 hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
                                int64_t n_tiles, int32_t n_sys, int32_t step0, int32_t nsteps,
                                RecordDev *out, hipStream_t st);
@@ -55,30 +56,36 @@ struct vb_ctx {
   int32_t *tile_sys = nullptr;
   PX *px[2] = {nullptr, nullptr};
   PV *pv[2] = {nullptr, nullptr};
-  PX *px_tmp = nullptr;
-  PV *pv_tmp = nullptr;
   PX *snap_px = nullptr;
   PV *snap_pv = nullptr;
   float4 *bp = nullptr;
   int32_t *cnt = nullptr, *nbr = nullptr;
   int32_t width = 0;
+  int32_t *bin_count = nullptr, *bins = nullptr;
+  int32_t bin_cap = 0;
+  int32_t *cellid = nullptr, *inv = nullptr;
+  // counting sort of the storage
   int32_t *cell_count = nullptr, *cell_start = nullptr, *block_sum = nullptr;
-  int32_t *cellid = nullptr, *cellid_new = nullptr, *inslot = nullptr;
-  int32_t *perm0 = nullptr, *perm = nullptr, *inv = nullptr;
-  int32_t *rebuilt_at = nullptr, *flags = nullptr, *overflow = nullptr, *err = nullptr;
+  int32_t *inslot = nullptr, *perm0 = nullptr;
+  // control
+  int32_t *flags = nullptr, *go = nullptr, *overflow = nullptr, *err = nullptr;
   TileStats *stats = nullptr;
   int32_t *rebuilt_ring = nullptr;
   RecordDev *hist_d = nullptr;
   int64_t hist_cap = 0;
   int32_t *pair_counts = nullptr;
   int64_t *pair_offsets = nullptr, *pair_total = nullptr;
-  int rebuild_grid = 0;
+  int broad_grid = 0;
+  int32_t row_limit = MAX_ROW;  // rows are sorted in LDS: TILE * width * 4 bytes
   int cur = 0;
   int64_t step = 0;
   int first = 1;
   int force_pending = 1;
+  int64_t next_sort = 0;       // step at which the storage is re-sorted next (-1: never)
+  int32_t sort_interval = 0;
   int loaded = 0;
-  int xcd_remap = 1;
+  int xcd_remap = 0;
+  int step_unroll = 4;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -111,11 +118,11 @@ static hipError_t dalloc(T **p, int64_t count) {
 }
 
 static void free_all(vb_ctx *c) {
-  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->px_tmp,
-                  c->pv_tmp, c->snap_px, c->snap_pv, c->bp, c->cnt, c->nbr, c->cell_count,
-                  c->cell_start, c->block_sum, c->cellid, c->cellid_new, c->inslot, c->perm0,
-                  c->perm, c->inv, c->rebuilt_at, c->flags, c->overflow, c->err, c->stats,
-                  c->rebuilt_ring, c->hist_d, c->pair_counts, c->pair_offsets, c->pair_total};
+  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->snap_px,
+                  c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins, c->cellid, c->inv,
+                  c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
+                  c->go, c->overflow, c->err, c->stats, c->rebuilt_ring, c->hist_d,
+                  c->pair_counts, c->pair_offsets, c->pair_total};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -141,6 +148,8 @@ static std::string check_params(const vb_params &p, int64_t n) {
   }
   if (p.max_neighbors < 1 || p.max_neighbors > MAX_ROW) return "max_neighbors must be 1..128";
   if (p.skin_mode == VB_FIXED_INTERVAL && p.fixed_interval < 1) return "fixed_interval must be >= 1";
+  if (p.reorder_interval < 0) return "reorder_interval must be >= 0";
+  if (p.bin_capacity < 0 || p.bin_capacity > MAX_BIN) return "bin_capacity must be 0..256";
   return "";
 }
 
@@ -167,15 +176,14 @@ static vb_status alloc_rows(vb_ctx *c, int32_t width) {
   c->nbr = nullptr;
   HIP_OK(c, dalloc(&c->nbr, c->slots * (int64_t)width));
   c->width = width;
-  int bpc = 0;
-  HIP_OK(c, rebuild_occupancy(width, &bpc));
-  if (bpc < 1) return fail(c, VB_ECAPACITY, "row width too large for the broad-phase kernel");
-  // the cooperative grid: every workgroup resident at once, no more than there is work
-  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(c->n_tiles, (int64_t)bpc * c->n_cu));
-  c->rebuild_grid = (int)want;
-  if (c->block_sum) (void)hipFree(c->block_sum);
-  c->block_sum = nullptr;
-  HIP_OK(c, dalloc(&c->block_sum, c->rebuild_grid));
+  return VB_OK;
+}
+
+static vb_status alloc_bins(vb_ctx *c, int32_t cap) {
+  if (c->bins) (void)hipFree(c->bins);
+  c->bins = nullptr;
+  HIP_OK(c, dalloc(&c->bins, c->n_cells * (int64_t)cap));
+  c->bin_cap = cap;
   return VB_OK;
 }
 
@@ -204,6 +212,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   c->stream = reinterpret_cast<hipStream_t>(stream);
   const char *env = std::getenv("VBUF_XCD_REMAP");
   if (env) c->xcd_remap = std::atoi(env) != 0;
+  if ((env = std::getenv("VBUF_STEP_UNROLL"))) c->step_unroll = std::atoi(env);
   vb_status st = VB_OK;
   auto bail = [&](vb_status code) {
     g_create_error = c->msg;
@@ -221,10 +230,12 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     return bail(VB_EDEVICE);
   }
   c->n_cu = prop.multiProcessorCount;
+  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, prop.sharedMemPerBlock / (TILE * sizeof(int32_t)));
   c->n_sys = n_sys;
   c->sys_h.resize(n_sys);
+  c->sort_interval = h_params[0].reorder_interval;
   int64_t p_off = 0, t_off = 0, c_off = 0, o_off = 0;
-  int32_t width = 1;
+  int32_t width = 1, bcap = 1;
   for (int s = 0; s < n_sys; ++s) {
     const vb_params &p = h_params[s];
     SysDev &S = c->sys_h[s];
@@ -260,16 +271,24 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     c_off += S.ncell;
     o_off += S.n;
     width = std::max(width, p.max_neighbors);
+    bcap = std::max(bcap, p.bin_capacity > 0 ? p.bin_capacity : 16);
     c->max_n = std::max(c->max_n, S.n);
+  }
+  if (width > c->row_limit) {
+    c->msg = "max_neighbors exceeds " + std::to_string(c->row_limit) + " on this device";
+    return bail(VB_EINVAL);
   }
   c->slots = p_off;
   c->n_tiles = t_off;
   c->n_cells = c_off;
   c->n_total = o_off;
-  if (c->slots > (int64_t)INT32_MAX) {
+  if (c->slots > (int64_t)INT32_MAX || c->n_cells > (int64_t)INT32_MAX) {
     c->msg = "batch too large";
     return bail(VB_EINVAL);
   }
+  // the broad-phase kernels walk the tiles grid-stride from a bounded grid, so
+  // that a step without broad phase costs two short launches
+  c->broad_grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_tiles, 8LL * c->n_cu));
   std::vector<int32_t> ts(std::max<int64_t>(c->n_tiles, 1), 0);
   for (int s = 0; s < n_sys; ++s)
     for (int t = 0; t < c->sys_h[s].n_tiles; ++t) ts[c->sys_h[s].tile_off + t] = s;
@@ -285,21 +304,19 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     ALLOC(c->px[b], c->slots);
     ALLOC(c->pv[b], c->slots);
   }
-  ALLOC(c->px_tmp, c->slots);
-  ALLOC(c->pv_tmp, c->slots);
   ALLOC(c->bp, c->slots);
   ALLOC(c->cnt, c->slots);
+  ALLOC(c->bin_count, c->n_cells);
+  ALLOC(c->cellid, c->slots);
+  ALLOC(c->inv, c->slots);
   ALLOC(c->cell_count, c->n_cells);
   ALLOC(c->cell_start, c->n_cells + 1);
-  ALLOC(c->cellid, c->slots);
-  ALLOC(c->cellid_new, c->slots);
+  ALLOC(c->block_sum, scan_blocks(c->n_cells) + 1);
   ALLOC(c->inslot, c->slots);
   ALLOC(c->perm0, c->slots);
-  ALLOC(c->perm, c->slots);
-  ALLOC(c->inv, c->slots);
-  ALLOC(c->rebuilt_at, n_sys);
   ALLOC(c->flags, 2 * n_sys);
-  ALLOC(c->overflow, 1);
+  ALLOC(c->go, n_sys);
+  ALLOC(c->overflow, 2);
   ALLOC(c->err, 1);
   ALLOC(c->stats, (int64_t)STATS_RING * std::max<int64_t>(c->n_tiles, 1));
   ALLOC(c->rebuilt_ring, (int64_t)STATS_RING * n_sys);
@@ -308,18 +325,21 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->pair_total, 1);
 #undef ALLOC
   if ((st = alloc_rows(c, width)) != VB_OK) return bail(st);
+  if ((st = alloc_bins(c, bcap)) != VB_OK) return bail(st);
   if ((st = alloc_hist(c, STATS_RING)) != VB_OK) return bail(st);
   if (hipMemcpy(c->sys_d, c->sys_h.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(c->tile_sys, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
+      hipMemset(c->bin_count, 0, sizeof(int32_t) * std::max<int64_t>(c->n_cells, 1)) !=
+          hipSuccess ||
       hipMemset(c->cell_count, 0, sizeof(int32_t) * std::max<int64_t>(c->n_cells, 1)) !=
           hipSuccess ||
       hipMemset(c->cnt, 0, sizeof(int32_t) * c->slots) != hipSuccess ||
       hipMemset(c->flags, 0, sizeof(int32_t) * 2 * n_sys) != hipSuccess ||
-      hipMemset(c->overflow, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(c->go, 0, sizeof(int32_t) * n_sys) != hipSuccess ||
+      hipMemset(c->overflow, 0, sizeof(int32_t) * 2) != hipSuccess ||
       hipMemset(c->rebuilt_ring, 0, sizeof(int32_t) * STATS_RING * n_sys) != hipSuccess ||
-      hipMemset(c->rebuilt_at, 0xFF, sizeof(int32_t) * n_sys) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     c->msg = "device initialisation failed";
     return bail(VB_EDEVICE);
@@ -334,11 +354,12 @@ extern "C" vb_status vb_create(const vb_params *h_params, int64_t n, void *strea
 }
 
 // Clears the per-run control state on the stream: no pending violation, no
-// broad phase recorded, no overflow.
+// broad phase under way, empty bins, no overflow.
 static vb_status reset_control(vb_ctx *c) {
   HIP_OK(c, launch_fill_i32(c->flags, 2 * c->n_sys, 0, c->stream));
-  HIP_OK(c, launch_fill_i32(c->rebuilt_at, c->n_sys, -1, c->stream));
-  HIP_OK(c, launch_fill_i32(c->overflow, 1, 0, c->stream));
+  HIP_OK(c, launch_fill_i32(c->go, c->n_sys, 0, c->stream));
+  HIP_OK(c, launch_fill_i32(c->bin_count, c->n_cells, 0, c->stream));
+  HIP_OK(c, launch_fill_i32(c->overflow, 2, 0, c->stream));
   return VB_OK;
 }
 
@@ -366,48 +387,63 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
   c->step = 0;
   c->first = v_is_half_step ? 0 : 1;
   c->force_pending = 1;
+  c->next_sort = 0;
   c->loaded = 1;
   return VB_OK;
 }
 
-static RebuildArgs rebuild_args(vb_ctx *c, int force) {
-  RebuildArgs a;
+static BroadArgs broad_args(vb_ctx *c, int force) {
+  BroadArgs a;
   a.sys = c->sys_d;
   a.tile_sys = c->tile_sys;
   a.n_sys = c->n_sys;
   a.n_tiles = c->n_tiles;
-  a.n_cells = c->n_cells;
-  a.px_cur = c->px[c->cur];
-  a.pv_cur = c->pv[c->cur];
-  a.px_tmp = c->px_tmp;
-  a.pv_tmp = c->pv_tmp;
+  a.px = c->px[c->cur];
+  a.pv = c->pv[c->cur];
   a.bp = c->bp;
   a.cnt = c->cnt;
   a.nbr = c->nbr;
   a.stride = c->slots;
   a.width = c->width;
-  a.cell_count = c->cell_count;
-  a.cell_start = c->cell_start;
-  a.block_sum = c->block_sum;
+  a.bin_count = c->bin_count;
+  a.bins = c->bins;
+  a.bin_cap = c->bin_cap;
   a.cellid = c->cellid;
-  a.cellid_new = c->cellid_new;
-  a.inslot = c->inslot;
-  a.perm0 = c->perm0;
-  a.perm = c->perm;
   a.inv = c->inv;
-  a.rebuilt_at = c->rebuilt_at;
   a.flags = c->flags;
+  a.go = c->go;
+  a.rebuilt_ring = c->rebuilt_ring;
   a.overflow = c->overflow;
   a.step = (int32_t)c->step;
   a.force = force;
   return a;
 }
 
-// Queues the broad-phase launch of the current step (a no-op on the device
-// unless a system needs one).
-static vb_status queue_rebuild(vb_ctx *c) {
-  const RebuildArgs a = rebuild_args(c, c->force_pending);
-  HIP_OK(c, launch_rebuild(a, c->rebuild_grid, c->stream));
+// Work that precedes the step kernel of the current step: the storage re-sort
+// when it is due (then a forced broad phase), and the conditional broad phase.
+static vb_status queue_broad_phase(vb_ctx *c) {
+  if (c->next_sort >= 0 && c->step >= c->next_sort && c->n_tiles > 0) {
+    SortArgs s;
+    s.sys = c->sys_d;
+    s.tile_sys = c->tile_sys;
+    s.n_tiles = c->n_tiles;
+    s.n_cells = c->n_cells;
+    s.px_src = c->px[c->cur];
+    s.pv_src = c->pv[c->cur];
+    s.px_dst = c->px[c->cur ^ 1];
+    s.pv_dst = c->pv[c->cur ^ 1];
+    s.cell_count = c->cell_count;
+    s.cell_start = c->cell_start;
+    s.block_sum = c->block_sum;
+    s.cellid = c->cellid;
+    s.inslot = c->inslot;
+    s.perm0 = c->perm0;
+    HIP_OK(c, launch_sort(s, c->stream));
+    c->cur ^= 1;
+    c->force_pending = 1;  // slots moved: every row must be rebuilt
+    c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
+  }
+  HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending), c->broad_grid, c->stream));
   c->force_pending = 0;
   return VB_OK;
 }
@@ -418,25 +454,22 @@ static vb_status queue_step(vb_ctx *c) {
   a.tile_sys = c->tile_sys;
   a.px_cur = c->px[c->cur];
   a.pv_cur = c->pv[c->cur];
-  a.px_tmp = c->px_tmp;
-  a.pv_tmp = c->pv_tmp;
   a.px_dst = c->px[c->cur ^ 1];
   a.pv_dst = c->pv[c->cur ^ 1];
   a.bp = c->bp;
   a.cnt = c->cnt;
   a.nbr = c->nbr;
   a.stride = c->slots;
-  a.rebuilt_at = c->rebuilt_at;
+  a.go = c->go;
   a.flags = c->flags;
+  a.bin_count = c->bin_count;
   a.n_sys = c->n_sys;
   a.stats = c->stats;
   a.n_tiles = c->n_tiles;
   a.step = (int32_t)c->step;
   a.first = c->first;
   a.xcd_remap = c->xcd_remap;
-  HIP_OK(c, launch_step(a, c->n_tiles, c->stream));
-  HIP_OK(c, launch_log_rebuilt(c->rebuilt_at, c->n_sys, (int32_t)c->step, c->rebuilt_ring,
-                               c->stream));
+  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->stream));
   return VB_OK;
 }
 
@@ -449,14 +482,14 @@ static vb_status ensure_events(vb_ctx *c, size_t n) {
   return VB_OK;
 }
 
-// Runs n_steps steps; records go to hist_d[r * n_sys + s].
+// Queues n_steps steps; records go to hist_d[r * n_sys + s].
 static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
   vb_status st;
   if (c->timing && (st = ensure_events(c, 3 * (size_t)n_steps)) != VB_OK) return st;
   int32_t pending = 0;
   for (int32_t i = 0; i < n_steps; ++i) {
     if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i], c->stream));
-    if ((st = queue_rebuild(c)) != VB_OK) return st;
+    if ((st = queue_broad_phase(c)) != VB_OK) return st;
     if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i + 1], c->stream));
     if ((st = queue_step(c)) != VB_OK) return st;
     if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i + 2], c->stream));
@@ -487,29 +520,34 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     HIP_OK(c, dalloc(&c->snap_px, c->slots));
     HIP_OK(c, dalloc(&c->snap_pv, c->slots));
   }
-  // starting state, to run the call again if a list row overflows
+  // starting state, to run the call again if a row or a bin overflows
   HIP_OK(c, hipMemcpyAsync(c->snap_px, c->px[c->cur], sizeof(PX) * c->slots,
                            hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->snap_pv, c->pv[c->cur], sizeof(PV) * c->slots,
                            hipMemcpyDeviceToDevice, c->stream));
-  const int64_t step0 = c->step;
-  const int first0 = c->first, force0 = c->force_pending;
+  const int64_t step0 = c->step, sort0 = c->next_sort;
+  const int first0 = c->first;
   for (int attempt = 0;; ++attempt) {
     if ((st = run_steps(c, n_steps)) != VB_OK) return st;
-    int32_t ovf = 0;
-    HIP_OK(c, hipMemcpyAsync(&ovf, c->overflow, sizeof(int32_t), hipMemcpyDeviceToHost,
-                             c->stream));
+    int32_t ovf[2] = {0, 0};
+    HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    if (ovf <= c->width) break;
-    if (ovf > MAX_ROW || attempt >= 4) {
+    if (ovf[0] <= c->width && ovf[1] <= c->bin_cap) break;
+    if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || attempt >= 4) {
       c->loaded = 0;
       return fail(c, VB_ECAPACITY,
-                  "a Verlet-list row needs " + std::to_string(ovf) + " entries (limit 128)");
+                  "a Verlet-list row needs " + std::to_string(ovf[0]) + " entries (limit " +
+                      std::to_string(c->row_limit) + ") or a "
+                  "cell bin " + std::to_string(ovf[1]) + " particles (limit 256)");
     }
-    // grow the rows and start again from the call's first step; the forced
-    // broad phase changes the schedule, not the results (theorem of Sec. 4.2)
-    const int32_t w = std::min<int32_t>(MAX_ROW, (ovf + ovf / 4 + 7) / 8 * 8);
-    if ((st = alloc_rows(c, w)) != VB_OK) return st;
+    // grow and start again from the call's first step; the forced broad phase
+    // changes the schedule, not the results (theorem of Sec. 4.2)
+    if (ovf[0] > c->width &&
+        (st = alloc_rows(c, std::min<int32_t>(c->row_limit, (ovf[0] + ovf[0] / 4 + 7) / 8 * 8))) != VB_OK)
+      return st;
+    if (ovf[1] > c->bin_cap &&
+        (st = alloc_bins(c, std::min<int32_t>(MAX_BIN, (ovf[1] + ovf[1] / 4 + 7) / 8 * 8))) != VB_OK)
+      return st;
     HIP_OK(c, hipMemcpyAsync(c->px[0], c->snap_px, sizeof(PX) * c->slots,
                              hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots,
@@ -519,8 +557,8 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     c->cur = 0;
     c->step = step0;
     c->first = first0;
+    c->next_sort = sort0;
     c->force_pending = 1;
-    (void)force0;
   }
   std::vector<vb_step_record> rec((size_t)n_steps * c->n_sys);
   HIP_OK(c, hipMemcpy(rec.data(), c->hist_d, sizeof(vb_step_record) * rec.size(),
@@ -564,17 +602,21 @@ extern "C" vb_status vb_get_pairs(vb_ctx *c, int32_t sys, int32_t which, int32_t
   if (which != 0 && which != 1) return fail(c, VB_EINVAL, "which must be 0 or 1");
   if (cap < 0 || (cap > 0 && !d_pairs)) return fail(c, VB_EINVAL, "bad output buffer");
   vb_status st;
-  if (which == 1 && (st = queue_rebuild(c)) != VB_OK) return st;
-  int32_t ra = -1;
-  HIP_OK(c, hipMemcpyAsync(&ra, c->rebuilt_at + sys, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c->stream));
-  HIP_OK(c, hipStreamSynchronize(c->stream));
-  // rows follow the slot order of the last broad phase: the permuted copy if it
-  // ran at this step, else the current state (which keeps that order)
-  const PX *src = (ra == (int32_t)c->step) ? c->px_tmp : c->px[c->cur];
-  HIP_OK(c, launch_pairs(c->sys_h[sys], src, c->cnt, c->nbr, c->slots, which, c->pair_counts,
-                         c->pair_offsets, c->pair_total, cap, cap > 0 ? d_pairs : nullptr,
-                         cap > 0 ? d_delta : nullptr, c->stream));
+  if (which == 1) {
+    // the broad phase the next step would run, if any; the next step repeats it
+    // when its flag is still set, so the bins are emptied again here
+    if ((st = queue_broad_phase(c)) != VB_OK) return st;
+    HIP_OK(c, launch_fill_i32(c->bin_count, c->n_cells, 0, c->stream));
+    int32_t ovf[2] = {0, 0};
+    HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (ovf[0] > c->width || ovf[1] > c->bin_cap)
+      return fail(c, VB_ECAPACITY, "list row or cell bin overflow in the broad phase; run a "
+                                   "step first so that vb_run grows them");
+  }
+  HIP_OK(c, launch_pairs(c->sys_h[sys], c->px[c->cur], c->cnt, c->nbr, c->slots, which,
+                         c->pair_counts, c->pair_offsets, c->pair_total, cap,
+                         cap > 0 ? d_pairs : nullptr, cap > 0 ? d_delta : nullptr, c->stream));
   int64_t total = 0;
   HIP_OK(c, hipMemcpyAsync(&total, c->pair_total, sizeof(int64_t), hipMemcpyDeviceToHost,
                            c->stream));

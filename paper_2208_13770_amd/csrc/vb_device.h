@@ -1,10 +1,10 @@
 // vb_device.h -- device-side data layout of libvbuf (internal).
 //
 // Particles live in "slots".  Each system of a batch owns a contiguous range of
-// slots padded to a multiple of TILE, so a tile (one workgroup of the step
-// kernel) never straddles two systems.  Slots are kept in cell-sorted order (by
-// cell, then by original index), re-permuted at every broad phase; the original
-// index travels inside the position record.
+// slots padded to a multiple of TILE, so a tile (one workgroup) never straddles
+// two systems.  The original index travels inside the position record; the slot
+// order is re-sorted by cell from time to time for locality (not at every broad
+// phase), so rows of the Verlet list hold slots and are ordered by original index.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -16,6 +16,8 @@ constexpr int WAVE = 64;          // CDNA wavefront
 constexpr int MAX_SYS = 1024;     // systems per batch
 constexpr int STATS_RING = 64;    // steps of per-tile statistics kept before reduction
 constexpr int MAX_ROW = 128;      // largest Verlet-list row (rows are sorted in LDS)
+constexpr int MAX_BIN = 256;      // largest cell-bin capacity
+constexpr int SCAN_ITEMS = 16;    // cells per thread in the block-level scans
 
 // Position record, 32 B: FP64 centre, FP32 cut-off radius R_C, original index.
 struct alignas(16) PX {
@@ -69,60 +71,71 @@ struct RecordDev {
   double kinetic_energy;
 };
 
+// Arguments of the two broad-phase kernels (binning, pair search).
+struct BroadArgs {
+  const SysDev *sys;
+  const int32_t *tile_sys;
+  int32_t n_sys;
+  int64_t n_tiles;
+  const PX *px;
+  const PV *pv;
+  float4 *bp;           // [slots] x0 (FP32) and R_NL of the broad phase
+  int32_t *cnt;         // [slots] row lengths
+  int32_t *nbr;         // rows, column-major: entry q of slot k at nbr[q * stride + k]
+  int64_t stride;
+  int32_t width;        // row capacity W
+  int32_t *bin_count;   // [cells] particles binned per cell (zeroed by the step kernel)
+  int32_t *bins;        // [cells][bin_cap] local slots
+  int32_t bin_cap;
+  int32_t *cellid;      // [slots] cell of each slot
+  int32_t *inv;         // [slots] inv[p_off + orig] = local slot
+  const int32_t *flags; // [2][n_sys] validity-violation flags; slot (step & 1) is read
+  int32_t *go;          // [n_sys] 1 if the system runs a broad phase at this step
+  int32_t *rebuilt_ring;  // [STATS_RING][n_sys]
+  int32_t *overflow;    // [0] longest row beyond W, [1] fullest bin beyond bin_cap
+  int32_t step;
+  int32_t force;        // 1: broad phase for every system regardless of flags
+};
+
 // Arguments of the fused step kernel.
 struct StepArgs {
   const SysDev *sys;
   const int32_t *tile_sys;
   const PX *px_cur;
   const PV *pv_cur;
-  const PX *px_tmp;   // permuted state written by a broad phase at this step
-  const PV *pv_tmp;
   PX *px_dst;
   PV *pv_dst;
-  const float4 *bp;   // x0 (FP32) and R_NL of the last broad phase
-  const int32_t *cnt; // row lengths
-  const int32_t *nbr; // rows, column-major: entry q of slot k at nbr[q * stride + k]
+  const float4 *bp;
+  const int32_t *cnt;
+  const int32_t *nbr;
   int64_t stride;
-  const int32_t *rebuilt_at;  // [n_sys] step of the last broad phase
-  int32_t *flags;     // [2][n_sys] validity-violation flags, slot (step & 1)
+  const int32_t *go;     // [n_sys] broad phase ran at this step
+  int32_t *flags;        // [2][n_sys]
+  int32_t *bin_count;    // cleared after a broad phase
   int32_t n_sys;
-  TileStats *stats;   // [STATS_RING][n_tiles_total]
+  TileStats *stats;      // [STATS_RING][n_tiles_total]
   int64_t n_tiles;
   int32_t step;
-  int32_t first;      // 1: the velocities are the full-step v^0 (no first half kick)
-  int32_t xcd_remap;  // 1: give each XCD a contiguous range of tiles
+  int32_t first;         // 1: the velocities are the full-step v^0 (no first half kick)
+  int32_t xcd_remap;     // 1: give each XCD a contiguous range of tiles
 };
 
-// Arguments of the broad-phase (rebuild) kernel.
-struct RebuildArgs {
+// Arguments of the spatial re-sort (counting sort of the slots by cell).
+struct SortArgs {
   const SysDev *sys;
   const int32_t *tile_sys;
-  int32_t n_sys;
   int64_t n_tiles;
-  int64_t n_cells;    // total cells of the batch
-  const PX *px_cur;
-  const PV *pv_cur;
-  PX *px_tmp;
-  PV *pv_tmp;
-  float4 *bp;
-  int32_t *cnt;
-  int32_t *nbr;
-  int64_t stride;
-  int32_t width;      // row capacity W
-  int32_t *cell_count;  // [n_cells]
-  int32_t *cell_start;  // [n_cells + 1]
-  int32_t *block_sum;   // [grid]
-  int32_t *cellid;      // [slots] cell of each slot (current order)
-  int32_t *cellid_new;  // [slots] cell of each slot (new order)
-  int32_t *inslot;      // [slots] arrival rank inside its cell
-  int32_t *perm0;       // [slots] provisional new order
-  int32_t *perm;        // [slots] new order: perm[new slot] = old local slot
-  int32_t *inv;         // [slots] inv[p_off + orig] = new local slot
-  int32_t *rebuilt_at;
-  int32_t *flags;
-  int32_t *overflow;    // [1] largest row length seen beyond W (0 if none)
-  int32_t step;
-  int32_t force;        // 1: broad phase for every system regardless of flags
+  int64_t n_cells;
+  const PX *px_src;
+  const PV *pv_src;
+  PX *px_dst;
+  PV *pv_dst;
+  int32_t *cell_count;  // [cells] zero on entry, zero on exit
+  int32_t *cell_start;  // [cells + 1]
+  int32_t *block_sum;   // [scan blocks]
+  int32_t *cellid;      // [slots]
+  int32_t *inslot;      // [slots]
+  int32_t *perm0;       // [slots]
 };
 
 }  // namespace vb

@@ -1,21 +1,24 @@
 // vb_kernels.hip -- gfx950 kernels of the local Verlet buffer DEM step.
 //
-// k_step     fused narrow phase + contact forces + velocity-Verlet integration
-//            + displacement validity test (Sec. 3.2 Eq. delta, Sec. 5.1 model and
-//            integrator, Sec. 4.2 Eq. update), one thread per particle, rows of
-//            the Verlet list gathered in ascending original partner index.
-// k_rebuild  the conditional broad phase (Def. autoverlet): local skin and cap
-//            (Eq. skin_formulus1, bounding_sphere, skin_formulus_mincell), cell
-//            binning by counting sort, cell-sorted permutation of the state, and
-//            the linked-cell pair search of Alg. 1 on the extended spheres.  One
-//            cooperative launch per step; it returns at once when no system of
-//            the batch needs a broad phase, so the host never waits on the flag.
-#include <hip/hip_cooperative_groups.h>
+// Per time step three launches run on the context's stream:
+//   k_bin    the start of the conditional broad phase (Def. autoverlet): for each
+//            system whose list went invalid (Eq. update failed at the previous
+//            step) or that is forced, the extended spheres of Eq. bounding_sphere
+//            with the local skin of Eq. skin_formulus1 capped as in Eq.
+//            skin_formulus_mincell, the reference positions x0, and the
+//            binning of the particles into the uniform cells of Alg. 1;
+//   k_pairs  the linked-cell pair search of Alg. 1 on those spheres, one thread
+//            per particle over the cells within `ring` cells, each row kept
+//            sorted by original index;
+//   k_step   narrow phase (Eq. delta), normal spring-dashpot contact force, walls,
+//            velocity-Verlet integration and the displacement test of Eq. update
+//            for the next step, fused, one thread per particle.
+// Both broad-phase kernels return at once when no system needs a broad phase,
+// so the host never waits on the validity flag.  A counting sort of the particle
+// storage by cell (k_sort_*) runs when the host schedules it, for locality.
 #include <hip/hip_runtime.h>
 
 #include "vb_device.h"
-
-namespace cg = cooperative_groups;
 
 namespace vb {
 
@@ -91,26 +94,59 @@ __device__ __forceinline__ bool overlap_positive(const PX &a, const PX &b, doubl
 }
 
 // Maps a workgroup index to a tile so that each of the 8 XCDs (which receive
-// workgroups round-robin) walks a contiguous range of tiles: neighbouring tiles
-// share neighbour particles, and each XCD has its own L2.
+// workgroups round-robin) walks a contiguous range of tiles.
 __device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n) {
   const int64_t x = i & 7, k = i >> 3;
   const int64_t q = n >> 3, r = n & 7;
   return x * q + (x < r ? x : r) + k;
 }
 
+// Uniform cell of a position (Alg. 1: uniform decomposition of the domain);
+// positions outside the box fall in the border cells.
+__device__ __forceinline__ int cell_of(const SysDev &S, double x, double y, double z) {
+  const double p[3] = {x, y, z};
+  int c[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    double f = floor((p[ax] - S.lo[ax]) * S.inv_edge[ax]);
+    f = fmin(fmax(f, 0.0), (double)(S.nc[ax] - 1));  // NaN -> 0, clamp to the grid
+    c[ax] = (int)f;
+  }
+  return (c[2] * S.nc[1] + c[1]) * S.nc[0] + c[0];
+}
+
+// Does system s run a broad phase at this step?  (Def. autoverlet: when Eq.
+// update failed after the previous step; always without buffer; every
+// fixed_interval steps in the fixed-interval practice; when forced.)
+__device__ __forceinline__ int needs_broad_phase(const SysDev &S, const int32_t *flags, int n_sys,
+                                                 int s, int step, int force) {
+  if (force || S.skin_mode == 2) return 1;
+  if (S.skin_mode == 3) return (step % S.fixed_interval) == 0;
+  return flags[(step & 1) * n_sys + s] != 0;
+}
+
 // ------------------------------------------------------------------ k_step
 
+template <int UNROLL>
 __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   const int64_t t = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int s = a.tile_sys[t];
   const SysDev &S = a.sys[s];
-  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  const int lt = (int)(t - S.tile_off);
+  const int local = lt * TILE + (int)threadIdx.x;
   const bool active = local < S.n;
   const int64_t k = S.p_off + local;
-  const bool fresh = a.rebuilt_at[s] == a.step;
-  const PX *__restrict__ px = fresh ? a.px_tmp : a.px_cur;
-  const PV *__restrict__ pv = fresh ? a.pv_tmp : a.pv_cur;
+  const PX *__restrict__ px = a.px_cur;
+  const PV *__restrict__ pv = a.pv_cur;
+
+  // after a broad phase: empty this tile's share of the system's cell bins and
+  // consume the flag that asked for it
+  if (a.go[s]) {
+    const int chunk = (S.ncell + S.n_tiles - 1) / S.n_tiles;
+    const int c1 = min(S.ncell, (lt + 1) * chunk);
+    for (int c = lt * chunk + (int)threadIdx.x; c < c1; c += TILE) a.bin_count[S.c_off + c] = 0;
+    if (lt == 0 && threadIdx.x == 0) a.flags[(a.step & 1) * a.n_sys + s] = 0;
+  }
 
   double ke = 0.0;
   int rowlen = 0, ncon = 0, viol = 0;
@@ -121,13 +157,14 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const float4 b = a.bp[k];
     rowlen = a.cnt[k];
     double fx = 0.0, fy = 0.0, fz = 0.0;
+    // Row entries in ascending original index; UNROLL gathers in flight at a time,
+    // accumulated strictly in row order.
     const int32_t *row = a.nbr + k;
-    for (int q = 0; q < rowlen; ++q) {
-      const int64_t j = S.p_off + row[(int64_t)q * a.stride];
-      const PX o = px[j];
+    const int64_t st = a.stride;
+    auto contact = [&](const PX &o, int32_t jl) {
       double dx, dy, dz, d, delta;
       if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
-        const PV ov = pv[j];
+        const PV ov = pv[S.p_off + jl];
         const double inv = 1.0 / d;
         const double nx = dx * inv, ny = dy * inv, nz = dz * inv;
         const double vn = (mv.vx - ov.vx) * nx + (mv.vy - ov.vy) * ny + (mv.vz - ov.vz) * nz;
@@ -137,6 +174,21 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         fz += fm * nz;
         ++ncon;
       }
+    };
+    int q = 0;
+    for (; q + UNROLL <= rowlen; q += UNROLL) {
+      int32_t j[UNROLL];
+      PX o[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) j[u] = row[(int64_t)(q + u) * st];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) o[u] = px[S.p_off + j[u]];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) contact(o[u], j[u]);
+    }
+    for (; q < rowlen; ++q) {
+      const int32_t j = row[(int64_t)q * st];
+      contact(px[S.p_off + j], j);
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
     // in the order -x, +x, -y, +y, -z, +z
@@ -205,197 +257,87 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    TileStats st;
-    st.ke = 0.0;
-    st.rowsum = st.contacts2 = st.violators = 0;
-    st.max_excess = -INFINITY;
+    TileStats stt;
+    stt.ke = 0.0;
+    stt.rowsum = stt.contacts2 = stt.violators = 0;
+    stt.max_excess = -INFINITY;
 #pragma unroll
     for (int i = 0; i < TILE / WAVE; ++i) {
-      st.ke += s_ke[i];
-      st.rowsum += s_i[0][i];
-      st.contacts2 += s_i[1][i];
-      st.violators += s_i[2][i];
-      st.max_excess = fmaxf(st.max_excess, s_x[i]);
+      stt.ke += s_ke[i];
+      stt.rowsum += s_i[0][i];
+      stt.contacts2 += s_i[1][i];
+      stt.violators += s_i[2][i];
+      stt.max_excess = fmaxf(stt.max_excess, s_x[i]);
     }
-    a.stats[(int64_t)(a.step % STATS_RING) * a.n_tiles + t] = st;
-    if (st.violators > 0 && (S.skin_mode == 0 || S.skin_mode == 1))
+    a.stats[(int64_t)(a.step % STATS_RING) * a.n_tiles + t] = stt;
+    if (stt.violators > 0 && (S.skin_mode == 0 || S.skin_mode == 1))
       atomicOr(&a.flags[((a.step + 1) & 1) * a.n_sys + s], 1);
   }
 }
 
-// ------------------------------------------------------------------ k_rebuild
+// ------------------------------------------------------------------ broad phase
 
-__device__ __forceinline__ void grid_barrier(cg::grid_group &grid) {
-  __threadfence();
-  grid.sync();
-  __threadfence();
-}
-
-__device__ __forceinline__ int cell_of(const SysDev &S, double x, double y, double z) {
-  const double p[3] = {x, y, z};
-  int c[3];
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    double f = floor((p[ax] - S.lo[ax]) * S.inv_edge[ax]);
-    f = fmin(fmax(f, 0.0), (double)(S.nc[ax] - 1));  // NaN -> 0, clamp to the grid
-    c[ax] = (int)f;
-  }
-  return (c[2] * S.nc[1] + c[1]) * S.nc[0] + c[0];
-}
-
-__global__ __launch_bounds__(TILE) void k_rebuild(RebuildArgs a) {
-  extern __shared__ int32_t s_row[];  // TILE * width, column t is thread t's row
-  __shared__ uint8_t need[MAX_SYS];
-  __shared__ int any_need;
-  cg::grid_group grid = cg::this_grid();
+// Extended spheres, reference positions and cell bins of every system that needs
+// a broad phase at this step.  Grid-stride over tiles.
+__global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
   const int tid = threadIdx.x;
-
-  // P0: which systems run a broad phase at this step (Def. autoverlet: the list
-  // is rebuilt when Eq. update failed at the end of the previous step)
-  if (tid == 0) any_need = 0;
-  __syncthreads();
+  int any = 0;
   for (int s = tid; s < a.n_sys; s += TILE) {
-    const SysDev &S = a.sys[s];
-    int nd = a.force;
-    if (S.skin_mode == 2) nd = 1;                                             // no buffer
-    else if (S.skin_mode == 3) nd |= (a.step % S.fixed_interval) == 0;       // fixed interval
-    else nd |= a.flags[(a.step & 1) * a.n_sys + s] != 0;                    // automatic
-    need[s] = (uint8_t)nd;
-    if (nd) atomicOr(&any_need, 1);
+    const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, a.step, a.force);
+    any |= nd;
+    if (blockIdx.x == 0) {
+      a.go[s] = nd;
+      a.rebuilt_ring[(a.step % STATS_RING) * a.n_sys + s] = nd;
+    }
   }
-  __syncthreads();
-  if (!any_need) return;  // the same decision in every workgroup
-  const int64_t G = gridDim.x;
-
-  // P1: cell of every particle; arrival slot inside the cell
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+  if (!__syncthreads_or(any)) return;  // the same decision in every workgroup
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const int s = a.tile_sys[t];
-    if (!need[s]) continue;
     const SysDev &S = a.sys[s];
+    if (!needs_broad_phase(S, a.flags, a.n_sys, s, a.step, a.force)) continue;
     const int local = (int)(t - S.tile_off) * TILE + tid;
-    if (local < S.n) {
-      const int64_t k = S.p_off + local;
-      const PX p = a.px_cur[k];
-      const int c = cell_of(S, p.x, p.y, p.z);
-      a.cellid[k] = c;
-      a.inslot[k] = atomicAdd(&a.cell_count[S.c_off + c], 1);
-    }
+    if (local >= S.n) continue;
+    const int64_t k = S.p_off + local;
+    const PX x = a.px[k];
+    const PV v = a.pv[k];
+    double skin;
+    if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
+    else if (S.skin_mode == 2) skin = 0.0;
+    else skin = S.skin_uniform;
+    const double r = (double)x.rc + skin;
+    const double rnl = r < S.cap ? r : S.cap;
+    a.bp[k] = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
+    const int c = cell_of(S, x.x, x.y, x.z);
+    a.cellid[k] = c;
+    a.inv[S.p_off + x.orig] = local;
+    const int slot = atomicAdd(&a.bin_count[S.c_off + c], 1);
+    if (slot < a.bin_cap) a.bins[(S.c_off + c) * a.bin_cap + slot] = local;
+    else atomicMax(&a.overflow[1], slot + 1);
   }
-  grid_barrier(grid);
+}
 
-  // P2: exclusive prefix sum of the cell counts over the whole batch
-  const int64_t C = a.n_cells;
-  const int64_t ch = (C + G - 1) / G;
-  const int64_t c0 = blockIdx.x * ch, c1 = c0 + ch < C ? c0 + ch : C;
-  {
-    int64_t part = 0;
-    for (int64_t c = c0 + tid; c < c1; c += TILE) part += a.cell_count[c];
-    part = block_sum_i64(part);
-    if (tid == 0) a.block_sum[blockIdx.x] = (int32_t)part;
-  }
-  grid_barrier(grid);
-  {
-    int64_t pre = 0;
-    for (int64_t b = tid; b < blockIdx.x; b += TILE) pre += a.block_sum[b];
-    int carry = (int)block_sum_i64(pre);
-    for (int64_t base = c0; base < c1; base += TILE) {
-      const int64_t c = base + tid;
-      const int v = c < c1 ? a.cell_count[c] : 0;
-      int tot;
-      const int incl = block_inclusive_scan(v, &tot);
-      if (c < c1) a.cell_start[c] = carry + incl - v;
-      carry += tot;
-    }
-    if (c0 < C && c1 == C && tid == 0) a.cell_start[C] = carry;
-  }
-  grid_barrier(grid);
-
-  // P3: counting-sort scatter into a provisional cell order; clear the counts
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
-    const int s = a.tile_sys[t];
-    if (!need[s]) continue;
-    const SysDev &S = a.sys[s];
-    const int local = (int)(t - S.tile_off) * TILE + tid;
-    if (local < S.n) {
-      const int64_t k = S.p_off + local;
-      const int32_t base = a.cell_start[S.c_off];
-      const int64_t pos = S.p_off + (a.cell_start[S.c_off + a.cellid[k]] - base) + a.inslot[k];
-      a.perm0[pos] = local;
-    }
-  }
-  for (int s = 0; s < a.n_sys; ++s) {
-    if (!need[s]) continue;
-    const SysDev &S = a.sys[s];
-    for (int64_t c = blockIdx.x * (int64_t)TILE + tid; c < S.ncell; c += G * TILE)
-      a.cell_count[S.c_off + c] = 0;
-  }
-  grid_barrier(grid);
-
-  // P4: inside each cell, order the particles by original index (deterministic)
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
-    const int s = a.tile_sys[t];
-    if (!need[s]) continue;
-    const SysDev &S = a.sys[s];
-    const int local = (int)(t - S.tile_off) * TILE + tid;
-    if (local < S.n) {
-      const int64_t p = S.p_off + local;
-      const int32_t q = a.perm0[p];
-      const int c = a.cellid[S.p_off + q];
-      const int32_t base = a.cell_start[S.c_off];
-      const int64_t cs = S.p_off + (a.cell_start[S.c_off + c] - base);
-      const int64_t ce = S.p_off + (a.cell_start[S.c_off + c + 1] - base);
-      const uint32_t my = a.px_cur[S.p_off + q].orig;
-      int rank = 0;
-      for (int64_t m = cs; m < ce; ++m) rank += a.px_cur[S.p_off + a.perm0[m]].orig < my;
-      a.perm[cs + rank] = q;
-    }
-  }
-  grid_barrier(grid);
-
-  // P5: permute the state into cell order; extended spheres of the broad phase:
-  // skin_p = K |v_p| dt (Eq. skin_formulus1), R_NL = min(R_C + skin, cap)
-  // (Eq. bounding_sphere, Eq. skin_formulus_mincell); reference positions x0
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
-    const int s = a.tile_sys[t];
-    if (!need[s]) continue;
-    const SysDev &S = a.sys[s];
-    const int local = (int)(t - S.tile_off) * TILE + tid;
-    if (local < S.n) {
-      const int64_t p = S.p_off + local;
-      const int64_t src = S.p_off + a.perm[p];
-      const PX x = a.px_cur[src];
-      const PV v = a.pv_cur[src];
-      a.px_tmp[p] = x;
-      a.pv_tmp[p] = v;
-      double skin;
-      if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
-      else if (S.skin_mode == 2) skin = 0.0;
-      else skin = S.skin_uniform;
-      const double r = (double)x.rc + skin;
-      const double rnl = r < S.cap ? r : S.cap;
-      a.bp[p] = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
-      a.cellid_new[p] = a.cellid[src];
-      a.inv[S.p_off + x.orig] = local;
-    }
-  }
-  grid_barrier(grid);
-
-  // P6: linked-cell pair search (Alg. 1) on the extended spheres: every particle
-  // of the cells within `ring` cells whose sphere meets this one (plus eps), kept
-  // as a row sorted by original index
+// Alg. 1 on the extended spheres: for each particle, every particle binned in
+// the cells within `ring` cells whose sphere meets this one (|x_i - x_j| <=
+// R_NL,i + R_NL,j, plus eps for FP32 rounding), kept as a row sorted by
+// original index in LDS (column t is thread t's row) and stored as slots.
+__global__ __launch_bounds__(TILE) void k_pairs(BroadArgs a) {
+  extern __shared__ int32_t s_row[];
+  const int tid = threadIdx.x;
+  int any = 0;
+  for (int s = tid; s < a.n_sys; s += TILE) any |= a.go[s];
+  if (!__syncthreads_or(any)) return;
   const int W = a.width;
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += G) {
+  for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const int s = a.tile_sys[t];
-    if (!need[s]) continue;
+    if (!a.go[s]) continue;
     const SysDev &S = a.sys[s];
     const int local = (int)(t - S.tile_off) * TILE + tid;
     if (local >= S.n) continue;
-    const int64_t p = S.p_off + local;
-    const float4 me = a.bp[p];
-    const int c = a.cellid_new[p];
+    const int64_t k = S.p_off + local;
+    const float4 me = a.bp[k];
+    const int c = a.cellid[k];
     const int nx = S.nc[0], ny = S.nc[1], nz = S.nc[2];
     const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-    const int32_t base = a.cell_start[S.c_off];
     int count = 0;
     for (int dz = -S.ring; dz <= S.ring; ++dz) {
       const int bz = cz + dz;
@@ -406,23 +348,24 @@ __global__ __launch_bounds__(TILE) void k_rebuild(RebuildArgs a) {
         for (int dx = -S.ring; dx <= S.ring; ++dx) {
           const int bx = cx + dx;
           if (bx < 0 || bx >= nx) continue;
-          const int cc = (bz * ny + by) * nx + bx;
-          const int64_t cs = S.p_off + (a.cell_start[S.c_off + cc] - base);
-          const int64_t ce = S.p_off + (a.cell_start[S.c_off + cc + 1] - base);
-          for (int64_t m = cs; m < ce; ++m) {
-            if (m == p) continue;
-            const float4 o = a.bp[m];
+          const int64_t cc = S.c_off + (bz * ny + by) * nx + bx;
+          const int nin = min(a.bin_count[cc], a.bin_cap);
+          const int32_t *bin = a.bins + cc * a.bin_cap;
+          for (int i = 0; i < nin; ++i) {
+            const int32_t m = bin[i];
+            if (m == local) continue;
+            const float4 o = a.bp[S.p_off + m];
             const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
             const float d = sqrtf(ex * ex + ey * ey + ez * ez);
             if (d <= me.w + o.w + S.eps) {
               if (count < W) {
-                const int32_t key = (int32_t)a.px_tmp[m].orig;
-                int i = count;
-                while (i > 0 && s_row[(i - 1) * TILE + tid] > key) {
-                  s_row[i * TILE + tid] = s_row[(i - 1) * TILE + tid];
-                  --i;
+                const int32_t key = (int32_t)a.px[S.p_off + m].orig;
+                int j = count;
+                while (j > 0 && s_row[(j - 1) * TILE + tid] > key) {
+                  s_row[j * TILE + tid] = s_row[(j - 1) * TILE + tid];
+                  --j;
                 }
-                s_row[i * TILE + tid] = key;
+                s_row[j * TILE + tid] = key;
               }
               ++count;
             }
@@ -431,18 +374,113 @@ __global__ __launch_bounds__(TILE) void k_rebuild(RebuildArgs a) {
       }
     }
     const int kept = count < W ? count : W;
-    for (int q = 0; q < kept; ++q) a.nbr[(int64_t)q * a.stride + p] = a.inv[S.p_off + s_row[q * TILE + tid]];
-    a.cnt[p] = kept;
-    if (count > W) atomicMax(a.overflow, count);
+    for (int q = 0; q < kept; ++q)
+      a.nbr[(int64_t)q * a.stride + k] = a.inv[S.p_off + s_row[q * TILE + tid]];
+    a.cnt[k] = kept;
+    if (count > W) atomicMax(&a.overflow[0], count);
   }
-  // every workgroup passed P0 before the first barrier: the flags can be consumed
-  if (blockIdx.x == 0) {
-    for (int s = tid; s < a.n_sys; s += TILE) {
-      if (!need[s]) continue;
-      a.flags[(a.step & 1) * a.n_sys + s] = 0;
-      a.rebuilt_at[s] = a.step;
-    }
+}
+
+// ------------------------------------------------------------------ spatial sort
+
+// Counting sort of every system's slots by cell, then by original index inside a
+// cell (deterministic).  Scheduled by the host; followed by a broad phase.
+__global__ __launch_bounds__(TILE) void k_sort_count(SortArgs a) {
+  const int64_t t = blockIdx.x;
+  const SysDev &S = a.sys[a.tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const PX p = a.px_src[k];
+  const int c = cell_of(S, p.x, p.y, p.z);
+  a.cellid[k] = c;
+  a.inslot[k] = atomicAdd(&a.cell_count[S.c_off + c], 1);
+}
+
+// Exclusive scan, stage 1: each workgroup scans TILE * SCAN_ITEMS cells.
+__global__ __launch_bounds__(TILE) void k_scan_blocks(const int32_t *in, int64_t n, int32_t *out,
+                                                      int32_t *block_sum) {
+  const int64_t base = (int64_t)blockIdx.x * TILE * SCAN_ITEMS + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0;
+    sum += v[i];
   }
+  int tot;
+  const int incl = block_inclusive_scan(sum, &tot);
+  int run = incl - sum;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+// Stage 2: exclusive scan of the block sums in one workgroup; block_sum[nb] = total.
+__global__ __launch_bounds__(TILE) void k_scan_top(int32_t *block_sum, int64_t nb) {
+  __shared__ int carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += TILE) {
+    const int64_t i = b0 + threadIdx.x;
+    const int v = i < nb ? block_sum[i] : 0;
+    int tot;
+    const int incl = block_inclusive_scan(v, &tot);
+    const int carry = carry_s;
+    if (i < nb) block_sum[i] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_sum[nb] = carry_s;
+}
+
+// Stage 3: add the block offsets; out[n] = total.
+__global__ __launch_bounds__(TILE) void k_scan_add(int32_t *out, int64_t n, const int32_t *block_sum,
+                                                   int64_t nb) {
+  const int64_t base = (int64_t)blockIdx.x * TILE * SCAN_ITEMS + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const int add = block_sum[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i)
+    if (base + i < n) out[base + i] += add;
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = block_sum[nb];
+}
+
+// Scatter every slot to a provisional place inside its cell; empty the counts.
+__global__ __launch_bounds__(TILE) void k_sort_scatter(SortArgs a) {
+  const int64_t t = blockIdx.x;
+  const int64_t chunk = (a.n_cells + a.n_tiles - 1) / a.n_tiles;
+  const int64_t c1 = min(a.n_cells, (t + 1) * chunk);
+  for (int64_t c = t * chunk + threadIdx.x; c < c1; c += TILE) a.cell_count[c] = 0;
+  const SysDev &S = a.sys[a.tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const int32_t base = a.cell_start[S.c_off];
+  a.perm0[S.p_off + (a.cell_start[S.c_off + a.cellid[k]] - base) + a.inslot[k]] = local;
+}
+
+// Final place = cell start + rank of the original index among the cell's
+// particles; move the state there.
+__global__ __launch_bounds__(TILE) void k_sort_place(SortArgs a) {
+  const int64_t t = blockIdx.x;
+  const SysDev &S = a.sys[a.tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t p = S.p_off + local;
+  const int32_t q = a.perm0[p];
+  const int c = a.cellid[S.p_off + q];
+  const int32_t base = a.cell_start[S.c_off];
+  const int64_t cs = S.p_off + (a.cell_start[S.c_off + c] - base);
+  const int64_t ce = S.p_off + (a.cell_start[S.c_off + c + 1] - base);
+  const PX me = a.px_src[S.p_off + q];
+  int rank = 0;
+  for (int64_t m = cs; m < ce; ++m) rank += a.px_src[S.p_off + a.perm0[m]].orig < me.orig;
+  a.px_dst[cs + rank] = me;
+  a.pv_dst[cs + rank] = a.pv_src[S.p_off + q];
 }
 
 // ------------------------------------------------------------------ statistics
@@ -499,13 +537,6 @@ __global__ __launch_bounds__(TILE) void k_stats_reduce(const SysDev *sys, const 
     rec.kinetic_energy = k2;
     out[(int64_t)r * n_sys + s] = rec;
   }
-}
-
-// Whether a broad phase ran at this step, per system (read by the reduction).
-__global__ void k_log_rebuilt(const int32_t *rebuilt_at, int32_t n_sys, int32_t step,
-                              int32_t *rebuilt_ring) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < n_sys) rebuilt_ring[(step % STATS_RING) * n_sys + s] = rebuilt_at[s] == step;
 }
 
 // ------------------------------------------------------------------ state I/O
@@ -660,32 +691,41 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 // Host entry points of the kernels above (C++ linkage, internal to the library).
 namespace vb {
 
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, hipStream_t st) {
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_step, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  if (unroll >= 4) hipLaunchKernelGGL(k_step<4>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  else if (unroll == 2) hipLaunchKernelGGL(k_step<2>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  else hipLaunchKernelGGL(k_step<1>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t rebuild_occupancy(int width, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, reinterpret_cast<const void *>(k_rebuild), TILE,
-      (size_t)TILE * (size_t)width * sizeof(int32_t));
-}
-
-hipError_t launch_rebuild(const RebuildArgs &a, int grid, hipStream_t st) {
-  RebuildArgs copy = a;
-  void *args[] = {&copy};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rebuild), dim3(grid),
-                                    dim3(TILE), args,
-                                    (unsigned)((size_t)TILE * (size_t)a.width * sizeof(int32_t)),
-                                    st);
-}
-
-hipError_t launch_log_rebuilt(const int32_t *rebuilt_at, int32_t n_sys, int32_t step,
-                              int32_t *ring, hipStream_t st) {
-  hipLaunchKernelGGL(k_log_rebuilt, dim3((n_sys + 255) / 256), dim3(256), 0, st, rebuilt_at,
-                     n_sys, step, ring);
+hipError_t launch_broad_phase(const BroadArgs &a, int grid, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin, dim3(grid), dim3(TILE), 0, st, a);
+  const size_t lds = (size_t)TILE * (size_t)a.width * sizeof(int32_t);
+  hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(TILE), lds, st, a);
   return hipGetLastError();
+}
+
+hipError_t launch_sort(const SortArgs &a, hipStream_t st) {
+  if (a.n_tiles <= 0) return hipSuccess;
+  const unsigned nt = (unsigned)a.n_tiles;
+  const int64_t per = (int64_t)TILE * SCAN_ITEMS;
+  const int64_t nb = (a.n_cells + per - 1) / per;
+  hipLaunchKernelGGL(k_sort_count, dim3(nt), dim3(TILE), 0, st, a);
+  hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(TILE), 0, st, a.cell_count,
+                     a.n_cells, a.cell_start, a.block_sum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(TILE), 0, st, a.block_sum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(TILE), 0, st, a.cell_start, a.n_cells,
+                     a.block_sum, nb);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(nt), dim3(TILE), 0, st, a);
+  hipLaunchKernelGGL(k_sort_place, dim3(nt), dim3(TILE), 0, st, a);
+  return hipGetLastError();
+}
+
+int64_t scan_blocks(int64_t n_cells) {
+  const int64_t per = (int64_t)TILE * SCAN_ITEMS;
+  return (n_cells + per - 1) / per;
 }
 
 hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,

@@ -90,7 +90,8 @@ def lattice_system(nx: int, ny: int, nz: int, n_boxes: int, n_balls: int, sigma:
     mass = (rad / (0.45 * a)) ** 3
     phys = physics_constants(a)
     v_max = phys["v_max"]
-    vel = np.zeros((n, 3))
+    # velocity field painted on the lattice grid, indexed [k, j, i] (z, y, x)
+    grid = np.zeros((nz, ny, nx, 3))
     dims = np.array([nx, ny, nz])
     for _ in range(n_boxes):
         lo = np.zeros(3, dtype=np.int64)
@@ -102,15 +103,24 @@ def lattice_system(nx: int, ny: int, nz: int, n_boxes: int, n_balls: int, sigma:
             lo[ax], hi[ax] = s, s + L
         speed = rng.uniform(0.0, 1.0) * v_max
         vv = speed * _unit_vector(rng)
-        inside = np.all((idx >= lo) & (idx < hi), axis=1)
-        vel[inside] = vv
+        grid[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = vv
     for _ in range(n_balls):
         c = rng.uniform(0.0, 1.0, size=3) * dims
         r = rng.uniform(0.05, 0.2) * dims.max()
         speed = rng.uniform(0.0, 1.0) * v_max
         vv = speed * _unit_vector(rng)
-        inside = np.sum((idx + 0.5 - c) ** 2, axis=1) <= r * r
-        vel[inside] = vv
+        # sites with (index + 1/2 - c)^2 summed <= r^2, searched in the ball's bounding box
+        b0 = np.maximum(np.floor(c - r - 1).astype(np.int64), 0)
+        b1 = np.minimum(np.ceil(c + r + 1).astype(np.int64), dims)
+        if np.any(b1 <= b0):
+            continue
+        gi = np.arange(b0[0], b1[0]) + 0.5 - c[0]
+        gj = np.arange(b0[1], b1[1]) + 0.5 - c[1]
+        gk = np.arange(b0[2], b1[2]) + 0.5 - c[2]
+        inside = (gi[None, None, :] ** 2 + gj[None, :, None] ** 2) + gk[:, None, None] ** 2 <= r * r
+        sub = grid[b0[2]:b1[2], b0[1]:b1[1], b0[0]:b1[0]]
+        sub[inside] = vv
+    vel = grid.reshape(n, 3)
     vel = vel + rng.normal(0.0, sigma * v_max, size=(n, 3))
 
     pos_r = np.empty((n, 4), dtype=np.float32)
