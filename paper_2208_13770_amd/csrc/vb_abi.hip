@@ -23,7 +23,8 @@
 
 namespace vb {
 hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st);
-hipError_t launch_broad_phase(const BroadArgs &a, int grid, hipStream_t st);
+hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st);
+size_t pairs_lds_bytes(int width, int pmax);
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 int64_t scan_blocks(int64_t n_cells);
 hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
@@ -61,9 +62,17 @@ struct vb_ctx {
   float4 *bp = nullptr;
   int32_t *cnt = nullptr, *nbr = nullptr;
   int32_t width = 0;
-  int32_t *bin_count = nullptr, *bins = nullptr;
+  int32_t *bin_count = nullptr;
+  float4 *bins_bp = nullptr;
+  int2 *bins_so = nullptr;
   int32_t bin_cap = 0;
   int32_t *cellid = nullptr, *inv = nullptr;
+  int32_t *brick_sys = nullptr;
+  int64_t n_bricks = 0;
+  int32_t pmax = 0;            // candidates k_pairs stages in LDS per workgroup
+  size_t lds_limit = 0;        // LDS bytes a workgroup may use on this device
+  int pairs_grid = 0;
+  int any_no_buffer = 0, any_fixed = 0;
   // counting sort of the storage
   int32_t *cell_count = nullptr, *cell_start = nullptr, *block_sum = nullptr;
   int32_t *inslot = nullptr, *perm0 = nullptr;
@@ -85,7 +94,7 @@ struct vb_ctx {
   int32_t sort_interval = 0;
   int loaded = 0;
   int xcd_remap = 0;
-  int step_unroll = 4;
+  int step_unroll = 8;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -119,7 +128,8 @@ static hipError_t dalloc(T **p, int64_t count) {
 
 static void free_all(vb_ctx *c) {
   void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->snap_px,
-                  c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins, c->cellid, c->inv,
+                  c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
+                  c->brick_sys, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
                   c->go, c->overflow, c->err, c->stats, c->rebuilt_ring, c->hist_d,
                   c->pair_counts, c->pair_offsets, c->pair_total};
@@ -156,19 +166,23 @@ static std::string check_params(const vb_params &p, int64_t n) {
 // Cell grid of one system: cells of edge at least L_C (1 + 2^-10) + 2 eps per
 // axis, so that every pair the FP32 inclusion test may accept lies in cells at
 // most `ring` apart (Sec. 3.2: cells not smaller than the bounding spheres).
-static void make_grid(const vb_params &p, SysDev &S) {
+// Cells are numbered brick by brick (bricks of BRICK^3 cells); the numbering
+// covers whole bricks, so a system uses nkeys >= nc[0] nc[1] nc[2] cell numbers.
+static int64_t make_grid(const vb_params &p, SysDev &S) {
   const double edge_min = p.cell_size * (1.0 + 1.0 / 1024.0) + 2.0 * p.eps;
-  int64_t ncell = 1;
+  int64_t nkeys = BRICK * BRICK * BRICK;
   for (int a = 0; a < 3; ++a) {
     const double len = p.hi[a] - p.lo[a];
     double k = std::floor(len / edge_min);
     if (k < 1) k = 1;
     if (k > 1 << 20) k = 1 << 20;
     S.nc[a] = (int32_t)k;
+    S.nb[a] = (S.nc[a] + BRICK - 1) / BRICK;
     S.inv_edge[a] = k / len;
-    ncell *= (int64_t)k;
+    nkeys *= S.nb[a];
   }
-  S.ncell = (int32_t)std::min<int64_t>(ncell, INT32_MAX);
+  S.nkeys = (int32_t)std::min<int64_t>(nkeys, INT32_MAX);
+  return nkeys;
 }
 
 static vb_status alloc_rows(vb_ctx *c, int32_t width) {
@@ -176,13 +190,23 @@ static vb_status alloc_rows(vb_ctx *c, int32_t width) {
   c->nbr = nullptr;
   HIP_OK(c, dalloc(&c->nbr, c->slots * (int64_t)width));
   c->width = width;
+  // LDS of k_pairs: the rows (TILE * width ints) plus up to 2048 staged
+  // candidates of 20 bytes; at least 80 KB (two workgroups per CU), at most the
+  // device's limit, 8 KB kept for the kernel's static arrays
+  const int64_t rows = (int64_t)pairs_lds_bytes(width, 0);
+  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit,
+                                           std::max<int64_t>(80 * 1024, rows + 8192 + 2048 * 20));
+  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows - 8192) / 20));
   return VB_OK;
 }
 
 static vb_status alloc_bins(vb_ctx *c, int32_t cap) {
-  if (c->bins) (void)hipFree(c->bins);
-  c->bins = nullptr;
-  HIP_OK(c, dalloc(&c->bins, c->n_cells * (int64_t)cap));
+  if (c->bins_bp) (void)hipFree(c->bins_bp);
+  if (c->bins_so) (void)hipFree(c->bins_so);
+  c->bins_bp = nullptr;
+  c->bins_so = nullptr;
+  HIP_OK(c, dalloc(&c->bins_bp, c->n_cells * (int64_t)cap));
+  HIP_OK(c, dalloc(&c->bins_so, c->n_cells * (int64_t)cap));
   c->bin_cap = cap;
   return VB_OK;
 }
@@ -230,11 +254,12 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     return bail(VB_EDEVICE);
   }
   c->n_cu = prop.multiProcessorCount;
-  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, prop.sharedMemPerBlock / (TILE * sizeof(int32_t)));
+  c->lds_limit = prop.sharedMemPerBlock;
+  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 8192) / (TILE * sizeof(int32_t)));
   c->n_sys = n_sys;
   c->sys_h.resize(n_sys);
   c->sort_interval = h_params[0].reorder_interval;
-  int64_t p_off = 0, t_off = 0, c_off = 0, o_off = 0;
+  int64_t p_off = 0, t_off = 0, c_off = 0, o_off = 0, b_off = 0;
   int32_t width = 1, bcap = 1;
   for (int s = 0; s < n_sys; ++s) {
     const vb_params &p = h_params[s];
@@ -246,8 +271,8 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.tile_off = t_off;
     S.c_off = c_off;
     S.o_off = o_off;
-    make_grid(p, S);
-    if ((int64_t)S.nc[0] * S.nc[1] * S.nc[2] > (1LL << 30)) {
+    S.b_off = b_off;
+    if (make_grid(p, S) > (1LL << 30)) {
       c->msg = "system " + std::to_string(s) + ": cell grid too fine for the box";
       return bail(VB_EINVAL);
     }
@@ -268,8 +293,11 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.ring = p.cap_mode == 0 ? 1 : 2;
     p_off += (int64_t)S.n_tiles * TILE;
     t_off += S.n_tiles;
-    c_off += S.ncell;
+    c_off += S.nkeys;
     o_off += S.n;
+    b_off += (int64_t)S.nb[0] * S.nb[1] * S.nb[2];
+    c->any_no_buffer |= p.skin_mode == VB_NO_BUFFER;
+    c->any_fixed |= p.skin_mode == VB_FIXED_INTERVAL;
     width = std::max(width, p.max_neighbors);
     bcap = std::max(bcap, p.bin_capacity > 0 ? p.bin_capacity : 16);
     c->max_n = std::max(c->max_n, S.n);
@@ -282,6 +310,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   c->n_tiles = t_off;
   c->n_cells = c_off;
   c->n_total = o_off;
+  c->n_bricks = b_off;
   if (c->slots > (int64_t)INT32_MAX || c->n_cells > (int64_t)INT32_MAX) {
     c->msg = "batch too large";
     return bail(VB_EINVAL);
@@ -289,9 +318,15 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   // the broad-phase kernels walk the tiles grid-stride from a bounded grid, so
   // that a step without broad phase costs two short launches
   c->broad_grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_tiles, 8LL * c->n_cu));
+  c->pairs_grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_bricks, 8LL * c->n_cu));
   std::vector<int32_t> ts(std::max<int64_t>(c->n_tiles, 1), 0);
   for (int s = 0; s < n_sys; ++s)
     for (int t = 0; t < c->sys_h[s].n_tiles; ++t) ts[c->sys_h[s].tile_off + t] = s;
+  std::vector<int32_t> bs(std::max<int64_t>(c->n_bricks, 1), 0);
+  for (int s = 0; s < n_sys; ++s) {
+    const SysDev &S = c->sys_h[s];
+    for (int64_t b = 0; b < (int64_t)S.nb[0] * S.nb[1] * S.nb[2]; ++b) bs[S.b_off + b] = s;
+  }
 
 #define ALLOC(ptr, count)                                         \
   if (dalloc(&(ptr), (count)) != hipSuccess) {                    \
@@ -307,6 +342,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->bp, c->slots);
   ALLOC(c->cnt, c->slots);
   ALLOC(c->bin_count, c->n_cells);
+  ALLOC(c->brick_sys, c->n_bricks);
   ALLOC(c->cellid, c->slots);
   ALLOC(c->inv, c->slots);
   ALLOC(c->cell_count, c->n_cells);
@@ -330,6 +366,8 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   if (hipMemcpy(c->sys_d, c->sys_h.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(c->tile_sys, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->brick_sys, bs.data(), sizeof(int32_t) * bs.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemset(c->bin_count, 0, sizeof(int32_t) * std::max<int64_t>(c->n_cells, 1)) !=
           hipSuccess ||
@@ -406,9 +444,17 @@ static BroadArgs broad_args(vb_ctx *c, int force) {
   a.stride = c->slots;
   a.width = c->width;
   a.bin_count = c->bin_count;
-  a.bins = c->bins;
+  a.bins_bp = c->bins_bp;
+  a.bins_so = c->bins_so;
   a.bin_cap = c->bin_cap;
-  a.cellid = c->cellid;
+  a.brick_sys = c->brick_sys;
+  a.n_bricks = c->n_bricks;
+  a.pmax = c->pmax;
+  a.host_need = force || c->any_no_buffer;
+  if (c->any_fixed)
+    for (int s = 0; s < c->n_sys; ++s)
+      if (c->sys_h[s].skin_mode == VB_FIXED_INTERVAL && c->step % c->sys_h[s].fixed_interval == 0)
+        a.host_need = 1;
   a.inv = c->inv;
   a.flags = c->flags;
   a.go = c->go;
@@ -443,7 +489,8 @@ static vb_status queue_broad_phase(vb_ctx *c) {
     c->force_pending = 1;  // slots moved: every row must be rebuilt
     c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
   }
-  HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending), c->broad_grid, c->stream));
+  HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending), c->broad_grid, c->pairs_grid,
+                               c->stream));
   c->force_pending = 0;
   return VB_OK;
 }
@@ -469,6 +516,7 @@ static vb_status queue_step(vb_ctx *c) {
   a.step = (int32_t)c->step;
   a.first = c->first;
   a.xcd_remap = c->xcd_remap;
+  a.width = c->width;
   HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->stream));
   return VB_OK;
 }

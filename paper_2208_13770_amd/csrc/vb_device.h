@@ -18,6 +18,7 @@ constexpr int STATS_RING = 64;    // steps of per-tile statistics kept before re
 constexpr int MAX_ROW = 128;      // largest Verlet-list row (rows are sorted in LDS)
 constexpr int MAX_BIN = 256;      // largest cell-bin capacity
 constexpr int SCAN_ITEMS = 16;    // cells per thread in the block-level scans
+constexpr int BRICK = 4;          // cells per brick edge: cells are numbered brick by brick
 
 // Position record, 32 B: FP64 centre, FP32 cut-off radius R_C, original index.
 struct alignas(16) PX {
@@ -42,8 +43,10 @@ struct SysDev {
   int64_t o_off;      // first index of the system in the caller's concatenated order
   int32_t n;          // particles
   int32_t n_tiles;    // tiles
+  int64_t b_off;      // first brick of the system in the concatenated brick list
   int32_t nc[3];      // cells per axis
-  int32_t ncell;      // nc[0] * nc[1] * nc[2]
+  int32_t nb[3];      // bricks per axis, ceil(nc / BRICK)
+  int32_t nkeys;      // cell numbers in use: nb[0] * nb[1] * nb[2] * BRICK^3
   double inv_edge[3]; // 1 / cell edge per axis (binning is done in FP64)
   double dt, K, kn, gamma_n, skin_uniform, cap;
   double lo[3], hi[3], g[3];
@@ -85,9 +88,13 @@ struct BroadArgs {
   int64_t stride;
   int32_t width;        // row capacity W
   int32_t *bin_count;   // [cells] particles binned per cell (zeroed by the step kernel)
-  int32_t *bins;        // [cells][bin_cap] local slots
+  float4 *bins_bp;      // [cells][bin_cap] x0 and R_NL of the binned particles
+  int2 *bins_so;        // [cells][bin_cap] (local slot, original index) of the binned particles
   int32_t bin_cap;
-  int32_t *cellid;      // [slots] cell of each slot
+  const int32_t *brick_sys;  // [bricks] system of each brick
+  int64_t n_bricks;
+  int32_t pmax;         // candidates a workgroup can stage in LDS
+  int32_t host_need;    // 1 if some system needs a broad phase regardless of the flags
   int32_t *inv;         // [slots] inv[p_off + orig] = local slot
   const int32_t *flags; // [2][n_sys] validity-violation flags; slot (step & 1) is read
   int32_t *go;          // [n_sys] 1 if the system runs a broad phase at this step
@@ -118,6 +125,7 @@ struct StepArgs {
   int32_t step;
   int32_t first;         // 1: the velocities are the full-step v^0 (no first half kick)
   int32_t xcd_remap;     // 1: give each XCD a contiguous range of tiles
+  int32_t width;         // row capacity W (entries below it are allocated)
 };
 
 // Arguments of the spatial re-sort (counting sort of the slots by cell).

@@ -101,18 +101,49 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n) {
   return x * q + (x < r ? x : r) + k;
 }
 
-// Uniform cell of a position (Alg. 1: uniform decomposition of the domain);
-// positions outside the box fall in the border cells.
-__device__ __forceinline__ int cell_of(const SysDev &S, double x, double y, double z) {
+// Cell number of integer cell coordinates.  Cells are numbered brick by brick
+// (bricks of BRICK^3 cells, x fastest inside a brick and between bricks), so that
+// cells close in space are close in memory.
+__device__ __forceinline__ int cell_key(const SysDev &S, int cx, int cy, int cz) {
+  const int brick = ((cz / BRICK) * S.nb[1] + (cy / BRICK)) * S.nb[0] + (cx / BRICK);
+  return brick * (BRICK * BRICK * BRICK) +
+         ((cz % BRICK) * BRICK + (cy % BRICK)) * BRICK + (cx % BRICK);
+}
+
+// Integer cell coordinates of a position (Alg. 1: uniform decomposition of the
+// domain); positions outside the box fall in the border cells.
+__device__ __forceinline__ void cell_coords(const SysDev &S, double x, double y, double z, int c[3]) {
   const double p[3] = {x, y, z};
-  int c[3];
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     double f = floor((p[ax] - S.lo[ax]) * S.inv_edge[ax]);
     f = fmin(fmax(f, 0.0), (double)(S.nc[ax] - 1));  // NaN -> 0, clamp to the grid
     c[ax] = (int)f;
   }
-  return (c[2] * S.nc[1] + c[1]) * S.nc[0] + c[0];
+}
+
+__device__ __forceinline__ int cell_of(const SysDev &S, double x, double y, double z) {
+  int c[3];
+  cell_coords(S, x, y, z, c);
+  return cell_key(S, c[0], c[1], c[2]);
+}
+
+// Slot of each lane in its cell bin with one atomic per run of equal cells in
+// the wave (the storage is sorted by cell, so neighbouring lanes mostly share a
+// cell).  key < 0 marks a lane that bins nothing; returns the lane's slot.
+__device__ __forceinline__ int wave_bin_slot(int32_t *count, int64_t key) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t prev = __shfl_up(key, 1, WAVE);
+  const bool head = lane == 0 || key != prev;
+  const uint64_t heads = __ballot(head);
+  const uint64_t upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);
+  const int head_lane = 63 - __clzll((long long)(heads & upto));
+  const uint64_t after = heads & ~upto;
+  const int next = after ? __ffsll((long long)after) - 1 : WAVE;
+  int base = 0;
+  if (head && key >= 0) base = atomicAdd(&count[key], next - lane);
+  base = __shfl(base, head_lane, WAVE);
+  return base + (lane - head_lane);
 }
 
 // Does system s run a broad phase at this step?  (Def. autoverlet: when Eq.
@@ -142,8 +173,8 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   // after a broad phase: empty this tile's share of the system's cell bins and
   // consume the flag that asked for it
   if (a.go[s]) {
-    const int chunk = (S.ncell + S.n_tiles - 1) / S.n_tiles;
-    const int c1 = min(S.ncell, (lt + 1) * chunk);
+    const int chunk = (S.nkeys + S.n_tiles - 1) / S.n_tiles;
+    const int c1 = min(S.nkeys, (lt + 1) * chunk);
     for (int c = lt * chunk + (int)threadIdx.x; c < c1; c += TILE) a.bin_count[S.c_off + c] = 0;
     if (lt == 0 && threadIdx.x == 0) a.flags[(a.step & 1) * a.n_sys + s] = 0;
   }
@@ -152,15 +183,20 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   int rowlen = 0, ncon = 0, viol = 0;
   float excess = -INFINITY;
   if (active) {
+    // the particle's records and the first UNROLL row entries are requested
+    // together: entries below the row width are always allocated, and an entry
+    // is used only if it lies below the row length
+    const int32_t *row = a.nbr + k;
+    const int64_t st = a.stride;
+    const int spec = min(UNROLL, a.width);
+    int32_t j[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? row[(int64_t)u * st] : 0;
     const PX me = px[k];
     const PV mv = pv[k];
     const float4 b = a.bp[k];
     rowlen = a.cnt[k];
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    // Row entries in ascending original index; UNROLL gathers in flight at a time,
-    // accumulated strictly in row order.
-    const int32_t *row = a.nbr + k;
-    const int64_t st = a.stride;
     auto contact = [&](const PX &o, int32_t jl) {
       double dx, dy, dz, d, delta;
       if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
@@ -175,20 +211,21 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         ++ncon;
       }
     };
-    int q = 0;
-    for (; q + UNROLL <= rowlen; q += UNROLL) {
-      int32_t j[UNROLL];
+    // Row entries in ascending original index, UNROLL gathers in flight at a
+    // time, accumulated strictly in row order.
+    for (int q = 0; q < rowlen; q += UNROLL) {
+      if (q > 0) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+          if (q + u < rowlen) j[u] = row[(int64_t)(q + u) * st];
+      }
       PX o[UNROLL];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) j[u] = row[(int64_t)(q + u) * st];
+      for (int u = 0; u < UNROLL; ++u)
+        if (q + u < rowlen) o[u] = px[S.p_off + j[u]];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) o[u] = px[S.p_off + j[u]];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) contact(o[u], j[u]);
-    }
-    for (; q < rowlen; ++q) {
-      const int32_t j = row[(int64_t)q * st];
-      contact(px[S.p_off + j], j);
+      for (int u = 0; u < UNROLL; ++u)
+        if (q + u < rowlen) contact(o[u], j[u]);
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
     // in the order -x, +x, -y, +y, -z, +z
@@ -281,103 +318,205 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
 // a broad phase at this step.  Grid-stride over tiles.
 __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
   const int tid = threadIdx.x;
-  int any = 0;
-  for (int s = tid; s < a.n_sys; s += TILE) {
-    const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, a.step, a.force);
-    any |= nd;
-    if (blockIdx.x == 0) {
+  int any = a.host_need;
+  for (int s = tid; s < a.n_sys; s += TILE) any |= a.flags[(a.step & 1) * a.n_sys + s];
+  if (!__syncthreads_or(any)) {  // the same decision in every workgroup
+    if (blockIdx.x == 0)
+      for (int s = tid; s < a.n_sys; s += TILE) {
+        a.go[s] = 0;
+        a.rebuilt_ring[(a.step % STATS_RING) * a.n_sys + s] = 0;
+      }
+    return;
+  }
+  if (blockIdx.x == 0)
+    for (int s = tid; s < a.n_sys; s += TILE) {
+      const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, a.step, a.force);
       a.go[s] = nd;
       a.rebuilt_ring[(a.step % STATS_RING) * a.n_sys + s] = nd;
     }
-  }
-  if (!__syncthreads_or(any)) return;  // the same decision in every workgroup
   for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const int s = a.tile_sys[t];
     const SysDev &S = a.sys[s];
     if (!needs_broad_phase(S, a.flags, a.n_sys, s, a.step, a.force)) continue;
     const int local = (int)(t - S.tile_off) * TILE + tid;
-    if (local >= S.n) continue;
-    const int64_t k = S.p_off + local;
-    const PX x = a.px[k];
-    const PV v = a.pv[k];
-    double skin;
-    if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
-    else if (S.skin_mode == 2) skin = 0.0;
-    else skin = S.skin_uniform;
-    const double r = (double)x.rc + skin;
-    const double rnl = r < S.cap ? r : S.cap;
-    a.bp[k] = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
-    const int c = cell_of(S, x.x, x.y, x.z);
-    a.cellid[k] = c;
-    a.inv[S.p_off + x.orig] = local;
-    const int slot = atomicAdd(&a.bin_count[S.c_off + c], 1);
-    if (slot < a.bin_cap) a.bins[(S.c_off + c) * a.bin_cap + slot] = local;
-    else atomicMax(&a.overflow[1], slot + 1);
+    int64_t key = -1;
+    float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint32_t orig = 0;
+    if (local < S.n) {
+      const int64_t k = S.p_off + local;
+      const PX x = a.px[k];
+      const PV v = a.pv[k];
+      double skin;
+      if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
+      else if (S.skin_mode == 2) skin = 0.0;
+      else skin = S.skin_uniform;
+      const double r = (double)x.rc + skin;
+      const double rnl = r < S.cap ? r : S.cap;
+      b = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
+      a.bp[k] = b;
+      a.inv[S.p_off + x.orig] = local;
+      orig = x.orig;
+      key = S.c_off + cell_of(S, x.x, x.y, x.z);
+    }
+    const int slot = wave_bin_slot(a.bin_count, key);
+    if (key >= 0) {
+      if (slot < a.bin_cap) {
+        a.bins_bp[key * a.bin_cap + slot] = b;
+        a.bins_so[key * a.bin_cap + slot] = make_int2(local, (int)orig);
+      } else {
+        atomicMax(&a.overflow[1], slot + 1);
+      }
+    }
   }
 }
 
-// Alg. 1 on the extended spheres: for each particle, every particle binned in
-// the cells within `ring` cells whose sphere meets this one (|x_i - x_j| <=
-// R_NL,i + R_NL,j, plus eps for FP32 rounding), kept as a row sorted by
-// original index in LDS (column t is thread t's row) and stored as slots.
+// Inserts key into the sorted row of this thread (column tid of s_row) if the
+// row has room; returns the new count (which may exceed W: overflow).
+__device__ __forceinline__ int row_insert(int32_t *s_row, int count, int W, int32_t key) {
+  if (count < W) {
+    int j = count;
+    while (j > 0 && s_row[(j - 1) * TILE + threadIdx.x] > key) {
+      s_row[j * TILE + threadIdx.x] = s_row[(j - 1) * TILE + threadIdx.x];
+      --j;
+    }
+    s_row[j * TILE + threadIdx.x] = key;
+  }
+  return count + 1;
+}
+
+// Alg. 1 on the extended spheres, one workgroup per brick of cells: the bins of
+// the brick and of the cells within `ring` cells around it are staged in LDS,
+// then every particle of the brick is tested against the particles of the cells
+// within `ring` cells of its own (|x_i - x_j| <= R_NL,i + R_NL,j, plus eps for
+// FP32 rounding).  Each row is kept sorted by original index in LDS and stored
+// as slots.  A neighbourhood too full for LDS is read from the bins directly.
 __global__ __launch_bounds__(TILE) void k_pairs(BroadArgs a) {
-  extern __shared__ int32_t s_row[];
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int W = a.width;
+  int32_t *s_row = reinterpret_cast<int32_t *>(lds);                     // [W][TILE]
+  float4 *s_pos = reinterpret_cast<float4 *>(lds + (size_t)W * TILE * 4);  // [pmax]
+  int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax);           // [pmax]
+  __shared__ int s_cnt[8 * 8 * 8];
+  __shared__ int s_off[8 * 8 * 8 + 1];
+  __shared__ int s_home[BRICK * BRICK * BRICK + 1];
   const int tid = threadIdx.x;
   int any = 0;
   for (int s = tid; s < a.n_sys; s += TILE) any |= a.go[s];
   if (!__syncthreads_or(any)) return;
-  const int W = a.width;
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-    const int s = a.tile_sys[t];
+  for (int64_t b = blockIdx.x; b < a.n_bricks; b += gridDim.x) {
+    const int s = a.brick_sys[b];
     if (!a.go[s]) continue;
     const SysDev &S = a.sys[s];
-    const int local = (int)(t - S.tile_off) * TILE + tid;
-    if (local >= S.n) continue;
-    const int64_t k = S.p_off + local;
-    const float4 me = a.bp[k];
-    const int c = a.cellid[k];
-    const int nx = S.nc[0], ny = S.nc[1], nz = S.nc[2];
-    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-    int count = 0;
-    for (int dz = -S.ring; dz <= S.ring; ++dz) {
-      const int bz = cz + dz;
-      if (bz < 0 || bz >= nz) continue;
-      for (int dy = -S.ring; dy <= S.ring; ++dy) {
-        const int by = cy + dy;
-        if (by < 0 || by >= ny) continue;
-        for (int dx = -S.ring; dx <= S.ring; ++dx) {
-          const int bx = cx + dx;
-          if (bx < 0 || bx >= nx) continue;
-          const int64_t cc = S.c_off + (bz * ny + by) * nx + bx;
-          const int nin = min(a.bin_count[cc], a.bin_cap);
-          const int32_t *bin = a.bins + cc * a.bin_cap;
-          for (int i = 0; i < nin; ++i) {
-            const int32_t m = bin[i];
-            if (m == local) continue;
-            const float4 o = a.bp[S.p_off + m];
-            const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
-            const float d = sqrtf(ex * ex + ey * ey + ez * ez);
-            if (d <= me.w + o.w + S.eps) {
-              if (count < W) {
-                const int32_t key = (int32_t)a.px[S.p_off + m].orig;
-                int j = count;
-                while (j > 0 && s_row[(j - 1) * TILE + tid] > key) {
-                  s_row[j * TILE + tid] = s_row[(j - 1) * TILE + tid];
-                  --j;
-                }
-                s_row[j * TILE + tid] = key;
-              }
-              ++count;
-            }
-          }
+    const int r = S.ring, E = BRICK + 2 * r, V = E * E * E;
+    const int lb = (int)(b - S.b_off);
+    const int bx = lb % S.nb[0], by = (lb / S.nb[0]) % S.nb[1], bz = lb / (S.nb[0] * S.nb[1]);
+    const int ox = bx * BRICK - r, oy = by * BRICK - r, oz = bz * BRICK - r;
+    // occupancy of every cell of the neighbourhood box (0 outside the grid)
+    for (int v = tid; v < V; v += TILE) {
+      const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
+      int n = 0;
+      if (cx >= 0 && cy >= 0 && cz >= 0 && cx < S.nc[0] && cy < S.nc[1] && cz < S.nc[2])
+        n = min(a.bin_count[S.c_off + cell_key(S, cx, cy, cz)], a.bin_cap);
+      s_cnt[v] = n;
+    }
+    __syncthreads();
+    {  // exclusive prefix over the box cells, two per thread
+      const int v0 = 2 * tid;
+      const int c0 = v0 < V ? s_cnt[v0] : 0, c1 = v0 + 1 < V ? s_cnt[v0 + 1] : 0;
+      int tot;
+      const int incl = block_inclusive_scan(c0 + c1, &tot);
+      if (v0 < V) s_off[v0] = incl - c0 - c1;
+      if (v0 + 1 < V) s_off[v0 + 1] = incl - c1;
+      if (tid == 0) s_off[V] = tot;
+    }
+    // particles of the brick itself: prefix over its BRICK^3 cells
+    if (tid == 0) {
+      int acc = 0;
+      for (int j = 0; j < BRICK * BRICK * BRICK; ++j) {
+        s_home[j] = acc;
+        const int v = ((r + j / (BRICK * BRICK)) * E + (r + (j / BRICK) % BRICK)) * E + r + j % BRICK;
+        acc += s_cnt[v];
+      }
+      s_home[BRICK * BRICK * BRICK] = acc;
+    }
+    __syncthreads();
+    const bool staged = s_off[V] <= a.pmax;
+    if (staged) {
+      for (int v = tid; v < V; v += TILE) {
+        const int n = s_cnt[v];
+        if (n == 0) continue;
+        const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
+        const int64_t base = (S.c_off + cell_key(S, cx, cy, cz)) * a.bin_cap;
+        const int off = s_off[v];
+        for (int i = 0; i < n; ++i) {
+          s_pos[off + i] = a.bins_bp[base + i];
+          s_key[off + i] = a.bins_so[base + i].y;
         }
       }
+      __syncthreads();
     }
-    const int kept = count < W ? count : W;
-    for (int q = 0; q < kept; ++q)
-      a.nbr[(int64_t)q * a.stride + k] = a.inv[S.p_off + s_row[q * TILE + tid]];
-    a.cnt[k] = kept;
-    if (count > W) atomicMax(&a.overflow[0], count);
+    const int H = s_home[BRICK * BRICK * BRICK];
+    for (int h = tid; h < H; h += TILE) {
+      int lo = 0, hi = BRICK * BRICK * BRICK;  // home cell j: s_home[j] <= h < s_home[j+1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_home[mid] <= h) lo = mid;
+        else hi = mid;
+      }
+      const int j = lo, i = h - s_home[j];
+      const int ix = r + j % BRICK, iy = r + (j / BRICK) % BRICK, iz = r + j / (BRICK * BRICK);
+      const int v = (iz * E + iy) * E + ix;
+      const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
+      const int2 so = a.bins_so[mybase + i];
+      const int me_e = s_off[v] + i;  // this particle's staged entry
+      const float4 me = staged ? s_pos[me_e] : a.bins_bp[mybase + i];
+      const float reach = me.w + S.eps;
+      int count = 0;
+      // inclusion |x_i - x_j| <= R_NL,i + R_NL,j + eps, tested on squares (monotone)
+      auto consider = [&](const float4 &o, int32_t key) {
+        const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
+        const float lim = reach + o.w;
+        if (ex * ex + ey * ey + ez * ez <= lim * lim) count = row_insert(s_row, count, W, key);
+      };
+      if (staged) {
+        // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
+        // row of the neighbourhood are one contiguous range of staged entries
+        for (int dz = -r; dz <= r; ++dz)
+          for (int dy = -r; dy <= r; ++dy) {
+            const int vrow = v + (dz * E + dy) * E;
+            const int e1 = s_off[vrow + r + 1];
+            int e = s_off[vrow - r];
+            for (; e + 4 <= e1; e += 4) {
+              const float4 o0 = s_pos[e], o1 = s_pos[e + 1], o2 = s_pos[e + 2], o3 = s_pos[e + 3];
+              if (e != me_e) consider(o0, s_key[e]);
+              if (e + 1 != me_e) consider(o1, s_key[e + 1]);
+              if (e + 2 != me_e) consider(o2, s_key[e + 2]);
+              if (e + 3 != me_e) consider(o3, s_key[e + 3]);
+            }
+            for (; e < e1; ++e)
+              if (e != me_e) consider(s_pos[e], s_key[e]);
+          }
+      } else {
+        for (int dz = -r; dz <= r; ++dz)
+          for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx) {
+              const int v2 = v + (dz * E + dy) * E + dx;
+              const int n2 = s_cnt[v2];
+              if (n2 == 0) continue;
+              const int64_t base =
+                  (S.c_off + cell_key(S, ox + ix + dx, oy + iy + dy, oz + iz + dz)) * a.bin_cap;
+              for (int e = 0; e < n2; ++e)
+                if (!(v2 == v && e == i)) consider(a.bins_bp[base + e], a.bins_so[base + e].y);
+            }
+      }
+      const int64_t k = S.p_off + so.x;
+      const int kept = count < W ? count : W;
+      for (int q = 0; q < kept; ++q)
+        a.nbr[(int64_t)q * a.stride + k] = a.inv[S.p_off + s_row[q * TILE + tid]];
+      a.cnt[k] = kept;
+      if (count > W) atomicMax(&a.overflow[0], count);
+    }
+    __syncthreads();  // the next brick reuses the LDS
   }
 }
 
@@ -693,17 +832,22 @@ namespace vb {
 
 hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  if (unroll >= 4) hipLaunchKernelGGL(k_step<4>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
-  else if (unroll == 2) hipLaunchKernelGGL(k_step<2>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  if (unroll >= 8) hipLaunchKernelGGL(k_step<8>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  else if (unroll >= 4) hipLaunchKernelGGL(k_step<4>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  else if (unroll >= 2) hipLaunchKernelGGL(k_step<2>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
   else hipLaunchKernelGGL(k_step<1>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_broad_phase(const BroadArgs &a, int grid, hipStream_t st) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin, dim3(grid), dim3(TILE), 0, st, a);
-  const size_t lds = (size_t)TILE * (size_t)a.width * sizeof(int32_t);
-  hipLaunchKernelGGL(k_pairs, dim3(grid), dim3(TILE), lds, st, a);
+size_t pairs_lds_bytes(int width, int pmax) {
+  return (size_t)TILE * (size_t)width * sizeof(int32_t) + (size_t)pmax * (sizeof(float4) + sizeof(int32_t));
+}
+
+hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st) {
+  if (grid_bin <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, a);
+  if (grid_pairs > 0)
+    hipLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(TILE), pairs_lds_bytes(a.width, a.pmax), st, a);
   return hipGetLastError();
 }
 
