@@ -17,7 +17,6 @@ Prints ONE JSON line:
   cpu_baseline the FP64 oracle on a bounded sample of the same workload, one core.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,16 +34,10 @@ HBM_PEAK_GBS = 8000.0
 STEP_BYTES_FIXED = 148
 STEP_BYTES_PER_ENTRY = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_M2_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2208_13770_amd", "csrc", "vb_kernels.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def measured_traffic():
@@ -55,6 +48,7 @@ def measured_traffic():
             t = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2208_13770_amd.profile_summary import kernel_hash
     if t.get("kernel_sha256_16") != kernel_hash():
         return None
     return t.get("bytes_per_launch")
@@ -112,7 +106,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=40,
+    ap.add_argument("--cpu-steps", type=int, default=120,
                     help="steps of the oracle on the same workload (CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")

@@ -71,6 +71,7 @@ struct vb_ctx {
   int64_t n_bricks = 0;
   int32_t pmax = 0;            // candidates k_pairs stages in LDS per workgroup
   size_t lds_limit = 0;        // LDS bytes a workgroup may use on this device
+  size_t lds_cu = 0;           // LDS bytes of one CU
   int pairs_grid = 0;
   int any_no_buffer = 0, any_fixed = 0;
   // counting sort of the storage
@@ -190,13 +191,13 @@ static vb_status alloc_rows(vb_ctx *c, int32_t width) {
   c->nbr = nullptr;
   HIP_OK(c, dalloc(&c->nbr, c->slots * (int64_t)width));
   c->width = width;
-  // LDS of k_pairs: the rows (TILE * width ints) plus up to 2048 staged
-  // candidates of 20 bytes; at least 80 KB (two workgroups per CU), at most the
-  // device's limit, 8 KB kept for the kernel's static arrays
+  // LDS of k_pairs: rows plus staged candidates of 24 bytes.  Half the CU's
+  // LDS per workgroup (two resident per CU), less 5 KB for the kernel's static
+  // arrays, unless wide rows need more; never beyond the device limit.
   const int64_t rows = (int64_t)pairs_lds_bytes(width, 0);
-  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit,
-                                           std::max<int64_t>(80 * 1024, rows + 8192 + 2048 * 20));
-  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows - 8192) / 20));
+  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - 6144,
+                                           std::max<int64_t>((int64_t)c->lds_cu / 2 - 5120, rows + 1024 * 24));
+  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
   return VB_OK;
 }
 
@@ -255,7 +256,8 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   }
   c->n_cu = prop.multiProcessorCount;
   c->lds_limit = prop.sharedMemPerBlock;
-  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 8192) / (TILE * sizeof(int32_t)));
+  c->lds_cu = std::max(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
+  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144) / (PAIRS_T * sizeof(uint16_t)));
   c->n_sys = n_sys;
   c->sys_h.resize(n_sys);
   c->sort_interval = h_params[0].reorder_interval;

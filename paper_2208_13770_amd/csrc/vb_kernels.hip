@@ -41,8 +41,9 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // Inclusive prefix sum over a TILE-thread block; *total receives the block sum.
+template <int NT = TILE>
 __device__ __forceinline__ int block_inclusive_scan(int v, int *total) {
-  __shared__ int wsum[TILE / WAVE];
+  __shared__ int wsum[NT / WAVE];
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
@@ -53,7 +54,7 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *total) {
   __syncthreads();
   int before = 0, all = 0;
 #pragma unroll
-  for (int i = 0; i < TILE / WAVE; ++i) {
+  for (int i = 0; i < NT / WAVE; ++i) {
     if (i < w) before += wsum[i];
     all += wsum[i];
   }
@@ -370,38 +371,107 @@ __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
   }
 }
 
-// Inserts key into the sorted row of this thread (column tid of s_row) if the
-// row has room; returns the new count (which may exceed W: overflow).
-__device__ __forceinline__ int row_insert(int32_t *s_row, int count, int W, int32_t key) {
+// Inserts key into the sorted row of this thread (column threadIdx.x of a
+// [W][ld] LDS array, threadIdx.x < ld) if the row has room; returns the new
+// count (which may exceed W: overflow).  Entries are original indices.
+__device__ __forceinline__ int row_insert(int32_t *s_row, int ld, int count, int W, int32_t key) {
   if (count < W) {
     int j = count;
-    while (j > 0 && s_row[(j - 1) * TILE + threadIdx.x] > key) {
-      s_row[j * TILE + threadIdx.x] = s_row[(j - 1) * TILE + threadIdx.x];
+    while (j > 0 && s_row[(j - 1) * ld + threadIdx.x] > key) {
+      s_row[j * ld + threadIdx.x] = s_row[(j - 1) * ld + threadIdx.x];
       --j;
     }
-    s_row[j * TILE + threadIdx.x] = key;
+    s_row[j * ld + threadIdx.x] = key;
   }
   return count + 1;
+}
+
+// Bitonic sort of N (key, value) pairs held in registers (all indices are
+// compile-time constants after unrolling), ascending by key.
+template <int N>
+__device__ __forceinline__ void bitonic_sort(int32_t (&key)[N], int32_t (&val)[N]) {
+#pragma unroll
+  for (int kk = 2; kk <= N; kk <<= 1)
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & kk) == 0;
+          const int32_t ki = key[i], kl = key[l], vi = val[i], vl = val[l];
+          const bool sw = up ? ki > kl : ki < kl;
+          key[i] = sw ? kl : ki;
+          key[l] = sw ? ki : kl;
+          val[i] = sw ? vl : vi;
+          val[l] = sw ? vi : vl;
+        }
+      }
+}
+
+// Writes this thread's row of n <= N staged-entry indices (column threadIdx.x
+// of a [.][PAIRS_T] LDS array) to the Verlet list as slots, ordered by original
+// index; the sort runs in registers.
+template <int N>
+__device__ __forceinline__ void row_write_sorted(const uint16_t *s_row, const int32_t *s_key,
+                                                 const int32_t *s_slot, int n, int32_t *out,
+                                                 int64_t stride) {
+  int32_t key[N], val[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) val[q] = q < n ? s_row[q * PAIRS_T + threadIdx.x] : 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) key[q] = q < n ? s_key[val[q]] : INT32_MAX;
+  bitonic_sort<N>(key, val);
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (q < n) out[(int64_t)q * stride] = s_slot[val[q]];
+}
+
+// The same for a row of any length up to W: insertion sort in LDS.
+__device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int32_t *s_key,
+                                                     const int32_t *s_slot, int n, int32_t *out,
+                                                     int64_t stride) {
+  for (int i = 1; i < n; ++i) {
+    const int e = s_row[i * PAIRS_T + threadIdx.x];
+    const int32_t key = s_key[e];
+    int j = i;
+    while (j > 0) {
+      const int prev = s_row[(j - 1) * PAIRS_T + threadIdx.x];
+      if (s_key[prev] <= key) break;
+      s_row[j * PAIRS_T + threadIdx.x] = (uint16_t)prev;
+      --j;
+    }
+    s_row[j * PAIRS_T + threadIdx.x] = (uint16_t)e;
+  }
+  for (int q = 0; q < n; ++q) out[(int64_t)q * stride] = s_slot[s_row[q * PAIRS_T + threadIdx.x]];
 }
 
 // Alg. 1 on the extended spheres, one workgroup per brick of cells: the bins of
 // the brick and of the cells within `ring` cells around it are staged in LDS,
 // then every particle of the brick is tested against the particles of the cells
 // within `ring` cells of its own (|x_i - x_j| <= R_NL,i + R_NL,j, plus eps for
-// FP32 rounding).  Each row is kept sorted by original index in LDS and stored
-// as slots.  A neighbourhood too full for LDS is read from the bins directly.
-__global__ __launch_bounds__(TILE) void k_pairs(BroadArgs a) {
+// FP32 rounding, tested on squares).  Matches are appended to the row in LDS;
+// the row is then sorted by original index and stored as slots.  A
+// neighbourhood too full for LDS is read from the bins directly, by half the
+// workgroup.
+__global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int HALF = PAIRS_T / 2;
   const int W = a.width;
-  int32_t *s_row = reinterpret_cast<int32_t *>(lds);                     // [W][TILE]
-  float4 *s_pos = reinterpret_cast<float4 *>(lds + (size_t)W * TILE * 4);  // [pmax]
-  int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax);           // [pmax]
+  float4 *s_pos = reinterpret_cast<float4 *>(lds);                          // [pmax]
+  int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax);             // [pmax]
+  int32_t *s_slot = s_key + a.pmax;                                         // [pmax]
+  unsigned char *rows = reinterpret_cast<unsigned char *>(s_slot + a.pmax);
+  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W][PAIRS_T]
+  int32_t *s_row32 = reinterpret_cast<int32_t *>(rows);                     // [W][HALF]
   __shared__ int s_cnt[8 * 8 * 8];
   __shared__ int s_off[8 * 8 * 8 + 1];
   __shared__ int s_home[BRICK * BRICK * BRICK + 1];
+  static_assert(BRICK * BRICK * BRICK == WAVE, "one lane per cell of a brick");
+  static_assert(2 * PAIRS_T >= 8 * 8 * 8, "two box cells per thread in the prefix");
   const int tid = threadIdx.x;
   int any = 0;
-  for (int s = tid; s < a.n_sys; s += TILE) any |= a.go[s];
+  for (int s = tid; s < a.n_sys; s += PAIRS_T) any |= a.go[s];
   if (!__syncthreads_or(any)) return;
   for (int64_t b = blockIdx.x; b < a.n_bricks; b += gridDim.x) {
     const int s = a.brick_sys[b];
@@ -412,7 +482,7 @@ __global__ __launch_bounds__(TILE) void k_pairs(BroadArgs a) {
     const int bx = lb % S.nb[0], by = (lb / S.nb[0]) % S.nb[1], bz = lb / (S.nb[0] * S.nb[1]);
     const int ox = bx * BRICK - r, oy = by * BRICK - r, oz = bz * BRICK - r;
     // occupancy of every cell of the neighbourhood box (0 outside the grid)
-    for (int v = tid; v < V; v += TILE) {
+    for (int v = tid; v < V; v += PAIRS_T) {
       const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
       int n = 0;
       if (cx >= 0 && cy >= 0 && cz >= 0 && cx < S.nc[0] && cy < S.nc[1] && cz < S.nc[2])
@@ -424,98 +494,139 @@ __global__ __launch_bounds__(TILE) void k_pairs(BroadArgs a) {
       const int v0 = 2 * tid;
       const int c0 = v0 < V ? s_cnt[v0] : 0, c1 = v0 + 1 < V ? s_cnt[v0 + 1] : 0;
       int tot;
-      const int incl = block_inclusive_scan(c0 + c1, &tot);
+      const int incl = block_inclusive_scan<PAIRS_T>(c0 + c1, &tot);
       if (v0 < V) s_off[v0] = incl - c0 - c1;
       if (v0 + 1 < V) s_off[v0 + 1] = incl - c1;
       if (tid == 0) s_off[V] = tot;
     }
-    // particles of the brick itself: prefix over its BRICK^3 cells
-    if (tid == 0) {
-      int acc = 0;
-      for (int j = 0; j < BRICK * BRICK * BRICK; ++j) {
-        s_home[j] = acc;
-        const int v = ((r + j / (BRICK * BRICK)) * E + (r + (j / BRICK) % BRICK)) * E + r + j % BRICK;
-        acc += s_cnt[v];
+    if (tid < WAVE) {  // particles of the brick itself: prefix over its cells, one lane each
+      const int j = tid;
+      const int v = ((r + j / (BRICK * BRICK)) * E + (r + (j / BRICK) % BRICK)) * E + r + j % BRICK;
+      const int c = s_cnt[v];
+      int incl = c;
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int u = __shfl_up(incl, o, WAVE);
+        if (j >= o) incl += u;
       }
-      s_home[BRICK * BRICK * BRICK] = acc;
+      s_home[j] = incl - c;
+      if (j == WAVE - 1) s_home[WAVE] = incl;
     }
     __syncthreads();
     const bool staged = s_off[V] <= a.pmax;
     if (staged) {
-      for (int v = tid; v < V; v += TILE) {
+      for (int v = tid; v < V; v += PAIRS_T) {
         const int n = s_cnt[v];
         if (n == 0) continue;
         const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
         const int64_t base = (S.c_off + cell_key(S, cx, cy, cz)) * a.bin_cap;
         const int off = s_off[v];
-        for (int i = 0; i < n; ++i) {
-          s_pos[off + i] = a.bins_bp[base + i];
-          s_key[off + i] = a.bins_so[base + i].y;
+        for (int i0 = 0; i0 < n; i0 += 8) {  // eight loads in flight per thread
+          float4 bp[8];
+          int2 so[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {  // entries past n re-read entry n - 1
+            const int64_t q = base + min(i0 + u, n - 1);
+            bp[u] = a.bins_bp[q];
+            so[u] = a.bins_so[q];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (i0 + u < n) {
+              s_pos[off + i0 + u] = bp[u];
+              s_key[off + i0 + u] = so[u].y;
+              s_slot[off + i0 + u] = so[u].x;
+            }
         }
       }
       __syncthreads();
     }
-    const int H = s_home[BRICK * BRICK * BRICK];
-    for (int h = tid; h < H; h += TILE) {
-      int lo = 0, hi = BRICK * BRICK * BRICK;  // home cell j: s_home[j] <= h < s_home[j+1]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_home[mid] <= h) lo = mid;
-        else hi = mid;
-      }
-      const int j = lo, i = h - s_home[j];
-      const int ix = r + j % BRICK, iy = r + (j / BRICK) % BRICK, iz = r + j / (BRICK * BRICK);
-      const int v = (iz * E + iy) * E + ix;
-      const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
-      const int2 so = a.bins_so[mybase + i];
-      const int me_e = s_off[v] + i;  // this particle's staged entry
-      const float4 me = staged ? s_pos[me_e] : a.bins_bp[mybase + i];
-      const float reach = me.w + S.eps;
-      int count = 0;
-      // inclusion |x_i - x_j| <= R_NL,i + R_NL,j + eps, tested on squares (monotone)
-      auto consider = [&](const float4 &o, int32_t key) {
-        const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
-        const float lim = reach + o.w;
-        if (ex * ex + ey * ey + ez * ez <= lim * lim) count = row_insert(s_row, count, W, key);
-      };
-      if (staged) {
-        // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
-        // row of the neighbourhood are one contiguous range of staged entries
-        for (int dz = -r; dz <= r; ++dz)
-          for (int dy = -r; dy <= r; ++dy) {
-            const int vrow = v + (dz * E + dy) * E;
-            const int e1 = s_off[vrow + r + 1];
-            int e = s_off[vrow - r];
-            for (; e + 4 <= e1; e += 4) {
-              const float4 o0 = s_pos[e], o1 = s_pos[e + 1], o2 = s_pos[e + 2], o3 = s_pos[e + 3];
-              if (e != me_e) consider(o0, s_key[e]);
-              if (e + 1 != me_e) consider(o1, s_key[e + 1]);
-              if (e + 2 != me_e) consider(o2, s_key[e + 2]);
-              if (e + 3 != me_e) consider(o3, s_key[e + 3]);
+    const int H = s_home[WAVE];
+    const int step_h = staged ? PAIRS_T : HALF;
+    if (staged || tid < HALF)
+      for (int h = tid; h < H; h += step_h) {
+        int lo = 0, hi = WAVE;  // home cell j: s_home[j] <= h < s_home[j+1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_home[mid] <= h) lo = mid;
+          else hi = mid;
+        }
+        const int j = lo, i = h - s_home[j];
+        const int ix = r + j % BRICK, iy = r + (j / BRICK) % BRICK, iz = r + j / (BRICK * BRICK);
+        const int v = (iz * E + iy) * E + ix;
+        int count = 0;
+        int64_t k;
+        if (staged) {
+          const int me_e = s_off[v] + i;  // this particle's staged entry
+          const float4 me = s_pos[me_e];
+          const float reach = me.w + S.eps;
+          k = S.p_off + s_slot[me_e];
+          // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
+          // row of the neighbourhood are one contiguous range of staged entries
+          for (int dz = -r; dz <= r; ++dz)
+            for (int dy = -r; dy <= r; ++dy) {
+              const int vrow = v + (dz * E + dy) * E;
+              const int e1 = s_off[vrow + r + 1];
+              int e = s_off[vrow - r];
+              for (; e + 4 <= e1; e += 4) {
+                const float4 o[4] = {s_pos[e], s_pos[e + 1], s_pos[e + 2], s_pos[e + 3]};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const float ex = me.x - o[u].x, ey = me.y - o[u].y, ez = me.z - o[u].z;
+                  const float lim = reach + o[u].w;
+                  if (e + u != me_e && ex * ex + ey * ey + ez * ez <= lim * lim) {
+                    if (count < W) s_row16[count * PAIRS_T + tid] = (uint16_t)(e + u);
+                    ++count;
+                  }
+                }
+              }
+              for (; e < e1; ++e) {
+                const float4 o = s_pos[e];
+                const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
+                const float lim = reach + o.w;
+                if (e != me_e && ex * ex + ey * ey + ez * ez <= lim * lim) {
+                  if (count < W) s_row16[count * PAIRS_T + tid] = (uint16_t)e;
+                  ++count;
+                }
+              }
             }
-            for (; e < e1; ++e)
-              if (e != me_e) consider(s_pos[e], s_key[e]);
-          }
-      } else {
-        for (int dz = -r; dz <= r; ++dz)
-          for (int dy = -r; dy <= r; ++dy)
-            for (int dx = -r; dx <= r; ++dx) {
-              const int v2 = v + (dz * E + dy) * E + dx;
-              const int n2 = s_cnt[v2];
-              if (n2 == 0) continue;
-              const int64_t base =
-                  (S.c_off + cell_key(S, ox + ix + dx, oy + iy + dy, oz + iz + dz)) * a.bin_cap;
-              for (int e = 0; e < n2; ++e)
-                if (!(v2 == v && e == i)) consider(a.bins_bp[base + e], a.bins_so[base + e].y);
-            }
+          const int kept = count < W ? count : W;
+          int32_t *out = a.nbr + k;
+          if (kept <= 8)
+            row_write_sorted<8>(s_row16, s_key, s_slot, kept, out, a.stride);
+          else if (kept <= 16)
+            row_write_sorted<16>(s_row16, s_key, s_slot, kept, out, a.stride);
+          else
+            row_write_sorted_lds(s_row16, s_key, s_slot, kept, out, a.stride);
+        } else {
+          const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
+          const float4 me = a.bins_bp[mybase + i];
+          const float reach = me.w + S.eps;
+          k = S.p_off + a.bins_so[mybase + i].x;
+          for (int dz = -r; dz <= r; ++dz)
+            for (int dy = -r; dy <= r; ++dy)
+              for (int dx = -r; dx <= r; ++dx) {
+                const int v2 = v + (dz * E + dy) * E + dx;
+                const int n2 = s_cnt[v2];
+                if (n2 == 0) continue;
+                const int64_t base =
+                    (S.c_off + cell_key(S, ox + ix + dx, oy + iy + dy, oz + iz + dz)) * a.bin_cap;
+                for (int e = 0; e < n2; ++e) {
+                  if (v2 == v && e == i) continue;
+                  const float4 o = a.bins_bp[base + e];
+                  const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
+                  const float lim = reach + o.w;
+                  if (ex * ex + ey * ey + ez * ez <= lim * lim)
+                    count = row_insert(s_row32, HALF, count, W, a.bins_so[base + e].y);
+                }
+              }
+          const int kept = count < W ? count : W;
+          for (int q = 0; q < kept; ++q)
+            a.nbr[(int64_t)q * a.stride + k] = a.inv[S.p_off + s_row32[q * HALF + tid]];
+        }
+        a.cnt[k] = count < W ? count : W;
+        if (count > W) atomicMax(&a.overflow[0], count);
       }
-      const int64_t k = S.p_off + so.x;
-      const int kept = count < W ? count : W;
-      for (int q = 0; q < kept; ++q)
-        a.nbr[(int64_t)q * a.stride + k] = a.inv[S.p_off + s_row[q * TILE + tid]];
-      a.cnt[k] = kept;
-      if (count > W) atomicMax(&a.overflow[0], count);
-    }
     __syncthreads();  // the next brick reuses the LDS
   }
 }
@@ -839,15 +950,19 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream
   return hipGetLastError();
 }
 
+// Dynamic LDS of k_pairs: staged candidates (position and R_NL, original index,
+// slot) and the rows (16-bit staged indices, or 32-bit keys for half the
+// threads in the fallback path: the same bytes).
 size_t pairs_lds_bytes(int width, int pmax) {
-  return (size_t)TILE * (size_t)width * sizeof(int32_t) + (size_t)pmax * (sizeof(float4) + sizeof(int32_t));
+  return (size_t)pmax * (sizeof(float4) + 2 * sizeof(int32_t)) +
+         (size_t)PAIRS_T * (size_t)width * sizeof(uint16_t);
 }
 
 hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st) {
   if (grid_bin <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, a);
   if (grid_pairs > 0)
-    hipLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(TILE), pairs_lds_bytes(a.width, a.pmax), st, a);
+    hipLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(PAIRS_T), pairs_lds_bytes(a.width, a.pmax), st, a);
   return hipGetLastError();
 }
 
