@@ -213,20 +213,22 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       }
     };
     // Row entries in ascending original index, UNROLL gathers in flight at a
-    // time, accumulated strictly in row order.
+    // time, accumulated strictly in row order; the next chunk's row entries
+    // are requested while this chunk's gathers are in flight.
     for (int q = 0; q < rowlen; q += UNROLL) {
-      if (q > 0) {
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-          if (q + u < rowlen) j[u] = row[(int64_t)(q + u) * st];
-      }
       PX o[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u)
         if (q + u < rowlen) o[u] = px[S.p_off + j[u]];
+      int32_t jn[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+        jn[u] = q + UNROLL + u < rowlen ? row[(int64_t)(q + UNROLL + u) * st] : 0;
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u)
         if (q + u < rowlen) contact(o[u], j[u]);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) j[u] = jn[u];
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
     // in the order -x, +x, -y, +y, -z, +z
@@ -943,10 +945,11 @@ namespace vb {
 
 hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  if (unroll >= 8) hipLaunchKernelGGL(k_step<8>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
-  else if (unroll >= 4) hipLaunchKernelGGL(k_step<4>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
-  else if (unroll >= 2) hipLaunchKernelGGL(k_step<2>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
-  else hipLaunchKernelGGL(k_step<1>, dim3((unsigned)n_tiles), dim3(TILE), 0, st, a);
+  const dim3 g((unsigned)n_tiles), b(TILE);
+  if (unroll >= 8) hipLaunchKernelGGL(k_step<8>, g, b, 0, st, a);
+  else if (unroll >= 4) hipLaunchKernelGGL(k_step<4>, g, b, 0, st, a);
+  else if (unroll >= 2) hipLaunchKernelGGL(k_step<2>, g, b, 0, st, a);
+  else hipLaunchKernelGGL(k_step<1>, g, b, 0, st, a);
   return hipGetLastError();
 }
 
