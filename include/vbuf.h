@@ -150,9 +150,11 @@ vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs
 vb_status vb_force_rebuild(vb_ctx *ctx);
 
 /* Enable (1) or disable (0) per-kernel HIP-event timing of vb_run, and read the
- * totals since timing was enabled: milliseconds spent in the broad-phase launches
- * of every step (including the storage re-sorts, and the launches that found no
- * system to rebuild), milliseconds in the step-kernel launches, the number of
+ * totals since timing was enabled.  The events take the kernels' own start and
+ * end times (as a kernel-trace profiler reports them, launch gaps excluded):
+ * milliseconds from the start of the binning kernel to the end of the pair
+ * search at every step (including the launches that found no system to rebuild;
+ * storage re-sorts excluded), milliseconds in the step kernel, the number of
  * steps timed and the number of steps at which any system ran a broad phase. */
 vb_status vb_set_timing(vb_ctx *ctx, int32_t on);
 vb_status vb_phase_times(vb_ctx *ctx, double *h_ms_rebuild, double *h_ms_step,

@@ -22,8 +22,10 @@
 #include "vb_device.h"
 
 namespace vb {
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st);
-hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st);
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st, hipEvent_t t0,
+                       hipEvent_t t1);
+hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st,
+                              hipEvent_t t0, hipEvent_t t1);
 size_t pairs_lds_bytes(int width, int pmax);
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 int64_t scan_blocks(int64_t n_cells);
@@ -469,7 +471,8 @@ static BroadArgs broad_args(vb_ctx *c, int force) {
 
 // Work that precedes the step kernel of the current step: the storage re-sort
 // when it is due (then a forced broad phase), and the conditional broad phase.
-static vb_status queue_broad_phase(vb_ctx *c) {
+// t0/t1 (may be null) take the start and end of the broad-phase kernels.
+static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   if (c->next_sort >= 0 && c->step >= c->next_sort && c->n_tiles > 0) {
     SortArgs s;
     s.sys = c->sys_d;
@@ -492,12 +495,12 @@ static vb_status queue_broad_phase(vb_ctx *c) {
     c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
   }
   HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending), c->broad_grid, c->pairs_grid,
-                               c->stream));
+                               c->stream, t0, t1));
   c->force_pending = 0;
   return VB_OK;
 }
 
-static vb_status queue_step(vb_ctx *c) {
+static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   StepArgs a;
   a.sys = c->sys_d;
   a.tile_sys = c->tile_sys;
@@ -519,7 +522,7 @@ static vb_status queue_step(vb_ctx *c) {
   a.first = c->first;
   a.xcd_remap = c->xcd_remap;
   a.width = c->width;
-  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->stream));
+  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->stream, t0, t1));
   return VB_OK;
 }
 
@@ -535,14 +538,14 @@ static vb_status ensure_events(vb_ctx *c, size_t n) {
 // Queues n_steps steps; records go to hist_d[r * n_sys + s].
 static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
   vb_status st;
-  if (c->timing && (st = ensure_events(c, 3 * (size_t)n_steps)) != VB_OK) return st;
+  // with timing on, four events per step take the kernels' own start and end
+  // times: binning start and pair-search end, step-kernel start and end
+  if (c->timing && (st = ensure_events(c, 4 * (size_t)n_steps)) != VB_OK) return st;
   int32_t pending = 0;
   for (int32_t i = 0; i < n_steps; ++i) {
-    if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i], c->stream));
-    if ((st = queue_broad_phase(c)) != VB_OK) return st;
-    if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i + 1], c->stream));
-    if ((st = queue_step(c)) != VB_OK) return st;
-    if (c->timing) HIP_OK(c, hipEventRecord(c->ev[3 * i + 2], c->stream));
+    hipEvent_t *e = c->timing ? &c->ev[4 * (size_t)i] : nullptr;
+    if ((st = queue_broad_phase(c, e ? e[0] : nullptr, e ? e[1] : nullptr)) != VB_OK) return st;
+    if ((st = queue_step(c, e ? e[2] : nullptr, e ? e[3] : nullptr)) != VB_OK) return st;
     c->first = 0;
     c->cur ^= 1;
     c->step += 1;
@@ -620,8 +623,8 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
   if (c->timing) {
     for (int32_t i = 0; i < n_steps; ++i) {
       float a = 0.f, b = 0.f;
-      HIP_OK(c, hipEventElapsedTime(&a, c->ev[3 * i], c->ev[3 * i + 1]));
-      HIP_OK(c, hipEventElapsedTime(&b, c->ev[3 * i + 1], c->ev[3 * i + 2]));
+      HIP_OK(c, hipEventElapsedTime(&a, c->ev[4 * (size_t)i], c->ev[4 * (size_t)i + 1]));
+      HIP_OK(c, hipEventElapsedTime(&b, c->ev[4 * (size_t)i + 2], c->ev[4 * (size_t)i + 3]));
       c->ms_rebuild += a;
       c->ms_step += b;
       int any = 0;

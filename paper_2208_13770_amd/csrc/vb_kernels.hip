@@ -17,6 +17,7 @@
 // so the host never waits on the validity flag.  A counting sort of the particle
 // storage by cell (k_sort_*) runs when the host schedules it, for locality.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "vb_device.h"
 
@@ -92,6 +93,15 @@ __device__ __forceinline__ bool overlap_positive(const PX &a, const PX &b, doubl
   d = sqrt(d2);
   delta = rs - d;
   return delta > 0.0;
+}
+
+// The pre-test of overlap_positive alone: false only where overlap_positive is
+// false too.
+__device__ __forceinline__ bool overlap_candidate(const PX &a, const PX &b) {
+  const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double rs = (double)a.rc + (double)b.rc;
+  return d2 < rs * rs * (1.0 + 1e-12);
 }
 
 // Maps a workgroup index to a tile so that each of the 8 XCDs (which receive
@@ -170,6 +180,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   const int64_t k = S.p_off + local;
   const PX *__restrict__ px = a.px_cur;
   const PV *__restrict__ pv = a.pv_cur;
+  __shared__ int32_t s_cand[MAX_CAND * TILE];  // per-thread lists of contact candidates
 
   // after a broad phase: empty this tile's share of the system's cell bins and
   // consume the flag that asked for it
@@ -198,10 +209,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const float4 b = a.bp[k];
     rowlen = a.cnt[k];
     double fx = 0.0, fy = 0.0, fz = 0.0;
-    auto contact = [&](const PX &o, int32_t jl) {
+    auto contact = [&](const PX &o, const PV &ov) {
       double dx, dy, dz, d, delta;
       if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
-        const PV ov = pv[S.p_off + jl];
         const double inv = 1.0 / d;
         const double nx = dx * inv, ny = dy * inv, nz = dz * inv;
         const double vn = (mv.vx - ov.vx) * nx + (mv.vy - ov.vy) * ny + (mv.vz - ov.vz) * nz;
@@ -212,23 +222,50 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         ++ncon;
       }
     };
-    // Row entries in ascending original index, UNROLL gathers in flight at a
-    // time, accumulated strictly in row order; the next chunk's row entries
-    // are requested while this chunk's gathers are in flight.
-    for (int q = 0; q < rowlen; q += UNROLL) {
-      PX o[UNROLL];
+    // Two passes over each segment of MAX_CAND row entries.  The scan walks the
+    // row (ascending original index) with UNROLL position gathers in flight,
+    // requesting the next chunk's row entries meanwhile, and lists the partners
+    // that pass a squared-distance pre-test in LDS.  The flush then requests the
+    // positions and velocities of the listed partners together and adds the
+    // contact forces in list (= row) order.
+    for (int q0 = 0; q0 < rowlen; q0 += MAX_CAND) {
+      const int q1 = min(rowlen, q0 + MAX_CAND);
+      int nc = 0;
+      for (int q = q0; q < q1; q += UNROLL) {
+        PX o[UNROLL];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u)
-        if (q + u < rowlen) o[u] = px[S.p_off + j[u]];
-      int32_t jn[UNROLL];
+        for (int u = 0; u < UNROLL; ++u)
+          if (q + u < q1) o[u] = px[S.p_off + j[u]];
+        int32_t jn[UNROLL];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u)
-        jn[u] = q + UNROLL + u < rowlen ? row[(int64_t)(q + UNROLL + u) * st] : 0;
+        for (int u = 0; u < UNROLL; ++u)
+          jn[u] = q + UNROLL + u < rowlen ? row[(int64_t)(q + UNROLL + u) * st] : 0;
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u)
-        if (q + u < rowlen) contact(o[u], j[u]);
+        for (int u = 0; u < UNROLL; ++u)
+          if (q + u < q1 && overlap_candidate(me, o[u])) {
+            s_cand[nc * TILE + threadIdx.x] = j[u];
+            ++nc;
+          }
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) j[u] = jn[u];
+        for (int u = 0; u < UNROLL; ++u) j[u] = jn[u];
+      }
+      for (int i0 = 0; i0 < nc; i0 += CONTACT_UNROLL) {
+        int32_t jj[CONTACT_UNROLL];
+        PX o[CONTACT_UNROLL];
+        PV ov[CONTACT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < CONTACT_UNROLL; ++u)
+          jj[u] = i0 + u < nc ? s_cand[(i0 + u) * TILE + threadIdx.x] : 0;
+#pragma unroll
+        for (int u = 0; u < CONTACT_UNROLL; ++u)
+          if (i0 + u < nc) {
+            o[u] = px[S.p_off + jj[u]];
+            ov[u] = pv[S.p_off + jj[u]];
+          }
+#pragma unroll
+        for (int u = 0; u < CONTACT_UNROLL; ++u)
+          if (i0 + u < nc) contact(o[u], ov[u]);
+      }
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
     // in the order -x, +x, -y, +y, -z, +z
@@ -943,13 +980,23 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 // Host entry points of the kernels above (C++ linkage, internal to the library).
 namespace vb {
 
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st) {
+// t0/t1 (both null, or both events): events that take the kernel's own start
+// and end times.
+template <typename K>
+static void launch_timed(K kernel, dim3 g, dim3 b, uint32_t lds, hipStream_t st, hipEvent_t t0,
+                         hipEvent_t t1, const StepArgs &a) {
+  if (t0 || t1) hipExtLaunchKernelGGL(kernel, g, b, lds, st, t0, t1, 0, a);
+  else hipLaunchKernelGGL(kernel, g, b, lds, st, a);
+}
+
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st, hipEvent_t t0,
+                       hipEvent_t t1) {
   if (n_tiles <= 0) return hipSuccess;
   const dim3 g((unsigned)n_tiles), b(TILE);
-  if (unroll >= 8) hipLaunchKernelGGL(k_step<8>, g, b, 0, st, a);
-  else if (unroll >= 4) hipLaunchKernelGGL(k_step<4>, g, b, 0, st, a);
-  else if (unroll >= 2) hipLaunchKernelGGL(k_step<2>, g, b, 0, st, a);
-  else hipLaunchKernelGGL(k_step<1>, g, b, 0, st, a);
+  if (unroll >= 8) launch_timed(k_step<8>, g, b, 0, st, t0, t1, a);
+  else if (unroll >= 4) launch_timed(k_step<4>, g, b, 0, st, t0, t1, a);
+  else if (unroll >= 2) launch_timed(k_step<2>, g, b, 0, st, t0, t1, a);
+  else launch_timed(k_step<1>, g, b, 0, st, t0, t1, a);
   return hipGetLastError();
 }
 
@@ -961,11 +1008,21 @@ size_t pairs_lds_bytes(int width, int pmax) {
          (size_t)PAIRS_T * (size_t)width * sizeof(uint16_t);
 }
 
-hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st) {
+// t0 takes the start of the binning kernel, t1 the end of the pair search
+// (both null, or both events).
+hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st,
+                              hipEvent_t t0, hipEvent_t t1) {
   if (grid_bin <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, a);
-  if (grid_pairs > 0)
-    hipLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(PAIRS_T), pairs_lds_bytes(a.width, a.pmax), st, a);
+  const uint32_t lds = (uint32_t)pairs_lds_bytes(a.width, a.pmax);
+  if (t0 || t1) {
+    hipExtLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, t0, grid_pairs > 0 ? nullptr : t1,
+                          0, a);
+    if (grid_pairs > 0)
+      hipExtLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(PAIRS_T), lds, st, nullptr, t1, 0, a);
+  } else {
+    hipLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, a);
+    if (grid_pairs > 0) hipLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(PAIRS_T), lds, st, a);
+  }
   return hipGetLastError();
 }
 
