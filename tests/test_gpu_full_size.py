@@ -1,0 +1,57 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py times.
+
+The workload is M2: 256x256x64 = 4,194,304 particles, K = 200, default launch
+parameters. The oracle runs the whole system (it is O(N) per step with linked
+cells), so every particle is compared, not just a sample. The tolerance is that
+of the small-size tests: positions within 1e-5 box units and velocities within
+1e-5 v_max, element by element. Contact counts are compared exactly at every
+step. The theorem of Sec. 4.2 (method == broad phase every step) is checked
+bitwise at full size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import gpu_trajectory, host_arrays, say
+
+pytestmark = pytest.mark.gpu
+
+TOL_X = 1e-5
+TOL_V = 1e-5
+STEPS = 100
+
+
+@pytest.fixture(scope="module")
+def m2():
+    return synth.config_systems("M2", seed=0)[0]
+
+
+def test_m2_full_size_parity_with_oracle(m2):
+    s = m2
+    say(f"M2 full size: N={s.n}, {STEPS} steps, GPU then oracle")
+    xg, vg, hg = gpu_trajectory([s], STEPS)
+    x, v, rc, invm = host_arrays([s])
+    xo, vo, ho, _ = oracle.run(s.params, x, v, rc, invm, STEPS)
+    ex = np.abs(xg - xo).max()
+    ev = np.abs(vg - vo).max() / s.meta["v_max"]
+    say(f"  max|dx| = {ex:.3e} box units, max|dv| = {ev:.3e} v_max; "
+        f"contacts at the last step {int(ho['contacts'][-1])}, "
+        f"broad phases GPU {int(hg[0]['rebuilt'].sum())} oracle {int(ho['rebuilt'].sum())}")
+    assert ex <= TOL_X and ev <= TOL_V
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert ho["contacts"][-1] > 10000
+    assert np.allclose(hg[0]["kinetic_energy"], ho["kinetic_energy"], rtol=1e-9, atol=0)
+
+
+def test_m2_full_size_k_invariance_bitwise(m2):
+    """K = 200 against the broad phase at every step: identical bits (Sec. 4.2)."""
+    s = m2
+    steps = 60
+    say(f"M2 full size: K=200 vs no buffer, {steps} steps")
+    xa, va, ha = gpu_trajectory([s], steps)
+    xb, vb_, hb = gpu_trajectory([s], steps, skin_mode=2)
+    say(f"  broad phases: K=200 {int(ha[0]['rebuilt'].sum())}, no buffer {int(hb[0]['rebuilt'].sum())}")
+    assert hb[0]["rebuilt"].all() and ha[0]["rebuilt"].sum() < steps
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb_)
+    assert np.array_equal(ha[0]["contacts"], hb[0]["contacts"])
