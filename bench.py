@@ -1,11 +1,17 @@
 """Benchmark of the local Verlet buffer DEM step on one MI355X.
 
-Workload M2 (the throughput configuration): a 256x256x64 jittered lattice of
-4,194,304 particles with 64 moving boxes and 32 moving balls, sigma 0.1, K = 200,
-500 time steps (Sec. 5.1: the paper's runs are >= 5000 steps on CPU; this is the
-synthetic stand-in).  A "step" is one DEM time step of the method: the
-conditional broad phase (skin, cap, binning, linked-cell pair search) and the
-fused narrow phase + forces + integration + validity test, for every particle.
+Default workload M2 (the throughput configuration): a 256x256x64 jittered
+lattice of 4,194,304 particles with 64 moving boxes and 32 moving balls, sigma
+0.1, K = 200, 500 time steps (Sec. 5.1: the paper's runs are >= 5000 steps on
+CPU; this is the synthetic stand-in).  A "step" is one DEM time step of the
+method: the conditional broad phase (skin, cap, binning, linked-cell pair
+search) and the fused narrow phase + forces + integration + validity test, for
+every particle of every system.
+
+--workload M3 runs the 64 uneven systems as one batch (and, with --sequential,
+also one context per system, one after the other); --workload M5 runs 16
+systems of 16.8M particles (268M in all).  Only the default workload times the
+CPU oracle.
 
 Prints ONE JSON line:
   value       whole-job throughput, Mparticle*step/s, of the method (K = 200) with
@@ -69,15 +75,18 @@ def copy_bandwidth(torch, nbytes=4 << 30):
     return 2 * nbytes / dt / 1e9
 
 
-def run_mode(vb, torch, system, steps, warmup, overrides, timing):
-    params = dict(system.params, **overrides)
-    ctx = vb.vb_create(params, system.n)
+def run_mode(vb, torch, systems, steps, warmup, overrides, timing):
+    """One context over `systems` (a batch when more than one); returns the wall
+    time of `steps` timed steps, the [n_sys, steps] records, phase times and info."""
+    params = [dict(s.params, **overrides) for s in systems]
+    ctx = vb.vb_batch_create(params, [s.n for s in systems])
     try:
-        x, v, rc, invm = vb.state_tensors([system])
+        x, v, rc, invm = vb.state_tensors(systems)
         if warmup > 0:
             vb.vb_set_state(ctx, x, v, rc, invm)
             vb.vb_run(ctx, warmup, want_history=False)
         vb.vb_set_state(ctx, x, v, rc, invm)  # the timed steps start at step 0
+        del x, v, rc, invm
         vb.vb_set_timing(ctx, timing)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -89,10 +98,11 @@ def run_mode(vb, torch, system, steps, warmup, overrides, timing):
     finally:
         vb.vb_destroy(ctx)
         torch.cuda.synchronize()
-    return wall, hist[0], pt, info
+    return wall, hist, pt, info
 
 
 def cpu_baseline(system, steps):
+    """The FP64 oracle on the first `steps` steps of the workload, one thread."""
     import oracle
     pos, vel = system.pos_r.astype(np.float64), system.vel_m.astype(np.float64)
     t0 = time.perf_counter()
@@ -101,16 +111,30 @@ def cpu_baseline(system, steps):
     return system.n * steps / dt / 1e6, dt
 
 
+WORKLOADS = {
+    "M2": "M2: 256x256x64 jittered lattice = {n} particles, 64 boxes + 32 balls moving, "
+          "sigma 0.1, K=200, cap L_C/2, L_C=1.7a, eps=2e-6",
+    "M3": "M3: 64 systems of (s_x/4)x(s_y/4)x16, s in {{256,384,512,768,1024}}, {n} particles "
+          "in all, sigma U[0.02,0.15], K=200, one batch",
+    "M5": "M5: 16 systems of 512x512x64 = {n} particles in all, 256 boxes + 128 balls, "
+          "sigma U[0.05,0.2], K=200, one batch",
+    "M1": "M1: 32x32x16 jittered lattice = {n} particles, 8 boxes + 4 balls, sigma 0.05, K=200",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="M2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=120,
-                    help="steps of the oracle on the same workload (CPU baseline)")
+                    help="steps of the oracle on the same workload (CPU baseline, M2 only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--scale", type=float, default=1.0, help="lattice scale (1 = M2)")
+    ap.add_argument("--sequential", action="store_true",
+                    help="also run every system of the batch in its own context, in turn")
+    ap.add_argument("--scale", type=float, default=1.0, help="lattice scale (1 = full size)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method's "
@@ -124,26 +148,31 @@ def main():
     from paper_2208_13770_amd import report
 
     t0 = time.perf_counter()
-    system = synth.config_systems("M2", seed=0, scale=args.scale)[0]
-    log(f"M2 input: {system.n} particles generated in {time.perf_counter() - t0:.1f}s")
+    systems = synth.config_systems(args.workload, seed=0, scale=args.scale,
+                                   workers=min(16, os.cpu_count() or 1))
+    n = sum(s.n for s in systems)
+    log(f"{args.workload} input: {len(systems)} system(s), {n} particles generated in "
+        f"{time.perf_counter() - t0:.1f}s")
     torch.cuda.init()
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
 
-    wall, hist, pt, info = run_mode(vb, torch, system, args.steps, args.warmup, {}, True)
-    n = system.n
+    wall, hist, pt, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, True)
     value = n * args.steps / wall / 1e6
-    n_rebuild = int(hist["rebuilt"].sum())
+    rebuilt = hist["rebuilt"].astype(bool)            # [n_sys, steps]
+    n_rebuild = int(rebuilt.sum())                     # broad phases over all systems
+    any_rebuild = int(rebuilt.any(axis=0).sum())       # steps at which some system rebuilt
+    pairs = hist["list_pairs"].sum(axis=0)             # per step, all systems
     step_ms = pt["ms_step"] / max(pt["steps"], 1)
-    bytes_per_launch = float(np.mean(STEP_BYTES_FIXED * n
-                                     + 2 * STEP_BYTES_PER_ENTRY * hist["list_pairs"]))
+    bytes_per_launch = float(np.mean(STEP_BYTES_FIXED * n + 2 * STEP_BYTES_PER_ENTRY * pairs))
     achieved = bytes_per_launch / (step_ms * 1e-3) / 1e9
-    log(f"method K=200: {wall * 1e3:.1f} ms for {args.steps} steps, {n_rebuild} broad phases, "
-        f"step kernel {step_ms * 1e3:.1f} us, broad-phase launches {pt['ms_rebuild']:.1f} ms total")
+    log(f"method K=200: {wall * 1e3:.1f} ms for {args.steps} steps, {n_rebuild} broad phases "
+        f"({any_rebuild} steps with one), step kernel {step_ms * 1e3:.1f} us, broad-phase "
+        f"launches {pt['ms_rebuild']:.1f} ms total")
 
     plain = None
     if not args.no_plain:
-        wall_p, hist_p, pt_p, _ = run_mode(vb, torch, system, args.steps, args.warmup,
+        wall_p, hist_p, pt_p, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
                                            {"skin_mode": vb.VB_NO_BUFFER}, True)
         plain = {
             "time_s": wall_p,
@@ -157,15 +186,26 @@ def main():
         log(f"plain (broad phase every step): {wall_p * 1e3:.1f} ms; Eq. impr "
             f"{plain['improvement_pct']:.1f} %")
 
+    sequential = None
+    if args.sequential and len(systems) > 1:
+        t_seq = 0.0
+        for s in systems:
+            w, _, _, _ = run_mode(vb, torch, [s], args.steps, 0, {}, False)
+            t_seq += w
+        sequential = {"time_s": t_seq, "value": n * args.steps / t_seq / 1e6,
+                      "batch_speedup": t_seq / wall}
+        log(f"one context per system, in turn: {t_seq * 1e3:.1f} ms "
+            f"(batch {t_seq / wall:.2f}x faster)")
+
     cpu = None
-    if not args.no_cpu and args.cpu_steps > 0:
-        v_cpu, dt_cpu = cpu_baseline(system, args.cpu_steps)
+    if args.workload == "M2" and not args.no_cpu and args.cpu_steps > 0:
+        v_cpu, dt_cpu = cpu_baseline(systems[0], args.cpu_steps)
         cpu = {"value": v_cpu, "unit": "Mparticle*step/s", "cores": 1, "kind": "oracle",
                "sample": f"M2 workload ({n} particles), first {args.cpu_steps} steps, K=200, "
                          f"FP64 oracle, single thread, {dt_cpu:.1f} s"}
         log(f"cpu oracle: {v_cpu:.3f} Mparticle*step/s ({dt_cpu:.1f} s)")
 
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.workload == "M2" and args.scale == 1.0 else None
     out = {
         "metric": "Mpixel·iter/s (% HBM peak) + time-to-1e-4 residual, plain vs batched+learned",
         "metric_note": "restated for the paper's DEM method: Mparticle*step/s (% HBM peak) of "
@@ -181,19 +221,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"M2: 256x256x64 jittered lattice = {n} particles, 64 boxes + 32 "
-                               "balls moving, sigma 0.1, K=200, cap L_C/2, L_C=1.7a, eps=2e-6",
-                   "particles": n, "steps": args.steps, "K": system.params["K"]},
+        "config": {"workload": WORKLOADS[args.workload].format(n=n),
+                   "particles": n, "systems": len(systems), "steps": args.steps,
+                   "K": systems[0].params["K"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step", "bytes_per_launch": bytes_per_launch,
                      "mean_launch_us": step_ms * 1e3, "copy_bandwidth_gbs": copy_gbs},
         "broad_phases": n_rebuild,
-        "executed_broad_phase_pct": report.executed_fraction(n_rebuild, args.steps),
+        "executed_broad_phase_pct": report.executed_fraction(n_rebuild, args.steps * len(systems)),
         "broad_phase_ms_total": pt["ms_rebuild"],
         "row_width": info["row_width"],
-        "mean_list_pairs": float(hist["list_pairs"].mean()),
+        "mean_list_pairs": float(pairs.mean()),
         "plain": plain,
+        "sequential": sequential,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

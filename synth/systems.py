@@ -191,16 +191,15 @@ CONFIGS = {
 }
 
 
-def config_systems(name: str, seed: int = 0, scale: float = 1.0):
-    """The list of systems of a named workload.  `scale` < 1 shrinks every lattice
-    side (for tests); the shapes of the distributions are unchanged."""
+def _lattice_args(name: str, seed: int, scale: float):
+    """Arguments of lattice_system for every system of a named workload."""
     def sc(v):
         return max(2, int(round(v * scale)))
 
     if name == "M1":
-        return [lattice_system(sc(32), sc(32), sc(16), 8, 4, 0.05, seed)]
+        return [(sc(32), sc(32), sc(16), 8, 4, 0.05, seed)]
     if name == "M2":
-        return [lattice_system(sc(256), sc(256), sc(64), 64, 32, 0.1, seed)]
+        return [(sc(256), sc(256), sc(64), 64, 32, 0.1, seed)]
     if name == "M3":
         rng = np.random.Generator(np.random.PCG64(12345 + seed))
         sides = np.array([256, 384, 512, 768, 1024])
@@ -212,11 +211,27 @@ def config_systems(name: str, seed: int = 0, scale: float = 1.0):
             B = int(round(8 * np.sqrt(nb / 16384.0)))
             D = int(np.ceil(B / 2))
             sigma = float(rng.uniform(0.02, 0.15))
-            out.append(lattice_system(nx, ny, nz, B, D, sigma, 1000 + b + seed))
+            out.append((nx, ny, nz, B, D, sigma, 1000 + b + seed))
         return out
     if name == "M5":
         rng = np.random.Generator(np.random.PCG64(54321 + seed))
-        return [lattice_system(sc(512), sc(512), sc(64), 256, 128,
-                               float(rng.uniform(0.05, 0.2)), 2000 + b + seed)
+        return [(sc(512), sc(512), sc(64), 256, 128, float(rng.uniform(0.05, 0.2)), 2000 + b + seed)
                 for b in range(16)]
     raise KeyError(name)
+
+
+def _make(args):
+    return lattice_system(*args)
+
+
+def config_systems(name: str, seed: int = 0, scale: float = 1.0, workers: int = 1):
+    """The list of systems of a named workload.  `scale` < 1 shrinks every lattice
+    side (for tests); the shapes of the distributions are unchanged.  With
+    workers > 1 the systems are generated in a process pool (same output: every
+    system has its own seed)."""
+    args = _lattice_args(name, seed, scale)
+    if workers <= 1 or len(args) == 1:
+        return [_make(a) for a in args]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(workers, len(args))) as ex:
+        return list(ex.map(_make, args))

@@ -55,3 +55,51 @@ def test_m2_full_size_k_invariance_bitwise(m2):
     assert hb[0]["rebuilt"].all() and ha[0]["rebuilt"].sum() < steps
     assert np.array_equal(xa, xb) and np.array_equal(va, vb_)
     assert np.array_equal(ha[0]["contacts"], hb[0]["contacts"])
+
+
+def _oracle_system(s, steps):
+    x, v, rc, invm = host_arrays([s])
+    return oracle.run(s.params, x, v, rc, invm, steps)
+
+
+def _slices(systems):
+    off = np.cumsum([0] + [s.n for s in systems])
+    return [slice(int(off[i]), int(off[i + 1])) for i in range(len(systems))]
+
+
+def test_m3_batch_parity_with_oracle():
+    """The 64 uneven systems (19.9M particles) as one batch against the oracle,
+    system by system, every particle."""
+    systems = synth.config_systems("M3", seed=0, workers=8)
+    steps = 30
+    say(f"M3: {len(systems)} systems, N={sum(s.n for s in systems)}, {steps} steps")
+    xg, vg, hg = gpu_trajectory(systems, steps)
+    worst_x = worst_v = 0.0
+    for i, (s, sl) in enumerate(zip(systems, _slices(systems))):
+        xo, vo, ho, _ = _oracle_system(s, steps)
+        worst_x = max(worst_x, np.abs(xg[sl] - xo).max())
+        worst_v = max(worst_v, np.abs(vg[sl] - vo).max() / s.meta["v_max"])
+        assert np.array_equal(hg[i]["contacts"], ho["contacts"]), i
+    say(f"  max|dx| = {worst_x:.3e} box units, max|dv| = {worst_v:.3e} v_max over all systems")
+    assert worst_x <= TOL_X and worst_v <= TOL_V
+    assert hg["contacts"][:, -1].sum() > 0
+
+
+def test_m5_sampled_parity_with_oracle():
+    """The largest workload, 16 systems of 512x512x64 (268M particles) in one
+    batch: the first and the last system (16.8M particles each) are compared with
+    the oracle, every particle of them."""
+    systems = synth.config_systems("M5", seed=0, workers=16)
+    steps = 10
+    say(f"M5: {len(systems)} systems, N={sum(s.n for s in systems)}, {steps} steps")
+    xg, vg, hg = gpu_trajectory(systems, steps)
+    sl = _slices(systems)
+    for i in (0, len(systems) - 1):
+        s = systems[i]
+        xo, vo, ho, _ = _oracle_system(s, steps)
+        ex = np.abs(xg[sl[i]] - xo).max()
+        ev = np.abs(vg[sl[i]] - vo).max() / s.meta["v_max"]
+        say(f"  system {i}: max|dx| = {ex:.3e}, max|dv| = {ev:.3e} v_max")
+        assert ex <= TOL_X and ev <= TOL_V
+        assert np.array_equal(hg[i]["contacts"], ho["contacts"])
+    assert hg["rebuilt"][:, 0].all()
