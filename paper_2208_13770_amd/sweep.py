@@ -1,0 +1,114 @@
+"""The paper's K experiment (Sec. 5.4) on the synthetic workloads.
+
+  python -m paper_2208_13770_amd.sweep [--workload M2] [--steps 500] [--out FILE.json]
+
+For every K in the sweep, the same steps run from the same state; the table
+reports the wall time, the time in the broad phase and in the step kernel
+(HIP events on the kernels themselves), the number of broad phases and the
+executed-broad-phase percentage (the quantity of Fig. executed), and Eq. impr
+against the run without Verlet buffer.  Two more skin variants are run: a
+uniform skin equal to the particle radius, and a broad phase at a fixed interval
+with that uniform skin (the scheme Sec. 2 argues against; its results may differ
+from the exact ones, which the table reports).  Every row also says whether its
+final state is bit-identical to the run without buffer (Sec. 4.2).  The last
+part is one line in the layout of Tab. summary: the time without buffer, the
+optimum K, its time and improvement, the time and improvement at K = 200, and
+the overhead of K = 200 over the optimum.
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import report
+
+K_SWEEP = (0.0, 10.0, 20.0, 50.0, 100.0, 200.0, 400.0, 500.0, 1000.0, 5000.0)
+K_DEFAULT = 200.0
+
+
+def summary_row(name, t_without, times_by_k):
+    """Tab. summary columns from the run without buffer and the times per K."""
+    k_opt = min(times_by_k, key=lambda k: (times_by_k[k], k))
+    t_opt = times_by_k[k_opt]
+    t_def = times_by_k[K_DEFAULT]
+    return {"testcase": name, "t_without": t_without, "k_opt": k_opt, "t_opt": t_opt,
+            "impr_opt": report.improvement(t_without, t_opt), "t_default": t_def,
+            "impr_default": report.improvement(t_without, t_def),
+            "overhead": report.overhead_to_optimum(t_def, t_opt)}
+
+
+def run_case(vb, torch, systems, x, v, rc, invm, steps, overrides):
+    params = [dict(s.params, **overrides) for s in systems]
+    ctx = vb.vb_batch_create(params, [s.n for s in systems])
+    try:
+        vb.vb_set_state(ctx, x, v, rc, invm)
+        vb.vb_set_timing(ctx, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = vb.vb_run(ctx, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        pt = vb.vb_phase_times(ctx)
+        xo = torch.empty_like(x)
+        vo = torch.empty_like(v)
+        vb.vb_get_state(ctx, xo, vo)
+    finally:
+        vb.vb_destroy(ctx)
+    return wall, hist, pt, xo, vo
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", default="M2")
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--fixed-interval", type=int, default=50)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+
+    import torch
+    import paper_2208_13770_amd as vb
+    import synth
+
+    systems = synth.config_systems(args.workload, seed=0, scale=args.scale)
+    n = sum(s.n for s in systems)
+    x, v, rc, invm = vb.state_tensors(systems)
+    # one untimed run first: library load, first allocation, caches
+    run_case(vb, torch, systems, x, v, rc, invm, min(args.steps, 20), {})
+
+    cases = [("no buffer", {"skin_mode": vb.VB_NO_BUFFER})]
+    cases += [(f"K={k:g}", {"K": k}) for k in K_SWEEP]
+    cases += [("uniform skin = radius", {"skin_mode": vb.VB_SKIN_UNIFORM}),
+              (f"fixed interval {args.fixed_interval}, skin = radius",
+               {"skin_mode": vb.VB_FIXED_INTERVAL, "fixed_interval": args.fixed_interval})]
+    rows, ref = [], None
+    for name, ov in cases:
+        wall, hist, pt, xo, vo = run_case(vb, torch, systems, x, v, rc, invm, args.steps, ov)
+        if ref is None:
+            ref = (wall, xo, vo, hist)
+        exact = bool(torch.equal(xo, ref[1]) and torch.equal(vo, ref[2]))
+        n_bp = int(hist["rebuilt"].sum())
+        row = {"case": name, "K": ov.get("K"), "time_ms": wall * 1e3,
+               "broad_phase_ms": pt["ms_rebuild"], "step_kernel_ms": pt["ms_step"],
+               "broad_phases": n_bp,
+               "executed_pct": report.executed_fraction(n_bp, args.steps * len(systems)),
+               "impr_pct": report.improvement(ref[0], wall),
+               "identical_to_no_buffer": exact,
+               "contacts_equal": bool(np.array_equal(hist["contacts"], ref[3]["contacts"]))}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    times = {r["K"]: r["time_ms"] / 1e3 for r in rows if r["K"] is not None}
+    out = {"workload": args.workload, "particles": n, "systems": len(systems),
+           "steps": args.steps, "rows": rows,
+           "summary": summary_row(args.workload, ref[0], times)}
+    text = json.dumps(out, indent=1)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+
+
+if __name__ == "__main__":
+    main()

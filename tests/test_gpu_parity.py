@@ -310,3 +310,23 @@ def test_periodic_storage_sort_changes_nothing():
     assert np.array_equal(xa, xb) and np.array_equal(va, vb_)
     assert np.array_equal(ha[0]["contacts"], hb[0]["contacts"])
     assert hb[0]["rebuilt"].sum() >= 150 // 7
+
+
+def test_k_sweep_rows_identical_to_no_buffer(tmp_path):
+    """The K experiment on M1: every K and the uniform skin reproduce the run
+    without buffer bit for bit, K = 0 rebuilds at (nearly) every step, larger K
+    rebuilds less, and the summary row names an optimum."""
+    import json
+    from paper_2208_13770_amd import sweep
+    out = tmp_path / "sweep.json"
+    say("K sweep on M1, 150 steps")
+    sweep.main(["--workload", "M1", "--steps", "150", "--out", str(out)])
+    res = json.loads(out.read_text())
+    rows = {r["case"]: r for r in res["rows"]}
+    for name, r in rows.items():
+        if not name.startswith("fixed"):
+            assert r["identical_to_no_buffer"], name
+    assert rows["no buffer"]["executed_pct"] == 100.0
+    assert rows["K=0"]["executed_pct"] > 90.0
+    assert rows["K=5000"]["broad_phases"] < rows["K=10"]["broad_phases"]
+    assert res["summary"]["k_opt"] in sweep.K_SWEEP
