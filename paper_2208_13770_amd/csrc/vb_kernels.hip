@@ -167,6 +167,25 @@ __device__ __forceinline__ int needs_broad_phase(const SysDev &S, const int32_t 
   return flags[(step & 1) * n_sys + s] != 0;
 }
 
+// Streaming accesses of the step kernel (the particle's own records, its row
+// and its new state) carry the non-temporal hint, so that they do not evict the
+// neighbour records the gathers reuse from L2.
+typedef float vf4_t __attribute__((ext_vector_type(4)));
+typedef double vd2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 nt_load(const float4 *p) {
+  const vf4_t v = __builtin_nontemporal_load(reinterpret_cast<const vf4_t *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int32_t nt_load(const int32_t *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void nt_store32(T *dst, const T &val) {
+  static_assert(sizeof(T) == 32, "32-byte records");
+  const vd2_t *s = reinterpret_cast<const vd2_t *>(&val);
+  vd2_t *d = reinterpret_cast<vd2_t *>(dst);
+  __builtin_nontemporal_store(s[0], d);
+  __builtin_nontemporal_store(s[1], d + 1);
+}
+
 // ------------------------------------------------------------------ k_step
 
 template <int UNROLL>
@@ -203,11 +222,11 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const int spec = min(UNROLL, a.width);
     int32_t j[UNROLL];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? row[(int64_t)u * st] : 0;
+    for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? nt_load(&row[(int64_t)u * st]) : 0;
     const PX me = px[k];
     const PV mv = pv[k];
-    const float4 b = a.bp[k];
-    rowlen = a.cnt[k];
+    const float4 b = nt_load(&a.bp[k]);
+    rowlen = nt_load(&a.cnt[k]);
     double fx = 0.0, fy = 0.0, fz = 0.0;
     auto contact = [&](const PX &o, const PV &ov) {
       double dx, dy, dz, d, delta;
@@ -239,7 +258,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         int32_t jn[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-          jn[u] = q + UNROLL + u < rowlen ? row[(int64_t)(q + UNROLL + u) * st] : 0;
+          jn[u] = q + UNROLL + u < rowlen ? nt_load(&row[(int64_t)(q + UNROLL + u) * st]) : 0;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           if (q + u < q1 && overlap_candidate(me, o[u])) {
@@ -302,8 +321,8 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     outv.vz = vn[2];
     outv.invm = mv.invm;
     outv.pad = 0;
-    a.px_dst[k] = outx;
-    a.pv_dst[k] = outv;
+    nt_store32(&a.px_dst[k], outx);
+    nt_store32(&a.pv_dst[k], outv);
     ke = 0.5 * (vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2]) / im;
     // Eq. update for the next step: straight-line displacement since the last
     // broad phase against the skin left after the cap (R_NL - R_C)
@@ -631,9 +650,10 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
             }
           const int kept = count < W ? count : W;
           int32_t *out = a.nbr + k;
-          if (kept <= 8)
+          // one sort for the whole wave, sized by its longest row (no divergence)
+          if (!__any(kept > 8))
             row_write_sorted<8>(s_row16, s_key, s_slot, kept, out, a.stride);
-          else if (kept <= 16)
+          else if (!__any(kept > 16))
             row_write_sorted<16>(s_row16, s_key, s_slot, kept, out, a.stride);
           else
             row_write_sorted_lds(s_row16, s_key, s_slot, kept, out, a.stride);
