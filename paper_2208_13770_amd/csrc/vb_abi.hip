@@ -41,6 +41,7 @@ hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const
                         int64_t *total, int64_t cap, int32_t *pairs, double *delta,
                         hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_pos32(const PX *px, float4 *pos32, int64_t n, hipStream_t st);
 }  // namespace vb
 
 using namespace vb;
@@ -59,6 +60,7 @@ struct vb_ctx {
   int32_t *tile_sys = nullptr;
   PX *px[2] = {nullptr, nullptr};
   PV *pv[2] = {nullptr, nullptr};
+  float4 *pos32[2] = {nullptr, nullptr};  // FP32 copies of px[0], px[1]
   PX *snap_px = nullptr;
   PV *snap_pv = nullptr;
   float4 *bp = nullptr;
@@ -130,7 +132,8 @@ static hipError_t dalloc(T **p, int64_t count) {
 }
 
 static void free_all(vb_ctx *c) {
-  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->snap_px,
+  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->pos32[0],
+                  c->pos32[1], c->snap_px,
                   c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
                   c->brick_sys, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
@@ -295,6 +298,12 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.skin_mode = p.skin_mode;
     S.fixed_interval = p.fixed_interval < 1 ? 1 : p.fixed_interval;
     S.ring = p.cap_mode == 0 ? 1 : 2;
+    {  // 2^-14 of the largest coordinate a particle can reach (box plus a cell)
+      double bound = 0.0;
+      for (int a = 0; a < 3; ++a)
+        bound = std::max(bound, std::max(std::fabs(p.lo[a]), std::fabs(p.hi[a])) + 2.0 * p.cell_size);
+      S.margin32 = (float)std::ldexp(bound, -14);
+    }
     p_off += (int64_t)S.n_tiles * TILE;
     t_off += S.n_tiles;
     c_off += S.nkeys;
@@ -342,6 +351,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   for (int b = 0; b < 2; ++b) {
     ALLOC(c->px[b], c->slots);
     ALLOC(c->pv[b], c->slots);
+    ALLOC(c->pos32[b], c->slots);
   }
   ALLOC(c->bp, c->slots);
   ALLOC(c->cnt, c->slots);
@@ -416,6 +426,7 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
     HIP_OK(c, launch_set_state(c->sys_h[s], c->px[0], c->pv[0], d_x, d_v, d_rc, d_invm, c->err,
                                c->stream));
   HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
+  HIP_OK(c, launch_pos32(c->px[0], c->pos32[0], c->slots, c->stream));
   vb_status st = reset_control(c);
   if (st != VB_OK) return st;
   int32_t err = 0;
@@ -491,6 +502,7 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.perm0 = c->perm0;
     HIP_OK(c, launch_sort(s, c->stream));
     c->cur ^= 1;
+    HIP_OK(c, launch_pos32(c->px[c->cur], c->pos32[c->cur], c->slots, c->stream));
     c->force_pending = 1;  // slots moved: every row must be rebuilt
     c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
   }
@@ -508,6 +520,8 @@ static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = 
   a.pv_cur = c->pv[c->cur];
   a.px_dst = c->px[c->cur ^ 1];
   a.pv_dst = c->pv[c->cur ^ 1];
+  a.pos32_cur = c->pos32[c->cur];
+  a.pos32_dst = c->pos32[c->cur ^ 1];
   a.bp = c->bp;
   a.cnt = c->cnt;
   a.nbr = c->nbr;
@@ -606,6 +620,7 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots,
                              hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
+    HIP_OK(c, launch_pos32(c->px[0], c->pos32[0], c->slots, c->stream));
     if ((st = reset_control(c)) != VB_OK) return st;
     c->cur = 0;
     c->step = step0;

@@ -58,6 +58,7 @@ struct SysDev {
   int32_t skin_mode;
   int32_t fixed_interval;
   int32_t ring;       // cell rings searched: 1 (cap mode 0) or 2 (cap mode 1)
+  float margin32;     // margin of the step kernel's FP32 contact pre-test
 };
 
 // Per-tile statistics of one step (reduced per system later, in a fixed order).
@@ -116,6 +117,8 @@ struct StepArgs {
   const PV *pv_cur;
   PX *px_dst;
   PV *pv_dst;
+  const float4 *pos32_cur;  // FP32 copies (x, y, z, R_C) of px_cur
+  float4 *pos32_dst;        // written with px_dst
   const float4 *bp;
   const int32_t *cnt;
   const int32_t *nbr;

@@ -95,13 +95,14 @@ __device__ __forceinline__ bool overlap_positive(const PX &a, const PX &b, doubl
   return delta > 0.0;
 }
 
-// The pre-test of overlap_positive alone: false only where overlap_positive is
-// false too.
-__device__ __forceinline__ bool overlap_candidate(const PX &a, const PX &b) {
-  const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-  const double d2 = dx * dx + dy * dy + dz * dz;
-  const double rs = (double)a.rc + (double)b.rc;
-  return d2 < rs * rs * (1.0 + 1e-12);
+// FP32 pre-test of a contact on the FP32 position copies (x, y, z, R_C): true
+// whenever the exact FP64 test can be.  The margin (2^-14 of the largest
+// coordinate) is some 200 times the rounding of the FP32 copies and of this
+// arithmetic, so a pair it rejects is farther apart than R_i + R_j.
+__device__ __forceinline__ bool contact_candidate(const float4 &a, const float4 &b, float margin) {
+  const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  const float reach = a.w + b.w + margin;
+  return dx * dx + dy * dy + dz * dz <= reach * reach;
 }
 
 // Maps a workgroup index to a tile so that each of the 8 XCDs (which receive
@@ -177,6 +178,10 @@ __device__ __forceinline__ float4 nt_load(const float4 *p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ int32_t nt_load(const int32_t *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void nt_store(float4 *p, const float4 &v) {
+  const vf4_t w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<vf4_t *>(p));
+}
 template <typename T>
 __device__ __forceinline__ void nt_store32(T *dst, const T &val) {
   static_assert(sizeof(T) == 32, "32-byte records");
@@ -225,6 +230,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? nt_load(&row[(int64_t)u * st]) : 0;
     const PX me = px[k];
     const PV mv = pv[k];
+    const float4 me32 = make_float4((float)me.x, (float)me.y, (float)me.z, me.rc);
     const float4 b = nt_load(&a.bp[k]);
     rowlen = nt_load(&a.cnt[k]);
     double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -242,26 +248,27 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       }
     };
     // Two passes over each segment of MAX_CAND row entries.  The scan walks the
-    // row (ascending original index) with UNROLL position gathers in flight,
-    // requesting the next chunk's row entries meanwhile, and lists the partners
-    // that pass a squared-distance pre-test in LDS.  The flush then requests the
-    // positions and velocities of the listed partners together and adds the
-    // contact forces in list (= row) order.
+    // row (ascending original index) with UNROLL gathers of the 16-byte FP32
+    // position copies in flight, requesting the next chunk's row entries
+    // meanwhile, and lists in LDS the partners that pass a conservative FP32
+    // pre-test.  The flush then requests the FP64 positions and the velocities
+    // of the listed partners together, runs the exact test and adds the contact
+    // forces in list (= row) order.
     for (int q0 = 0; q0 < rowlen; q0 += MAX_CAND) {
       const int q1 = min(rowlen, q0 + MAX_CAND);
       int nc = 0;
       for (int q = q0; q < q1; q += UNROLL) {
-        PX o[UNROLL];
+        float4 o[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-          if (q + u < q1) o[u] = px[S.p_off + j[u]];
+          if (q + u < q1) o[u] = a.pos32_cur[S.p_off + j[u]];
         int32_t jn[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           jn[u] = q + UNROLL + u < rowlen ? nt_load(&row[(int64_t)(q + UNROLL + u) * st]) : 0;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-          if (q + u < q1 && overlap_candidate(me, o[u])) {
+          if (q + u < q1 && contact_candidate(me32, o[u], S.margin32)) {
             s_cand[nc * TILE + threadIdx.x] = j[u];
             ++nc;
           }
@@ -323,6 +330,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     outv.pad = 0;
     nt_store32(&a.px_dst[k], outx);
     nt_store32(&a.pv_dst[k], outv);
+    nt_store(&a.pos32_dst[k], make_float4((float)xn[0], (float)xn[1], (float)xn[2], me.rc));
     ke = 0.5 * (vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2]) / im;
     // Eq. update for the next step: straight-line displacement since the last
     // broad phase against the skin left after the cap (R_NL - R_C)
@@ -852,6 +860,14 @@ __global__ __launch_bounds__(TILE) void k_stats_reduce(const SysDev *sys, const 
 
 // Load one system from the caller's original order; flags bad values in *err:
 // bit 0 non-finite, bit 1 radius out of range, bit 2 non-positive inverse mass.
+// FP32 copies (x, y, z, R_C) of the positions, for the step kernel's pre-test.
+__global__ void k_pos32(const PX *px, float4 *pos32, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const PX p = px[i];
+  pos32[i] = make_float4((float)p.x, (float)p.y, (float)p.z, p.rc);
+}
+
 __global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const double *v,
                             const float *rc, const float *invm, int32_t *err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1106,6 +1122,12 @@ hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const
   if (pairs)
     hipLaunchKernelGGL(k_pairs_write, dim3(g), dim3(256), 0, st, S, px, cnt, nbr, stride,
                        contacts_only, offsets, cap, pairs, delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_pos32(const PX *px, float4 *pos32, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pos32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, px, pos32, n);
   return hipGetLastError();
 }
 
