@@ -149,6 +149,15 @@ vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs
 /* Request a broad phase at the next step (all systems). */
 vb_status vb_force_rebuild(vb_ctx *ctx);
 
+/* Set the skin factor K of Eq. skin_formulus1 for system sys (every system when
+ * sys < 0).  K is the method's one tuning parameter, with an optimum that
+ * depends on the case (Sec. 5.4); by the theorem of Sec. 4.2 the results do not
+ * depend on it, so it may change between two vb_run calls (a tuner does).  The
+ * new K shapes the skins from the next broad phase on; the current list stays
+ * valid until its own validity test fails.
+ * Errors: VB_EINVAL if K is negative or not finite, or sys >= the system count. */
+vb_status vb_set_K(vb_ctx *ctx, int32_t sys, double K);
+
 /* Enable (1) or disable (0) per-kernel HIP-event timing of vb_run, and read the
  * totals since timing was enabled.  The events take the kernels' own start and
  * end times (as a kernel-trace profiler reports them, launch gaps excluded):

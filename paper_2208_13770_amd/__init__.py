@@ -58,6 +58,7 @@ _SIGNATURES = {
     "vb_get_pairs": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int64)]),
     "vb_force_rebuild": (ctypes.c_int32, [_P]),
+    "vb_set_K": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_double]),
     "vb_set_timing": (ctypes.c_int32, [_P, ctypes.c_int32]),
     "vb_phase_times": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -180,6 +181,11 @@ def vb_get_pairs(ctx, sys, which, pairs=None, delta=None):
 
 def vb_force_rebuild(ctx):
     _check(lib().vb_force_rebuild(ctx), ctx)
+
+
+def vb_set_K(ctx, K, sys=-1):
+    """Skin factor K for system sys (all when sys < 0), from the next broad phase."""
+    _check(lib().vb_set_K(ctx, int(sys), float(K)), ctx)
 
 
 def vb_set_timing(ctx, on):

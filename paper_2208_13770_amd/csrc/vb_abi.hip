@@ -700,6 +700,19 @@ extern "C" vb_status vb_force_rebuild(vb_ctx *c) {
   return VB_OK;
 }
 
+extern "C" vb_status vb_set_K(vb_ctx *c, int32_t sys, double K) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!(K >= 0.0) || !std::isfinite(K)) return fail(c, VB_EINVAL, "K must be finite and >= 0");
+  if (sys >= c->n_sys) return fail(c, VB_EINVAL, "sys out of range");
+  for (int s = 0; s < c->n_sys; ++s)
+    if (sys < 0 || s == sys) c->sys_h[s].K = K;
+  // queued behind the work already on the stream, which still reads the old K
+  HIP_OK(c, hipMemcpyAsync(c->sys_d, c->sys_h.data(), sizeof(SysDev) * c->n_sys,
+                           hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return VB_OK;
+}
+
 extern "C" vb_status vb_set_timing(vb_ctx *c, int32_t on) {
   if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
   c->timing = on != 0;

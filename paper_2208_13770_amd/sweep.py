@@ -9,7 +9,8 @@ executed-broad-phase percentage (the quantity of Fig. executed), and Eq. impr
 against the run without Verlet buffer.  Two more skin variants are run: a
 uniform skin equal to the particle radius, and a broad phase at a fixed interval
 with that uniform skin (the scheme Sec. 2 argues against; its results may differ
-from the exact ones, which the table reports).  Every row also says whether its
+from the exact ones, which the table reports).  A last row lets the runtime
+tuner choose K while the simulation runs (autotune.py).  Every row also says whether its
 final state is bit-identical to the run without buffer (Sec. 4.2).  The last
 part is one line in the layout of Tab. summary: the time without buffer, the
 optimum K, its time and improvement, the time and improvement at K = 200, and
@@ -22,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import report
+from . import autotune, report
 
 K_SWEEP = (0.0, 10.0, 20.0, 50.0, 100.0, 200.0, 400.0, 500.0, 1000.0, 5000.0)
 K_DEFAULT = 200.0
@@ -99,6 +100,34 @@ def main(argv=None):
                "contacts_equal": bool(np.array_equal(hist["contacts"], ref[3]["contacts"]))}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
+    # K chosen at run time, windows of about 1/20 of the run
+    params = [dict(s.params) for s in systems]
+    ctx = vb.vb_batch_create(params, [s.n for s in systems])
+    try:
+        vb.vb_set_state(ctx, x, v, rc, invm)
+        vb.vb_set_timing(ctx, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        windows, k_auto = autotune.tuned_run(vb, ctx, args.steps, K0=K_DEFAULT,
+                                             window=max(10, args.steps // 20),
+                                             exploit=max(40, args.steps // 4))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        pt = vb.vb_phase_times(ctx)
+        xo = torch.empty_like(x)
+        vo = torch.empty_like(v)
+        vb.vb_get_state(ctx, xo, vo)
+    finally:
+        vb.vb_destroy(ctx)
+    row = {"case": "auto (tuned K)", "K": None, "K_final": k_auto, "time_ms": wall * 1e3,
+           "broad_phase_ms": pt["ms_rebuild"], "step_kernel_ms": pt["ms_step"],
+           "broad_phases": int(pt["rebuild_steps"]),
+           "executed_pct": report.executed_fraction(int(pt["rebuild_steps"]), args.steps),
+           "impr_pct": report.improvement(ref[0], wall),
+           "identical_to_no_buffer": bool(torch.equal(xo, ref[1]) and torch.equal(vo, ref[2])),
+           "contacts_equal": None, "windows": [[k, s_, t] for k, s_, t in windows]}
+    rows.append(row)
+    print(json.dumps({k: v_ for k, v_ in row.items() if k != "windows"}), file=sys.stderr, flush=True)
     times = {r["K"]: r["time_ms"] / 1e3 for r in rows if r["K"] is not None}
     out = {"workload": args.workload, "particles": n, "systems": len(systems),
            "steps": args.steps, "rows": rows,

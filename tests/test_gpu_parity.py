@@ -330,3 +330,24 @@ def test_k_sweep_rows_identical_to_no_buffer(tmp_path):
     assert rows["K=0"]["executed_pct"] > 90.0
     assert rows["K=5000"]["broad_phases"] < rows["K=10"]["broad_phases"]
     assert res["summary"]["k_opt"] in sweep.K_SWEEP
+    assert rows["auto (tuned K)"]["identical_to_no_buffer"]
+
+
+def test_changing_K_mid_run_changes_nothing():
+    """vb_set_K between vb_run calls (what the tuner does): bit-identical to the
+    broad phase at every step (Sec. 4.2); invalid K values are refused."""
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=5)[0]
+    say("K changed between calls: 200 -> 10 -> 5000 -> 0 -> 100")
+    xr, vr, hr = gpu_trajectory([s], 160, skin_mode=2)
+    with GpuRun([s]) as g:
+        for K, n in ((200.0, 40), (10.0, 30), (5000.0, 40), (0.0, 20), (100.0, 30)):
+            vb.vb_set_K(g.ctx, K)
+            g.run(n)
+        x, v, _ = g.state()
+        for bad in (-1.0, float("nan"), float("inf")):
+            with pytest.raises(vb.VbError):
+                vb.vb_set_K(g.ctx, bad)
+        with pytest.raises(vb.VbError):
+            vb.vb_set_K(g.ctx, 1.0, sys=3)
+    assert np.array_equal(x, xr) and np.array_equal(v, vr)
