@@ -15,6 +15,9 @@ from .build import LIB, build
 SKIN_LOCAL, SKIN_UNIFORM, NO_BUFFER, FIXED_INTERVAL, NAIVE = 0, 1, 2, 3, 4
 
 
+MAX_PLANES = 4
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("skin_mode", ctypes.c_int32),
@@ -35,6 +38,9 @@ class Params(ctypes.Structure):
         ("kn", ctypes.c_double),
         ("gamma_n", ctypes.c_double),
         ("g", ctypes.c_double * 3),
+        ("n_planes", ctypes.c_int32),
+        ("pad2_", ctypes.c_int32),
+        ("planes", (ctypes.c_double * 5) * MAX_PLANES),
     ]
 
 
@@ -100,6 +106,12 @@ def make_params(p: dict) -> Params:
     for k in ("lo", "hi", "g"):
         v = p.get(k, (0.0, 0.0, 0.0))
         getattr(q, k)[:] = [float(t) for t in v]
+    planes = p.get("planes", ())
+    if len(planes) > MAX_PLANES:
+        raise ValueError(f"at most {MAX_PLANES} planar walls")
+    q.n_planes = len(planes)
+    for w, pl in enumerate(planes):
+        q.planes[w][:] = [float(t) for t in pl]
     return q
 
 

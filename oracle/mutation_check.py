@@ -10,7 +10,7 @@ SRC = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 MUT = [
  ("dashpot sign", "double fm = p->kn * delta - p->gamma_n * vn;", "double fm = p->kn * delta + p->gamma_n * vn;"),
  ("normal flipped", "double nrm[3] = {(xi[0] - xj[0]) / d, (xi[1] - xj[1]) / d, (xi[2] - xj[2]) / d};", "double nrm[3] = {(xj[0] - xi[0]) / d, (xj[1] - xi[1]) / d, (xj[2] - xi[2]) / d};"),
- ("full kick at first half", "vfull[a] = step == 0 ? vh[3 * i + a] : vh[3 * i + a] + hdt * acc;", "vfull[a] = step == 0 ? vh[3 * i + a] : vh[3 * i + a] + p->dt * acc;"),
+ ("full kick at first half", "vfull[a] = (step == 0 && !p->v_in_is_half_step) ? vh[3 * i + a] : vh[3 * i + a] + hdt * acc;", "vfull[a] = (step == 0 && !p->v_in_is_half_step) ? vh[3 * i + a] : vh[3 * i + a] + p->dt * acc;"),
  ("skin without dt", "skin = p->K * norm3(v + 3 * i) * p->dt;", "skin = p->K * norm3(v + 3 * i);"),
  ("no cap", "rnl[i] = r < cap ? r : cap;", "rnl[i] = r;"),
  ("validity >=", "if (disp > skin_test[i]) viol++;", "if (disp >= skin_test[i]) viol++;"),
@@ -26,13 +26,16 @@ MUT = [
  ("broad brute strict", "if (dist3(x + 3 * i, x + 3 * j) <= r[i] + r[j] + eps) pv_push(out, (int32_t)i, (int32_t)j);", "if (dist3(x + 3 * i, x + 3 * j) < r[i] + r[j] + eps) pv_push(out, (int32_t)i, (int32_t)j);"),
  ("skin from speed squared", "static double norm3(const double *a) { return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }", "static double norm3(const double *a) { return (a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }"),
  ("eps dropped in linked cell", "if (dist3(x + 3 * pa, x + 3 * pb) <= r[pa] + r[pb] + eps) {", "if (dist3(x + 3 * pa, x + 3 * pb) <= r[pa] + r[pb]) {"),
+ ("plane force reversed", "        f[0] += fm * pl[0];", "        f[0] -= fm * pl[0];"),
+ ("plane offset sign", "double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] - pl[3];", "double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] + pl[3];"),
+ ("plane height ignored", "if (!(xi[2] > pl[4])) continue;", ";"),
+ ("plane damping sign", "double fm = p->kn * delta - p->gamma_n * vn;\n        f[0] += fm * pl[0];", "double fm = p->kn * delta + p->gamma_n * vn;\n        f[0] += fm * pl[0];"),
 ]
 dst = os.path.join(tempfile.mkdtemp(prefix='orc_mut_'), 'repo')
 results = []
 survivors = 0
 for name, a, b in MUT:
     if os.path.exists(dst): shutil.rmtree(os.path.dirname(dst))
-sys.exit(1 if survivors else 0)
     shutil.copytree(SRC, dst, ignore=shutil.ignore_patterns('.git', '_work', 'gpurun_out', '*.so', '__pycache__'))
     p = os.path.join(dst, 'oracle/orc.c')
     s = open(p).read()

@@ -241,7 +241,8 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
  *     (kn delta - gamma_n ((v_i - v_j) . n)) n.
  * A wall is a half-space boundary of infinite mass at rest; its overlap is
  * R_C - (distance of the centre to the plane) and its normal points into the box.
- * Pair terms are summed in ascending partner index, then the walls -x,+x,-y,+y,-z,+z. */
+ * Pair terms are summed in ascending partner index, then the walls -x,+x,-y,+y,-z,+z,
+ * then the planar walls. */
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
                const double *rc, int64_t ncontacts, const int32_t *contacts, double *F) {
   int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
@@ -293,6 +294,21 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
       double dhi = rc[i] - (p->hi[ax] - xi[ax]); /* wall at hi, normal -e_ax */
       if (dhi > 0.0) f[ax] -= p->kn * dhi - p->gamma_n * (-vi[ax]);
     }
+    /* planar walls: the same law against a half-space of infinite mass at rest,
+     * overlap = R_C minus the signed distance of the centre from the plane */
+    for (int w = 0; w < p->n_planes; w++) {
+      const double *pl = p->planes[w];
+      if (!(xi[2] > pl[4])) continue;
+      double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] - pl[3];
+      double delta = rc[i] - s;
+      if (delta > 0.0) {
+        double vn = vi[0] * pl[0] + vi[1] * pl[1] + vi[2] * pl[2];
+        double fm = p->kn * delta - p->gamma_n * vn;
+        f[0] += fm * pl[0];
+        f[1] += fm * pl[1];
+        f[2] += fm * pl[2];
+      }
+    }
     F[3 * i] = f[0];
     F[3 * i + 1] = f[1];
     F[3 * i + 2] = f[2];
@@ -334,6 +350,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
             int64_t *list_n) {
   if (n < 0 || n_steps < 0 || !(p->dt > 0.0) || !(p->cell_size > 0.0) || p->eps < 0.0) return -1;
   if (p->skin_mode == ORC_FIXED_INTERVAL && p->fixed_interval < 1) return -1;
+  if (p->n_planes < 0 || p->n_planes > ORC_MAX_PLANES) return -1;
   int32_t ring = p->ring > 0 ? p->ring : (p->cap_mode == 0 ? 1 : 2);
   /* the smallest cell edge that keeps Alg. 1 complete for the chosen cap: every
      reach R_NL,i + R_NL,j + eps is at most ring * edge */

@@ -25,6 +25,8 @@
 #define ORC_H
 #include <stdint.h>
 
+#define ORC_MAX_PLANES 4
+
 enum {
   ORC_SKIN_LOCAL = 0,      /* skin_p = K |v_p| dt (the paper's method)              */
   ORC_SKIN_UNIFORM = 1,    /* skin_p = skin_uniform for every particle               */
@@ -48,6 +50,11 @@ typedef struct {
   double lo[3], hi[3];     /* box; a planar wall on each of the six faces                     */
   double kn, gamma_n;      /* normal linear spring-dashpot                                    */
   double g[3];             /* gravity acceleration                                            */
+  int32_t n_planes;        /* planar walls besides the six box faces, 0..ORC_MAX_PLANES      */
+  int32_t pad2_;
+  double planes[ORC_MAX_PLANES][5]; /* (n_x, n_y, n_z, d, z_min): unit normal n into the      */
+                           /*     domain; the wall fills n.x < d and acts on particles whose  */
+                           /*     centre has z > z_min (a finite wall, e.g. a hopper side)     */
 } orc_params;
 
 typedef struct {
@@ -84,8 +91,9 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
                       double *rnl, double *skin_eff);
 
 /* Forces on every particle from a canonical sorted contact list: pair terms summed
- * in ascending partner index, then the six walls, in the order -x,+x,-y,+y,-z,+z.
- * Gravity is not included (it is added as an acceleration by the integrator). */
+ * in ascending partner index, then the six walls, in the order -x,+x,-y,+y,-z,+z,
+ * then the planar walls in index order.  Gravity is not included (it is added as
+ * an acceleration by the integrator). */
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
                const double *rc, int64_t ncontacts, const int32_t *contacts, double *F);
 

@@ -412,3 +412,97 @@ def test_resume_from_half_step_state(orc):
         x1, v1, _, _ = orc.run(p, x, v, rc, invm, 120)
         xb, vb, _, _ = orc.run(dict(p, v_in_is_half_step=1), x1, v1, rc, invm, 80)
         assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
+# ---------------------------------------------------------------- planar walls
+def _incline(theta, n_steps, gamma=0.0):
+    """One sphere resting, at its static overlap, on a frictionless plane through
+    the origin tilted by theta about y, under vertical gravity.  The normal is
+    n = (-sin, 0, cos); the tangent t = (cos, 0, sin) points up the slope."""
+    R, g0, kn = 0.05, 2.0, 1e4
+    n = np.array([-np.sin(theta), 0.0, np.cos(theta)])
+    t = np.array([np.cos(theta), 0.0, np.sin(theta)])
+    delta_star = g0 * np.cos(theta) / kn          # m = 1: kn delta = m g cos(theta)
+    x0 = np.array([[0.0, 0.0, 0.0]]) + (R - delta_star) * n + 0.1 * t
+    x0 = x0 + np.array([[5.0, 5.0, 5.0]])         # plane offset moves with the shift
+    d = float(n @ np.array([5.0, 5.0, 5.0]))
+    p = {"skin_mode": 0, "K": 200.0, "dt": 1e-3, "cell_size": 0.25, "eps": 0.0,
+         "lo": (0, 0, 0), "hi": (10, 10, 10), "kn": kn, "gamma_n": gamma,
+         "g": (0.0, 0.0, -g0), "planes": [(n[0], n[1], n[2], d, -1e9)]}
+    return x0, p, n, t, d, R, delta_star, g0
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.7])
+def test_frictionless_incline(orc, theta):
+    """A normal spring-dashpot plane exerts no tangential force, so the sphere slides
+    down with the constant acceleration g sin(theta) of the textbook incline,
+    exactly the Verlet trajectory x_t(n) = x_t(0) - (n dt)^2 g sin(theta) / 2,
+    while its overlap stays at the static value m g cos(theta) / kn."""
+    steps = 400
+    x0, p, n, t, d, R, delta_star, g0 = _incline(theta, steps)
+    xo, vo, _, _ = orc.run(p, x0, np.zeros((1, 3)), np.array([R]), np.array([1.0]), steps)
+    T = steps * p["dt"]
+    along = float((xo[0] - x0[0]) @ t)
+    assert along == pytest.approx(-0.5 * g0 * np.sin(theta) * T * T, rel=1e-9, abs=1e-13)
+    overlap = R - (float(xo[0] @ n) - d)
+    assert overlap == pytest.approx(delta_star, rel=1e-6, abs=1e-12)
+
+
+def test_floor_plane_equals_box_floor(orc):
+    """A plane z = lo_z with normal +z reproduces the box's own floor bit for bit
+    (a bouncing particle, gravity and damping on): same overlap, same law."""
+    R = 2.0 ** -6
+    x0 = np.array([[0.5, 0.5, 0.2]])
+    v0 = np.array([[0.01, -0.02, -0.3]])
+    base = {"skin_mode": 0, "K": 200.0, "dt": 2.0 ** -12, "cell_size": 2.0 ** -3, "eps": 0.0,
+            "kn": 1e3, "gamma_n": 2.0, "g": (0.0, 0.0, -1.0), "hi": (1, 1, 1)}
+    box = dict(base, lo=(0, 0, 0))
+    plane = dict(base, lo=(0, 0, -4.0), planes=[(0.0, 0.0, 1.0, 0.0, -1e9)])
+    for steps in (500, 3000):
+        xa, va, ha, _ = orc.run(box, x0, v0, np.array([R]), np.array([1.0]), steps)
+        xb, vb, hb, _ = orc.run(plane, x0, v0, np.array([R]), np.array([1.0]), steps)
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert xa[0, 2] < 0.2 and xa[0, 2] > R * 0.5   # it fell and was held up
+
+
+def test_plane_acts_only_above_its_height(orc):
+    """Below z_min the wall is open (an outlet): the particle falls through on the
+    exact constant-gravity trajectory; above it the same wall holds it."""
+    dt = 2.0 ** -10
+    g = np.array([0.0, 0.0, -2.0 ** -2])
+    R = 2.0 ** -6
+    x0 = np.array([[0.5, 0.5, 0.5]])
+    v0 = np.zeros((1, 3))
+    wall = (0.0, 0.0, 1.0, 0.5 - R / 2, 0.75)     # would overlap the particle by R/2
+    p = {"skin_mode": 0, "K": 200.0, "dt": dt, "cell_size": 2.0 ** -3, "eps": 0.0,
+         "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1.0, "gamma_n": 0.0, "g": tuple(g),
+         "planes": [wall]}
+    n = 200
+    xo, vo, _, _ = orc.run(p, x0, v0, np.array([R]), np.array([1.0]), n)
+    assert np.array_equal(xo[0], x0[0] + 0.5 * n * n * dt * dt * g)
+    held = dict(p, kn=1e4, planes=[wall[:4] + (0.25,)])
+    xh, _, _, _ = orc.run(held, x0, v0, np.array([R]), np.array([1.0]), n)
+    assert xh[0, 2] > x0[0, 2]                     # pushed up out of the overlap
+
+
+def test_plane_count_is_bounded(orc):
+    p = {"skin_mode": 0, "K": 1.0, "dt": 1e-3, "cell_size": 0.1, "lo": (0, 0, 0), "hi": (1, 1, 1),
+         "kn": 1.0, "planes": [(0, 0, 1, 0, 0)] * 5}
+    with pytest.raises(ValueError):
+        orc.run(p, np.zeros((1, 3)) + 0.5, np.zeros((1, 3)), np.array([0.01]), np.array([1.0]), 1)
+
+
+def test_mutation_check_patterns_match_the_oracle():
+    """Every mistake oracle/mutation_check.py plants must still have its target
+    text in orc.c (a stale pattern would silently test nothing)."""
+    import ast
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = open(os.path.join(here, "oracle", "mutation_check.py")).read()
+    tree = ast.parse(src)
+    mut = next(node.value for node in tree.body if isinstance(node, ast.Assign)
+               and getattr(node.targets[0], "id", None) == "MUT")
+    orc_c = open(os.path.join(here, "oracle", "orc.c")).read()
+    items = ast.literal_eval(mut)
+    assert len(items) >= 20
+    for name, target, _ in items:
+        assert target in orc_c, name
