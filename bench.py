@@ -10,8 +10,10 @@ every particle of every system.
 
 --workload M3 runs the 64 uneven systems as one batch (and, with --sequential,
 also one context per system, one after the other); --workload M5 runs 16
-systems of 16.8M particles (268M in all).  Only the default workload times the
-CPU oracle.
+systems of 16.8M particles (268M in all); H125, H250, H500 and INCLINE are the
+gravity-driven stand-ins for the paper's hopper and inclined-plane cases
+(planar walls, polydisperse radii).  Only the default workload times the CPU
+oracle.
 
 Prints ONE JSON line:
   value       whole-job throughput, Mparticle*step/s, of the method (K = 200) with
@@ -119,6 +121,14 @@ WORKLOADS = {
     "M5": "M5: 16 systems of 512x512x64 = {n} particles in all, 256 boxes + 128 balls, "
           "sigma U[0.05,0.2], K=200, one batch",
     "M1": "M1: 32x32x16 jittered lattice = {n} particles, 8 boxes + 4 balls, sigma 0.05, K=200",
+    "H125": "hopper stand-in: wedge hopper (walls at 30 deg, outlet 8a) of {n} polydisperse "
+            "particles under gravity, K=200",
+    "H250": "hopper stand-in: wedge hopper (walls at 30 deg, outlet 8a) of {n} polydisperse "
+            "particles under gravity, K=200",
+    "H500": "hopper stand-in: wedge hopper (walls at 30 deg, outlet 8a) of {n} polydisperse "
+            "particles under gravity, K=200",
+    "INCLINE": "inclined-plane stand-in: slab of {n} polydisperse particles, gravity tilted "
+               "25 deg, K=200",
 }
 
 

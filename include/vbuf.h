@@ -62,6 +62,8 @@ typedef int32_t vb_status;
 #define VB_FIXED_INTERVAL 3 /* broad phase every fixed_interval steps with the uniform skin; the  */
                             /* fixed-update practice the automatic scheme replaces (Sec. 1, 4.2)  */
 
+#define VB_MAX_PLANES 4
+
 /* Parameters of one particle system.  Float fields are read as given; positions,
  * velocities and the contact law are evaluated in FP64. */
 typedef struct vb_params {
@@ -81,6 +83,13 @@ typedef struct vb_params {
   int32_t reorder_interval; /* steps between re-sorts of the particle storage by cell, for memory */
                           /* locality (0: only after vb_set_state); the batch uses system 0's     */
   int32_t bin_capacity;   /* initial particles per cell bin (grown on overflow), 1..256; 0 = 16   */
+  int32_t n_planes;       /* planar walls besides the box faces, 0..VB_MAX_PLANES                 */
+  int32_t reserved_;
+  double planes[VB_MAX_PLANES][5]; /* (n_x, n_y, n_z, d, z_min): unit normal n pointing into   */
+                          /* the domain; the wall fills n.x < d and acts, with the contact law   */
+                          /* of the box faces, on particles whose centre has z > z_min (a finite */
+                          /* wall such as a hopper side above its outlet).  Walls act after the  */
+                          /* box faces, in index order.                                           */
 } vb_params;
 
 /* Diagnostics of one time step n of one system (the state x^n whose forces the

@@ -17,6 +17,9 @@ VB_OK, VB_EINVAL, VB_ENOMEM, VB_EDEVICE, VB_ECAPACITY, VB_ENONFINITE = 0, -1, -2
 VB_SKIN_LOCAL, VB_SKIN_UNIFORM, VB_NO_BUFFER, VB_FIXED_INTERVAL = 0, 1, 2, 3
 
 
+VB_MAX_PLANES = 4
+
+
 class vb_params(ctypes.Structure):
     _fields_ = [
         ("skin_mode", ctypes.c_int32),
@@ -35,6 +38,9 @@ class vb_params(ctypes.Structure):
         ("fixed_interval", ctypes.c_int32),
         ("reorder_interval", ctypes.c_int32),
         ("bin_capacity", ctypes.c_int32),
+        ("n_planes", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
+        ("planes", (ctypes.c_double * 5) * VB_MAX_PLANES),
     ]
 
 
@@ -124,6 +130,12 @@ def make_params(p: dict) -> vb_params:
     q.fixed_interval = int(p.get("fixed_interval", 1))
     q.reorder_interval = int(p.get("reorder_interval", 0))
     q.bin_capacity = int(p.get("bin_capacity", 0))
+    planes = p.get("planes", ())
+    if len(planes) > VB_MAX_PLANES:
+        raise ValueError(f"at most {VB_MAX_PLANES} planar walls")
+    q.n_planes = len(planes)
+    for w, pl in enumerate(planes):
+        q.planes[w][:] = [float(t) for t in pl]
     return q
 
 

@@ -166,6 +166,14 @@ static std::string check_params(const vb_params &p, int64_t n) {
   if (p.skin_mode == VB_FIXED_INTERVAL && p.fixed_interval < 1) return "fixed_interval must be >= 1";
   if (p.reorder_interval < 0) return "reorder_interval must be >= 0";
   if (p.bin_capacity < 0 || p.bin_capacity > MAX_BIN) return "bin_capacity must be 0..256";
+  if (p.n_planes < 0 || p.n_planes > VB_MAX_PLANES) return "n_planes must be 0..4";
+  for (int w = 0; w < p.n_planes; ++w) {
+    const double *pl = p.planes[w];
+    for (int c = 0; c < 5; ++c)
+      if (!std::isfinite(pl[c]) && !(c == 4 && pl[c] == -INFINITY)) return "plane values must be finite";
+    const double nn = pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2];
+    if (std::fabs(nn - 1.0) > 1e-9) return "plane normals must have unit length";
+  }
   return "";
 }
 
@@ -298,6 +306,9 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.skin_mode = p.skin_mode;
     S.fixed_interval = p.fixed_interval < 1 ? 1 : p.fixed_interval;
     S.ring = p.cap_mode == 0 ? 1 : 2;
+    S.n_planes = p.n_planes;
+    for (int w = 0; w < p.n_planes; ++w)
+      for (int c = 0; c < 5; ++c) S.planes[w][c] = p.planes[w][c];
     {  // 2^-14 of the largest coordinate a particle can reach (box plus a cell)
       double bound = 0.0;
       for (int a = 0; a < 3; ++a)

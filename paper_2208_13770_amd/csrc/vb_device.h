@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/vbuf.h"
+
 namespace vb {
 
 constexpr int TILE = 256;         // particles per tile = threads per workgroup
@@ -59,6 +61,8 @@ struct SysDev {
   int32_t fixed_interval;
   int32_t ring;       // cell rings searched: 1 (cap mode 0) or 2 (cap mode 1)
   float margin32;     // margin of the step kernel's FP32 contact pre-test
+  int32_t n_planes;   // planar walls besides the box faces
+  double planes[VB_MAX_PLANES][5];  // (n_x, n_y, n_z, d, z_min) as in vb_params
 };
 
 // Per-tile statistics of one step (reduced per system later, in a fixed order).

@@ -294,7 +294,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       }
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
-    // in the order -x, +x, -y, +y, -z, +z
+    // in the order -x, +x, -y, +y, -z, +z, then the planar walls
     const double pos[3] = {me.x, me.y, me.z};
     const double vel[3] = {mv.vx, mv.vy, mv.vz};
     double f[3] = {fx, fy, fz};
@@ -304,6 +304,21 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       if (dlo > 0.0) f[ax] += S.kn * dlo - S.gamma_n * vel[ax];
       const double dhi = (double)me.rc - (S.hi[ax] - pos[ax]);
       if (dhi > 0.0) f[ax] -= S.kn * dhi - S.gamma_n * (-vel[ax]);
+    }
+    // planar walls, in index order: the same law against the half-space n.x < d,
+    // for centres above the wall's height bound
+    for (int w = 0; w < S.n_planes; ++w) {
+      const double *pl = S.planes[w];
+      if (!(pos[2] > pl[4])) continue;
+      const double sd = pl[0] * pos[0] + pl[1] * pos[1] + pl[2] * pos[2] - pl[3];
+      const double dw = (double)me.rc - sd;
+      if (dw > 0.0) {
+        const double vn = vel[0] * pl[0] + vel[1] * pl[1] + vel[2] * pl[2];
+        const double fm = S.kn * dw - S.gamma_n * vn;
+        f[0] += fm * pl[0];
+        f[1] += fm * pl[1];
+        f[2] += fm * pl[2];
+      }
     }
     // velocity Verlet: v^n = v^{n-1/2} + dt/2 a^n, v^{n+1/2} = v^n + dt/2 a^n,
     // x^{n+1} = x^n + dt v^{n+1/2}

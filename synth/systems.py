@@ -191,6 +191,127 @@ CONFIGS = {
 }
 
 
+def _gravity_scale(a: float, dt: float) -> float:
+    """Gravity for the gravity-driven stand-ins: 4e-6 a/dt^2.  Under it a
+    particle's weight compresses one contact by about 0.002 a (kn = 1e5, m = 1),
+    so a column of 50 particles stays within 0.1 a; and a particle falling for
+    500 steps reaches v_max."""
+    return 4e-6 * a / (dt * dt)
+
+
+def hopper_system(n_target: int, seed: int, alpha_deg: float = 30.0, outlet: int = 8,
+                  polydisperse: bool = True, K: float = 200.0, cell_factor: float = 1.7,
+                  eps: float = 2e-6, sigma: float = 0.05) -> ParticleSystem:
+    """A wedge hopper (two planar walls at alpha from the vertical, extruded along
+    y) holding about n_target particles on a jittered lattice, above an outlet
+    slit `outlet` lattice spacings wide and a collection bin; gravity along -z.
+    The walls act only above the outlet height, so particles leave through the
+    slit.  A stand-in for the hopper discharge cases of Sec. 5.2, whose geometry
+    is not published."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tan_a = np.tan(np.radians(alpha_deg))
+    side = max(8, int(round((n_target / 0.6) ** (1.0 / 3.0))))  # hopper top width and depth
+    ny = side
+    bin_h = 10                                                    # collection bin, in sites
+    # fill the wedge layer by layer until n_target sites
+    rows = []
+    k = 0
+    total = 0
+    while total < n_target:
+        half = 0.5 * outlet + k * tan_a                           # half width at layer k (sites)
+        half = min(half, 0.5 * side)
+        w = int(np.floor(2 * half - 1.0))                          # sites clear of both walls
+        if w > 0:
+            rows.append((k, w))
+            total += w * ny
+        k += 1
+        if k > 100000:
+            raise ValueError("hopper does not fill")
+    nz = bin_h + k + 2
+    nx = side + 2
+    a = 1.0 / (max(nx, ny, nz) + 1)
+    xc = 0.5 * (nx + 1) * a
+    z_o = (bin_h + 1) * a
+    pts = []
+    for k, w in rows:
+        xs = xc + (np.arange(w) - 0.5 * (w - 1)) * a
+        ys = (np.arange(ny) + 1.0) * a
+        X, Y = np.meshgrid(xs, ys, indexing="xy")
+        Z = np.full_like(X, z_o + (k + 0.5) * a)
+        pts.append(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+    pos = np.concatenate(pts, axis=0)
+    n = pos.shape[0]
+    pos = pos + rng.uniform(-0.04 * a, 0.04 * a, size=(n, 3))
+    rad = rng.uniform(0.35 * a, 0.45 * a, size=n) if polydisperse else np.full(n, 0.45 * a)
+    mass = (rad / (0.45 * a)) ** 3
+    phys = physics_constants(a)
+    v_max = phys["v_max"]
+    vel = rng.normal(0.0, sigma * v_max, size=(n, 3))
+    g0 = _gravity_scale(a, phys["dt"])
+    ca, sa = np.cos(np.radians(alpha_deg)), np.sin(np.radians(alpha_deg))
+    planes = [  # (n, d, z_min): left wall (normal to +x and up), right wall
+        (_f32(ca), 0.0, _f32(sa), float(np.float32((xc - 0.5 * outlet * a) * ca + z_o * sa)), _f32(z_o)),
+        (_f32(-ca), 0.0, _f32(sa), float(np.float32(-(xc + 0.5 * outlet * a) * ca + z_o * sa)), _f32(z_o)),
+    ]
+    # normals rounded to float32 stay unit length to ~1e-8: renormalise in FP64
+    planes = [tuple(np.array(pl[:3]) / np.linalg.norm(pl[:3])) + pl[3:] for pl in planes]
+    return _system(pos, rad, mass, vel, a, phys, (nx + 1) * a, (ny + 1) * a, (nz + 1) * a,
+                   (0.0, 0.0, -g0), planes, K, cell_factor, eps,
+                   {"kind": "hopper", "alpha_deg": alpha_deg, "outlet_sites": outlet,
+                    "layers": k, "seed": seed, "v_max": v_max, "a": a})
+
+
+def incline_system(n_target: int, seed: int, theta_deg: float = 25.0,
+                   polydisperse: bool = True, K: float = 200.0, cell_factor: float = 1.7,
+                   eps: float = 2e-6, sigma: float = 0.05) -> ParticleSystem:
+    """A slab of about n_target particles resting on a frictionless floor with
+    gravity tilted by theta about y (the frame of an inclined plane), so the
+    slab flows along +x and piles up against the far wall.  A stand-in for the
+    inclined-plane flow case of Sec. 5.2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nz = max(4, int(round((n_target / 8.0) ** (1.0 / 3.0))))
+    nx = 4 * nz
+    ny = max(1, int(round(n_target / (nx * nz))))
+    lx = nx + nx // 2                                          # room to flow
+    a = 1.0 / (max(lx, ny, 3 * nz) + 1)
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    pos = np.stack([i.transpose(2, 1, 0).ravel(), j.transpose(2, 1, 0).ravel(),
+                    k.transpose(2, 1, 0).ravel()], axis=1)
+    pos = (pos + 1.0) * a
+    n = pos.shape[0]
+    pos = pos + rng.uniform(-0.04 * a, 0.04 * a, size=(n, 3))
+    rad = rng.uniform(0.35 * a, 0.45 * a, size=n) if polydisperse else np.full(n, 0.45 * a)
+    mass = (rad / (0.45 * a)) ** 3
+    phys = physics_constants(a)
+    v_max = phys["v_max"]
+    vel = rng.normal(0.0, sigma * v_max, size=(n, 3))
+    g0 = _gravity_scale(a, phys["dt"])
+    th = np.radians(theta_deg)
+    return _system(pos, rad, mass, vel, a, phys, (lx + 1) * a, (ny + 1) * a, (3 * nz + 1) * a,
+                   (g0 * np.sin(th), 0.0, -g0 * np.cos(th)), [], K, cell_factor, eps,
+                   {"kind": "incline", "theta_deg": theta_deg, "seed": seed, "v_max": v_max,
+                    "a": a})
+
+
+def _system(pos, rad, mass, vel, a, phys, hx, hy, hz, gravity, planes, K, cell_factor, eps, meta):
+    n = pos.shape[0]
+    pos_r = np.empty((n, 4), dtype=np.float32)
+    pos_r[:, :3] = pos
+    pos_r[:, 3] = rad
+    vel_m = np.empty((n, 4), dtype=np.float32)
+    vel_m[:, :3] = vel
+    vel_m[:, 3] = 1.0 / mass
+    params = {
+        "skin_mode": 0, "cap_mode": 0, "K": _f32(K), "dt": phys["dt"],
+        "cell_size": _f32(cell_factor * a), "skin_uniform": _f32(0.45 * a), "eps": _f32(eps),
+        "lo": (0.0, 0.0, 0.0), "hi": (_f32(hx), _f32(hy), _f32(hz)),
+        "kn": phys["kn"], "gamma_n": phys["gamma_n"],
+        "g": tuple(_f32(t) for t in gravity), "max_neighbors": 32, "fixed_interval": 1,
+        "planes": [tuple(float(t) for t in pl) for pl in planes],
+    }
+    return ParticleSystem(pos_r, vel_m, params, dict(meta))
+
+
 def _lattice_args(name: str, seed: int, scale: float):
     """Arguments of lattice_system for every system of a named workload."""
     def sc(v):
@@ -229,6 +350,11 @@ def config_systems(name: str, seed: int = 0, scale: float = 1.0, workers: int = 
     side (for tests); the shapes of the distributions are unchanged.  With
     workers > 1 the systems are generated in a process pool (same output: every
     system has its own seed)."""
+    if name in ("H125", "H250", "H500"):
+        n = int(round({"H125": 125000, "H250": 250000, "H500": 500000}[name] * scale ** 3))
+        return [hopper_system(max(n, 200), 3000 + seed)]
+    if name == "INCLINE":
+        return [incline_system(max(int(round(250000 * scale ** 3)), 200), 4000 + seed)]
     args = _lattice_args(name, seed, scale)
     if workers <= 1 or len(args) == 1:
         return [_make(a) for a in args]

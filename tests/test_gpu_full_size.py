@@ -103,3 +103,18 @@ def test_m5_sampled_parity_with_oracle():
         assert ex <= TOL_X and ev <= TOL_V
         assert np.array_equal(hg[i]["contacts"], ho["contacts"])
     assert hg["rebuilt"][:, 0].all()
+
+
+@pytest.mark.parametrize("name,steps", [("H125", 200), ("INCLINE", 150)])
+def test_paper_size_gravity_workloads_parity(name, steps):
+    """The hopper stand-in at the paper's smallest size (125k particles) and the
+    inclined-plane stand-in (250k), every particle against the oracle."""
+    s = synth.config_systems(name, seed=0)[0]
+    say(f"{name}: N={s.n}, {steps} steps")
+    xg, vg, hg = gpu_trajectory([s], steps)
+    xo, vo, ho, _ = _oracle_system(s, steps)
+    ex = np.abs(xg - xo).max()
+    ev = np.abs(vg - vo).max() / s.meta["v_max"]
+    say(f"  max|dx| = {ex:.3e}, max|dv| = {ev:.3e} v_max, contacts at the end {int(ho['contacts'][-1])}")
+    assert ex <= TOL_X and ev <= TOL_V
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])

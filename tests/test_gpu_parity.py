@@ -351,3 +351,36 @@ def test_changing_K_mid_run_changes_nothing():
         with pytest.raises(vb.VbError):
             vb.vb_set_K(g.ctx, 1.0, sys=3)
     assert np.array_equal(x, xr) and np.array_equal(v, vr)
+
+
+@pytest.mark.parametrize("name,scale,steps", [("H125", 0.3, 1500), ("INCLINE", 0.15, 1500)])
+def test_gravity_plane_workloads_parity(name, scale, steps):
+    """Gravity, polydisperse radii and planar walls (hopper sides with an outlet,
+    tilted gravity on a floor): GPU vs oracle, element by element."""
+    s = synth.config_systems(name, scale=scale)[0]
+    say(f"{name} at scale {scale}: N={s.n}, {steps} steps, {len(s.params['planes'])} planes")
+    xg, vg, hg = gpu_trajectory([s], steps)
+    xo, vo, ho, _ = oracle_run(s, steps)
+    assert_close(s, xg, vg, xo, vo, name)
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert ho["contacts"].max() > 20
+    check_schedule(hg[0], ho, name)
+
+
+def test_gravity_plane_k_invariance_bitwise():
+    s = synth.config_systems("H125", scale=0.35)[0]
+    say(f"hopper K-invariance: N={s.n}")
+    ref = gpu_trajectory([s], 300, skin_mode=2)
+    for ov in ({}, {"K": 20.0}, {"K": 2000.0}):
+        x, v, h = gpu_trajectory([s], 300, **ov)
+        assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), ov
+        assert np.array_equal(h[0]["contacts"], ref[2][0]["contacts"])
+
+
+def test_plane_parameters_are_checked():
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", scale=0.25)[0]
+    for planes in ([(0.0, 0.0, 2.0, 0.0, 0.0)], [(float("nan"), 0.0, 1.0, 0.0, 0.0)],
+                   [(0.0, 0.0, 1.0, 0.0, 0.0)] * 5):
+        with pytest.raises((vb.VbError, ValueError)):
+            vb.vb_create(dict(s.params, planes=planes), s.n)
