@@ -41,6 +41,9 @@ class Params(ctypes.Structure):
         ("n_planes", ctypes.c_int32),
         ("pad2_", ctypes.c_int32),
         ("planes", (ctypes.c_double * 5) * MAX_PLANES),
+        ("kt", ctypes.c_double),
+        ("gamma_t", ctypes.c_double),
+        ("mu", ctypes.c_double),
     ]
 
 
@@ -101,7 +104,7 @@ def make_params(p: dict) -> Params:
     q.check_superset = int(p.get("check_superset", 0))
     q.validity_uses_uncapped_skin = int(p.get("validity_uses_uncapped_skin", 0))
     q.v_in_is_half_step = int(p.get("v_in_is_half_step", 0))
-    for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n"):
+    for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n", "kt", "gamma_t", "mu"):
         setattr(q, k, float(p.get(k, 0.0)))
     for k in ("lo", "hi", "g"):
         v = p.get(k, (0.0, 0.0, 0.0))

@@ -29,6 +29,10 @@ MUT = [
  ("plane force reversed", "        f[0] += fm * pl[0];", "        f[0] -= fm * pl[0];"),
  ("plane offset sign", "double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] - pl[3];", "double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] + pl[3];"),
  ("plane height ignored", "if (!(xi[2] > pl[4])) continue;", ";"),
+ ("friction opposes nothing", "          ft[c] = -p->kt * s[c] - p->gamma_t * vt[c];", "          ft[c] = p->kt * s[c] - p->gamma_t * vt[c];"),
+ ("friction uncapped", "        if (ftn > lim) {", "        if (ftn > 1e300) {"),
+ ("friction history dropped", "          for (int c = 0; c < 3; c++) s[c] = old->xi[3 * h + c];", "          ;"),
+ ("friction tangent not projected", "          s[c] = (s[c] - sn * nrm[c]) + vt[c] * p->dt;", "          s[c] = s[c] + vt[c] * p->dt;"),
  ("plane damping sign", "double fm = p->kn * delta - p->gamma_n * vn;\n        f[0] += fm * pl[0];", "double fm = p->kn * delta + p->gamma_n * vn;\n        f[0] += fm * pl[0];"),
 ]
 dst = os.path.join(tempfile.mkdtemp(prefix='orc_mut_'), 'repo')

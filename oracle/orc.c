@@ -235,16 +235,31 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
 
 /* --------------------------------------------------------------------- forces */
 
-/* Linear spring-dashpot in the normal direction (the normal part of the model
- * named in Sec. 5.1).  For a contact (i, j) with overlap delta > 0 and unit
- * normal n = (x_i - x_j)/|x_i - x_j|, the force on i is
- *     (kn delta - gamma_n ((v_i - v_j) . n)) n.
- * A wall is a half-space boundary of infinite mass at rest; its overlap is
- * R_C - (distance of the centre to the plane) and its normal points into the box.
- * Pair terms are summed in ascending partner index, then the walls -x,+x,-y,+y,-z,+z,
- * then the planar walls. */
-int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
-               const double *rc, int64_t ncontacts, const int32_t *contacts, double *F) {
+/* History of the tangential springs: for every particle i, its contacts of
+ * the previous step, partner index ascending, with the spring elongation xi of
+ * the pair as seen from i (i's partner holds the opposite vector). */
+typedef struct {
+  int64_t *off; /* [n + 1] */
+  int32_t *j;
+  double *xi;   /* 3 per entry */
+  int64_t cap;
+} history;
+
+static int friction_on(const orc_params *p) {
+  return p->mu > 0.0 && (p->kt > 0.0 || p->gamma_t > 0.0);
+}
+
+/* The pair and wall forces of one step.  With a history (friction on), each
+ * contact also gets the tangential linear spring-dashpot with a Coulomb limit
+ * (the "LSD" law with static friction named in Sec. 5.1, translational part):
+ *   xi <- xi_old projected on the tangent plane + v_t dt,
+ *   F_t = -kt xi - gamma_t v_t, capped at mu max(F_n, 0), xi then set to the
+ *   elongation of the capped force;
+ * a contact absent from the previous step starts with xi = 0, and the new
+ * history holds exactly this step's contacts. */
+static int forces_core(const orc_params *p, int64_t n, const double *x, const double *v,
+                       const double *rc, int64_t ncontacts, const int32_t *contacts, double *F,
+                       const history *old, history *neu) {
   int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
   int32_t *adj = (int32_t *)malloc((size_t)(2 * ncontacts + 1) * sizeof(int32_t));
   int64_t *fill = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
@@ -273,9 +288,24 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
       adj[b + 1] = key;
     }
   }
+  if (neu) {
+    if (neu->cap < 2 * ncontacts + 1) {
+      int32_t *nj = (int32_t *)realloc(neu->j, (size_t)(2 * ncontacts + 1) * sizeof(int32_t));
+      double *nx = (double *)realloc(neu->xi, (size_t)(2 * ncontacts + 1) * 3 * sizeof(double));
+      if (nj) neu->j = nj;
+      if (nx) neu->xi = nx;
+      if (!nj || !nx) {
+        free(deg), free(adj), free(fill);
+        return -2;
+      }
+      neu->cap = 2 * ncontacts + 1;
+    }
+    memcpy(neu->off, deg, (size_t)(n + 1) * sizeof(int64_t));
+  }
   for (int64_t i = 0; i < n; i++) {
     const double *xi = x + 3 * i, *vi = v + 3 * i;
     double f[3] = {0.0, 0.0, 0.0};
+    int64_t h = old ? old->off[i] : 0, h_end = old ? old->off[i + 1] : 0;
     for (int64_t a = deg[i]; a < deg[i + 1]; a++) {
       int64_t j = adj[a];
       const double *xj = x + 3 * j, *vj = v + 3 * j;
@@ -287,6 +317,36 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
       f[0] += fm * nrm[0];
       f[1] += fm * nrm[1];
       f[2] += fm * nrm[2];
+      if (neu) {
+        double s[3] = {0.0, 0.0, 0.0}; /* the pair's spring from the previous step, if any */
+        while (h < h_end && old->j[h] < j) h++;
+        if (h < h_end && old->j[h] == j)
+          for (int c = 0; c < 3; c++) s[c] = old->xi[3 * h + c];
+        double vt[3], sn = s[0] * nrm[0] + s[1] * nrm[1] + s[2] * nrm[2];
+        for (int c = 0; c < 3; c++) {
+          vt[c] = (vi[c] - vj[c]) - vn * nrm[c];
+          s[c] = (s[c] - sn * nrm[c]) + vt[c] * p->dt;
+        }
+        double ft[3], ftn = 0.0;
+        for (int c = 0; c < 3; c++) {
+          ft[c] = -p->kt * s[c] - p->gamma_t * vt[c];
+          ftn += ft[c] * ft[c];
+        }
+        ftn = sqrt(ftn);
+        double lim = p->mu * (fm > 0.0 ? fm : 0.0);
+        if (ftn > lim) { /* sliding: the force on the cone, the spring that gives it */
+          double sc = lim / ftn;
+          for (int c = 0; c < 3; c++) {
+            ft[c] *= sc;
+            s[c] = p->kt > 0.0 ? -(ft[c] + p->gamma_t * vt[c]) / p->kt : 0.0;
+          }
+        }
+        f[0] += ft[0];
+        f[1] += ft[1];
+        f[2] += ft[2];
+        neu->j[a] = (int32_t)j;
+        for (int c = 0; c < 3; c++) neu->xi[3 * a + c] = s[c];
+      }
     }
     for (int ax = 0; ax < 3; ax++) {
       double dlo = rc[i] - (xi[ax] - p->lo[ax]); /* wall at lo, normal +e_ax */
@@ -315,6 +375,14 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
   }
   free(deg), free(adj), free(fill);
   return 0;
+}
+
+/* Linear spring-dashpot (Sec. 5.1) on the contact pairs (i < j), normal part:
+ * pair terms summed in ascending partner index, then the walls -x,+x,-y,+y,-z,+z,
+ * then the planar walls. */
+int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
+               const double *rc, int64_t ncontacts, const int32_t *contacts, double *F) {
+  return forces_core(p, n, x, v, rc, ncontacts, contacts, F, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------- the run */
@@ -364,7 +432,17 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
   double *skin_eff = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   double *skin_test = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   pairvec L = {0}, C = {0}, B = {0};
+  history H[2] = {{0}, {0}};
+  const int fric = friction_on(p);
+  int cur_h = 0;
   int ret = 0;
+  if (fric) {
+    for (int b = 0; b < 2; b++) H[b].off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!H[0].off || !H[1].off) {
+      ret = -2;
+      goto done;
+    }
+  }
   if (!x || !vh || !x0 || !F || !rnl || !skin_eff || !skin_test) {
     ret = -2;
     goto done;
@@ -420,10 +498,12 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
       goto done;
     }
     /* 4. forces */
-    if (orc_forces(p, n, x, vh, rc, C.n, C.p, F) != 0) {
+    if (forces_core(p, n, x, vh, rc, C.n, C.p, F, fric ? &H[cur_h] : NULL,
+                    fric ? &H[cur_h ^ 1] : NULL) != 0) {
       ret = -2;
       goto done;
     }
+    cur_h ^= 1;
     /* 5. integration */
     double ke = 0.0;
     double hdt = 0.5 * p->dt;
@@ -474,5 +554,6 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
 done:
   free(x), free(vh), free(x0), free(F), free(rnl), free(skin_eff), free(skin_test);
   free(L.p), free(C.p), free(B.p);
+  for (int b = 0; b < 2; b++) free(H[b].off), free(H[b].j), free(H[b].xi);
   return ret;
 }

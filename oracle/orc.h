@@ -55,6 +55,8 @@ typedef struct {
   double planes[ORC_MAX_PLANES][5]; /* (n_x, n_y, n_z, d, z_min): unit normal n into the      */
                            /*     domain; the wall fills n.x < d and acts on particles whose  */
                            /*     centre has z > z_min (a finite wall, e.g. a hopper side)     */
+  double kt, gamma_t, mu;  /* tangential spring, tangential dashpot, Coulomb coefficient of   */
+                           /*     particle-particle friction; all 0 = frictionless            */
 } orc_params;
 
 typedef struct {
@@ -93,7 +95,8 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
 /* Forces on every particle from a canonical sorted contact list: pair terms summed
  * in ascending partner index, then the six walls, in the order -x,+x,-y,+y,-z,+z,
  * then the planar walls in index order.  Gravity is not included (it is added as
- * an acceleration by the integrator). */
+ * an acceleration by the integrator).  Normal forces only: the tangential
+ * (friction) term needs the contact history that orc_run keeps. */
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
                const double *rc, int64_t ncontacts, const int32_t *contacts, double *F);
 

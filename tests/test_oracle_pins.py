@@ -506,3 +506,89 @@ def test_mutation_check_patterns_match_the_oracle():
     assert len(items) >= 20
     for name, target, _ in items:
         assert target in orc_c, name
+
+
+# ---------------------------------------------------------------- friction (f2)
+def _collide(u_n, u_t, p_extra, R=2.0 ** -6, k=1e6):
+    """Two equal unit-mass spheres touching at the start of a collision: relative
+    normal velocity u_n (approaching along x), relative tangential velocity u_t
+    (along y); normal and tangential springs of stiffness k, no dashpots.  The
+    contact lasts pi / sqrt(2 k) (about 290 steps at dt = 2^-17)."""
+    x = np.array([[0.5, 0.5, 0.5], [0.5 + 2 * R - 1e-9, 0.5, 0.5]])
+    v = np.array([[0.5 * u_n, 0.5 * u_t, 0.0], [-0.5 * u_n, -0.5 * u_t, 0.0]])
+    p = {"skin_mode": 0, "K": 200.0, "dt": 2.0 ** -17, "cell_size": 2.0 ** -3, "eps": 0.0,
+         "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": k, "gamma_n": 0.0, "g": (0, 0, 0),
+         "v_in_is_half_step": 1, "kt": k, "gamma_t": 0.0}
+    p.update(p_extra)
+    return x, v, np.full(2, R), np.ones(2), p
+
+
+def test_friction_off_is_the_frictionless_law(orc):
+    x, v, rc, invm, p = _collide(0.2, 0.1, {"mu": 0.0})
+    a = orc.run(p, x, v, rc, invm, 300)
+    for extra in ({"kt": 1e6, "gamma_t": 1.0, "mu": 0.0}, {"kt": 0.0, "gamma_t": 0.0, "mu": 0.5}):
+        b = orc.run(dict(p, **extra), x, v, rc, invm, 300)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    c = orc.run(dict(p, mu=0.5), x, v, rc, invm, 300)
+    assert not np.array_equal(a[1], c[1])                 # and friction on does act
+
+
+def test_sliding_collision_transfers_mu_times_the_normal_impulse(orc):
+    """While a contact slides, |F_t| = mu F_n at every step, so over a collision
+    that slides throughout the tangential impulse is mu times the normal one
+    (Coulomb's law): |du_t| = mu |du_n| = 2 mu u_n for the elastic normal
+    rebound, and the sliding is slowed, never reversed."""
+    mu, u_n, u_t = 0.3, 0.002, 0.003
+    x, v, rc, invm, p = _collide(u_n, u_t, {"mu": mu})
+    xo, vo, h, _ = orc.run(p, x, v, rc, invm, 400)
+    assert h["contacts"][0] == 1 and h["contacts"][-1] == 0
+    du = (vo[0] - vo[1]) - (v[0] - v[1])
+    assert du[1] < 0 and (vo[0] - vo[1])[1] > 0
+    # the normal turns by ~2e-4 rad while the spheres slide past each other,
+    # which moves the ratio by ~u t_c / R (3.5e-4 here)
+    assert abs(du[1]) / abs(du[0]) == pytest.approx(mu, rel=1e-3)
+    assert abs(du[0]) == pytest.approx(2 * u_n, rel=1e-3)
+
+
+def test_sticking_contact_is_an_elastic_tangential_rebound(orc):
+    """An unbounded Coulomb limit (the contact sticks) and kt = kn: the tangential
+    spring completes half a period while the normal one does, so the relative
+    tangential velocity comes back reversed and the kinetic energy is the same
+    (an elastic tangential rebound), to the integrator's error."""
+    u_n, u_t = 0.2, 0.01
+    x, v, rc, invm, p = _collide(u_n, u_t, {"mu": 1e30})
+    _, vo, h, _ = orc.run(p, x, v, rc, invm, 400)
+    assert h["contacts"][-1] == 0
+    rel = vo[0] - vo[1]
+    assert rel[1] == pytest.approx(-u_t, rel=2e-2)
+    assert rel[0] == pytest.approx(-u_n, rel=1e-3)
+    assert 0.5 * (vo ** 2).sum() == pytest.approx(0.5 * (v ** 2).sum(), rel=1e-3)
+    # a finite mu and a fast slide: energy is lost
+    x, v, rc, invm, p = _collide(u_n, 0.3, {"mu": 0.3})
+    _, vo, _, _ = orc.run(p, x, v, rc, invm, 400)
+    assert 0.5 * (vo ** 2).sum() < 0.99 * 0.5 * (v ** 2).sum()
+
+
+def test_friction_conserves_momentum_and_the_method_stays_exact(orc):
+    """A cascade of frictional collisions: total momentum is conserved to rounding
+    (the pair's two springs stay opposite), and the local Verlet buffer gives the
+    same bits as brute force every step (Sec. 4.2: the history belongs to the
+    contact, not to the list)."""
+    s = synth.config_systems("M1", seed=2, scale=0.4)[0]
+    x = s.pos_r[:, :3].astype(np.float64)
+    v = s.vel_m[:, :3].astype(np.float64)
+    rc = s.pos_r[:, 3].astype(np.float64)
+    invm = s.vel_m[:, 3].astype(np.float64)
+    fr = {"kt": 0.5 * s.params["kn"], "gamma_t": 0.5 * s.params["gamma_n"], "mu": 0.4}
+    p = dict(s.params, **fr)
+    far = dict(p, lo=(-10, -10, -10), hi=(11, 11, 11))   # no walls touched
+    xo, vo, h, _ = orc.run(far, x, v, rc, invm, 300)
+    assert h["contacts"].max() > 10
+    m = 1.0 / invm
+    p0 = (m[:, None] * v).sum(axis=0)
+    p1 = (m[:, None] * vo).sum(axis=0)
+    assert np.abs(p1 - p0).max() <= 1e-12 * np.abs(m[:, None] * v).sum()
+    xn, vn, hn, _ = orc.run(dict(p, skin_mode=orc.NAIVE), x, v, rc, invm, 300)
+    xm, vm, hm, _ = orc.run(p, x, v, rc, invm, 300)
+    assert np.array_equal(xn, xm) and np.array_equal(vn, vm)
+    assert np.array_equal(hn["contacts"], hm["contacts"]) and hm["rebuilt"].sum() < 300
