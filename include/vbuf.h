@@ -90,6 +90,12 @@ typedef struct vb_params {
                           /* of the box faces, on particles whose centre has z > z_min (a finite */
                           /* wall such as a hopper side above its outlet).  Walls act after the  */
                           /* box faces, in index order.                                           */
+  double kt, gamma_t, mu; /* tangential spring, tangential dashpot and Coulomb coefficient of the */
+                          /* particle-particle friction (translational; the spring of a contact   */
+                          /* is kept while the contact lasts); mu = 0 or kt = gamma_t = 0: none   */
+  int32_t contact_capacity; /* initial contacts per particle the friction history holds (grown  */
+                          /* on overflow), 1..64; 0 = 16                                           */
+  int32_t reserved2_;
 } vb_params;
 
 /* Diagnostics of one time step n of one system (the state x^n whose forces the

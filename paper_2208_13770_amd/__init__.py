@@ -41,6 +41,11 @@ class vb_params(ctypes.Structure):
         ("n_planes", ctypes.c_int32),
         ("reserved_", ctypes.c_int32),
         ("planes", (ctypes.c_double * 5) * VB_MAX_PLANES),
+        ("kt", ctypes.c_double),
+        ("gamma_t", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("contact_capacity", ctypes.c_int32),
+        ("reserved2_", ctypes.c_int32),
     ]
 
 
@@ -121,8 +126,9 @@ def make_params(p: dict) -> vb_params:
     q = vb_params()
     q.skin_mode = int(p.get("skin_mode", VB_SKIN_LOCAL))
     q.cap_mode = int(p.get("cap_mode", 0))
-    for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n"):
+    for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n", "kt", "gamma_t", "mu"):
         setattr(q, k, float(p.get(k, 0.0)))
+    q.contact_capacity = int(p.get("contact_capacity", 0))
     q.lo[:] = [float(t) for t in p.get("lo", (0.0, 0.0, 0.0))]
     q.hi[:] = [float(t) for t in p.get("hi", (1.0, 1.0, 1.0))]
     q.gravity[:] = [float(t) for t in p.get("g", p.get("gravity", (0.0, 0.0, 0.0)))]

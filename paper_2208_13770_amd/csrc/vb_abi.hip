@@ -22,8 +22,8 @@
 #include "vb_device.h"
 
 namespace vb {
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st, hipEvent_t t0,
-                       hipEvent_t t1);
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, hipStream_t st,
+                       hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st,
                               hipEvent_t t0, hipEvent_t t1);
 size_t pairs_lds_bytes(int width, int pmax);
@@ -61,6 +61,14 @@ struct vb_ctx {
   PX *px[2] = {nullptr, nullptr};
   PV *pv[2] = {nullptr, nullptr};
   float4 *pos32[2] = {nullptr, nullptr};  // FP32 copies of px[0], px[1]
+  // friction history (allocated only when some system has friction)
+  int any_friction = 0;
+  int32_t hcap = 0;
+  HistEntry *hist[2] = {nullptr, nullptr};
+  int32_t *hcnt[2] = {nullptr, nullptr};
+  HistEntry *hist_snap = nullptr;
+  int32_t *hcnt_snap = nullptr;
+  int32_t hist_snap_cap = 0;   // entries per slot hist_snap holds
   PX *snap_px = nullptr;
   PV *snap_pv = nullptr;
   float4 *bp = nullptr;
@@ -133,7 +141,8 @@ static hipError_t dalloc(T **p, int64_t count) {
 
 static void free_all(vb_ctx *c) {
   void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->pos32[0],
-                  c->pos32[1], c->snap_px,
+                  c->pos32[1], c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
+                  c->hcnt_snap, c->snap_px,
                   c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
                   c->brick_sys, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
@@ -166,6 +175,10 @@ static std::string check_params(const vb_params &p, int64_t n) {
   if (p.skin_mode == VB_FIXED_INTERVAL && p.fixed_interval < 1) return "fixed_interval must be >= 1";
   if (p.reorder_interval < 0) return "reorder_interval must be >= 0";
   if (p.bin_capacity < 0 || p.bin_capacity > MAX_BIN) return "bin_capacity must be 0..256";
+  if (!(p.kt >= 0.0) || !(p.gamma_t >= 0.0) || !(p.mu >= 0.0) || !std::isfinite(p.kt) ||
+      !std::isfinite(p.gamma_t) || !std::isfinite(p.mu))
+    return "kt, gamma_t and mu must be finite and >= 0";
+  if (p.contact_capacity < 0 || p.contact_capacity > MAX_HIST) return "contact_capacity must be 0..64";
   if (p.n_planes < 0 || p.n_planes > VB_MAX_PLANES) return "n_planes must be 0..4";
   for (int w = 0; w < p.n_planes; ++w) {
     const double *pl = p.planes[w];
@@ -211,6 +224,23 @@ static vb_status alloc_rows(vb_ctx *c, int32_t width) {
   const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - 6144,
                                            std::max<int64_t>((int64_t)c->lds_cu / 2 - 5120, rows + 1024 * 24));
   c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
+  return VB_OK;
+}
+
+// Friction history: cap entries per slot, double-buffered, plus the snapshot
+// vb_run keeps to run a call again.  The contents are not kept (a regrow runs
+// the call again from its snapshot, which is re-laid by copy_hist).
+static vb_status alloc_hist_tables(vb_ctx *c, int32_t cap) {
+  for (int b = 0; b < 2; ++b) {
+    if (c->hist[b]) (void)hipFree(c->hist[b]);
+    if (c->hcnt[b]) (void)hipFree(c->hcnt[b]);
+    c->hist[b] = nullptr;
+    c->hcnt[b] = nullptr;
+    HIP_OK(c, dalloc(&c->hist[b], c->slots * (int64_t)cap));
+    HIP_OK(c, dalloc(&c->hcnt[b], c->slots));
+    HIP_OK(c, hipMemset(c->hcnt[b], 0, sizeof(int32_t) * c->slots));
+  }
+  c->hcap = cap;
   return VB_OK;
 }
 
@@ -306,6 +336,12 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.skin_mode = p.skin_mode;
     S.fixed_interval = p.fixed_interval < 1 ? 1 : p.fixed_interval;
     S.ring = p.cap_mode == 0 ? 1 : 2;
+    S.kt = p.kt;
+    S.gamma_t = p.gamma_t;
+    S.mu = p.mu;
+    S.friction = p.mu > 0.0 && (p.kt > 0.0 || p.gamma_t > 0.0);
+    c->any_friction |= S.friction;
+    c->hcap = std::max(c->hcap, p.contact_capacity > 0 ? p.contact_capacity : 16);
     S.n_planes = p.n_planes;
     for (int w = 0; w < p.n_planes; ++w)
       for (int c = 0; c < 5; ++c) S.planes[w][c] = p.planes[w][c];
@@ -377,7 +413,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->perm0, c->slots);
   ALLOC(c->flags, 2 * n_sys);
   ALLOC(c->go, n_sys);
-  ALLOC(c->overflow, 2);
+  ALLOC(c->overflow, 3);
   ALLOC(c->err, 1);
   ALLOC(c->stats, (int64_t)STATS_RING * std::max<int64_t>(c->n_tiles, 1));
   ALLOC(c->rebuilt_ring, (int64_t)STATS_RING * n_sys);
@@ -386,6 +422,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->pair_total, 1);
 #undef ALLOC
   if ((st = alloc_rows(c, width)) != VB_OK) return bail(st);
+  if (c->any_friction && (st = alloc_hist_tables(c, c->hcap)) != VB_OK) return bail(st);
   if ((st = alloc_bins(c, bcap)) != VB_OK) return bail(st);
   if ((st = alloc_hist(c, STATS_RING)) != VB_OK) return bail(st);
   if (hipMemcpy(c->sys_d, c->sys_h.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice) !=
@@ -401,7 +438,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
       hipMemset(c->cnt, 0, sizeof(int32_t) * c->slots) != hipSuccess ||
       hipMemset(c->flags, 0, sizeof(int32_t) * 2 * n_sys) != hipSuccess ||
       hipMemset(c->go, 0, sizeof(int32_t) * n_sys) != hipSuccess ||
-      hipMemset(c->overflow, 0, sizeof(int32_t) * 2) != hipSuccess ||
+      hipMemset(c->overflow, 0, sizeof(int32_t) * 3) != hipSuccess ||
       hipMemset(c->rebuilt_ring, 0, sizeof(int32_t) * STATS_RING * n_sys) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     c->msg = "device initialisation failed";
@@ -422,7 +459,7 @@ static vb_status reset_control(vb_ctx *c) {
   HIP_OK(c, launch_fill_i32(c->flags, 2 * c->n_sys, 0, c->stream));
   HIP_OK(c, launch_fill_i32(c->go, c->n_sys, 0, c->stream));
   HIP_OK(c, launch_fill_i32(c->bin_count, c->n_cells, 0, c->stream));
-  HIP_OK(c, launch_fill_i32(c->overflow, 2, 0, c->stream));
+  HIP_OK(c, launch_fill_i32(c->overflow, 3, 0, c->stream));
   return VB_OK;
 }
 
@@ -438,6 +475,7 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
                                c->stream));
   HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
   HIP_OK(c, launch_pos32(c->px[0], c->pos32[0], c->slots, c->stream));
+  if (c->any_friction) HIP_OK(c, launch_fill_i32(c->hcnt[0], c->slots, 0, c->stream));
   vb_status st = reset_control(c);
   if (st != VB_OK) return st;
   int32_t err = 0;
@@ -511,6 +549,12 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.cellid = c->cellid;
     s.inslot = c->inslot;
     s.perm0 = c->perm0;
+    s.hist_src = c->any_friction ? c->hist[c->cur] : nullptr;
+    s.hcnt_src = c->any_friction ? c->hcnt[c->cur] : nullptr;
+    s.hist_dst = c->any_friction ? c->hist[c->cur ^ 1] : nullptr;
+    s.hcnt_dst = c->any_friction ? c->hcnt[c->cur ^ 1] : nullptr;
+    s.hcap = c->hcap;
+    s.stride = c->slots;
     HIP_OK(c, launch_sort(s, c->stream));
     c->cur ^= 1;
     HIP_OK(c, launch_pos32(c->px[c->cur], c->pos32[c->cur], c->slots, c->stream));
@@ -547,7 +591,13 @@ static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = 
   a.first = c->first;
   a.xcd_remap = c->xcd_remap;
   a.width = c->width;
-  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->stream, t0, t1));
+  a.hist_cur = c->hist[c->cur];
+  a.hcnt_cur = c->hcnt[c->cur];
+  a.hist_dst = c->hist[c->cur ^ 1];
+  a.hcnt_dst = c->hcnt[c->cur ^ 1];
+  a.hcap = c->hcap;
+  a.overflow = c->overflow;
+  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->any_friction, c->stream, t0, t1));
   return VB_OK;
 }
 
@@ -603,20 +653,36 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
                            hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->snap_pv, c->pv[c->cur], sizeof(PV) * c->slots,
                            hipMemcpyDeviceToDevice, c->stream));
+  int32_t snap_hcap = 0;
+  if (c->any_friction) {
+    if (c->hist_snap_cap < c->hcap) {
+      if (c->hist_snap) (void)hipFree(c->hist_snap);
+      c->hist_snap = nullptr;
+      HIP_OK(c, dalloc(&c->hist_snap, c->slots * (int64_t)c->hcap));
+      c->hist_snap_cap = c->hcap;
+    }
+    if (!c->hcnt_snap) HIP_OK(c, dalloc(&c->hcnt_snap, c->slots));
+    snap_hcap = c->hcap;
+    HIP_OK(c, hipMemcpyAsync(c->hist_snap, c->hist[c->cur], sizeof(HistEntry) * c->slots * c->hcap,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->hcnt_snap, c->hcnt[c->cur], sizeof(int32_t) * c->slots,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
   const int64_t step0 = c->step, sort0 = c->next_sort;
   const int first0 = c->first;
   for (int attempt = 0;; ++attempt) {
     if ((st = run_steps(c, n_steps)) != VB_OK) return st;
-    int32_t ovf[2] = {0, 0};
+    int32_t ovf[3] = {0, 0, 0};
     HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    if (ovf[0] <= c->width && ovf[1] <= c->bin_cap) break;
-    if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || attempt >= 4) {
+    if (ovf[0] <= c->width && ovf[1] <= c->bin_cap && ovf[2] <= c->hcap) break;
+    if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || ovf[2] > MAX_HIST || attempt >= 4) {
       c->loaded = 0;
       return fail(c, VB_ECAPACITY,
                   "a Verlet-list row needs " + std::to_string(ovf[0]) + " entries (limit " +
-                      std::to_string(c->row_limit) + ") or a "
-                  "cell bin " + std::to_string(ovf[1]) + " particles (limit 256)");
+                      std::to_string(c->row_limit) + "), a cell bin " + std::to_string(ovf[1]) +
+                      " particles (limit 256) or a friction history " + std::to_string(ovf[2]) +
+                      " contacts (limit " + std::to_string(MAX_HIST) + ")");
     }
     // grow and start again from the call's first step; the forced broad phase
     // changes the schedule, not the results (theorem of Sec. 4.2)
@@ -626,12 +692,21 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     if (ovf[1] > c->bin_cap &&
         (st = alloc_bins(c, std::min<int32_t>(MAX_BIN, (ovf[1] + ovf[1] / 4 + 7) / 8 * 8))) != VB_OK)
       return st;
+    if (ovf[2] > c->hcap &&
+        (st = alloc_hist_tables(c, std::min<int32_t>(MAX_HIST, (ovf[2] + ovf[2] / 4 + 3) / 4 * 4))) != VB_OK)
+      return st;
     HIP_OK(c, hipMemcpyAsync(c->px[0], c->snap_px, sizeof(PX) * c->slots,
                              hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots,
                              hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
     HIP_OK(c, launch_pos32(c->px[0], c->pos32[0], c->slots, c->stream));
+    if (c->any_friction) {  // entries c < snap_hcap sit at the same place in a wider table
+      HIP_OK(c, hipMemcpyAsync(c->hist[0], c->hist_snap, sizeof(HistEntry) * c->slots * snap_hcap,
+                               hipMemcpyDeviceToDevice, c->stream));
+      HIP_OK(c, hipMemcpyAsync(c->hcnt[0], c->hcnt_snap, sizeof(int32_t) * c->slots,
+                               hipMemcpyDeviceToDevice, c->stream));
+    }
     if ((st = reset_control(c)) != VB_OK) return st;
     c->cur = 0;
     c->step = step0;

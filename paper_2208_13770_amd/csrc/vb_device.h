@@ -19,6 +19,7 @@ constexpr int MAX_SYS = 1024;     // systems per batch
 constexpr int STATS_RING = 64;    // steps of per-tile statistics kept before reduction
 constexpr int MAX_ROW = 128;      // largest Verlet-list row (rows are sorted in LDS)
 constexpr int MAX_BIN = 256;      // largest cell-bin capacity
+constexpr int MAX_HIST = 64;      // largest friction history per particle (contacts)
 constexpr int SCAN_ITEMS = 16;    // cells per thread in the block-level scans
 constexpr int BRICK = 4;          // cells per brick edge: cells are numbered brick by brick
 constexpr int MAX_CAND = 32;      // row entries per segment of the step kernel's two-pass scan
@@ -62,8 +63,20 @@ struct SysDev {
   int32_t ring;       // cell rings searched: 1 (cap mode 0) or 2 (cap mode 1)
   float margin32;     // margin of the step kernel's FP32 contact pre-test
   int32_t n_planes;   // planar walls besides the box faces
+  int32_t friction;   // 1: tangential spring-dashpot with Coulomb limit on the contacts
   double planes[VB_MAX_PLANES][5];  // (n_x, n_y, n_z, d, z_min) as in vb_params
+  double kt, gamma_t, mu;           // friction law
 };
+
+// One entry of a particle's friction history: a contact of the previous step
+// (partner's original index) and the tangential spring of that contact as seen
+// from the particle.  Entries of a particle are ordered by partner.
+struct alignas(16) HistEntry {
+  double sx, sy, sz;
+  uint32_t orig;
+  uint32_t pad;
+};
+static_assert(sizeof(HistEntry) == 32, "history entries are 32 bytes");
 
 // Per-tile statistics of one step (reduced per system later, in a fixed order).
 struct TileStats {
@@ -137,6 +150,14 @@ struct StepArgs {
   int32_t first;         // 1: the velocities are the full-step v^0 (no first half kick)
   int32_t xcd_remap;     // 1: give each XCD a contiguous range of tiles
   int32_t width;         // row capacity W (entries below it are allocated)
+  // friction history (used only when some system has friction): column-major,
+  // entry c of slot k at hist[c * stride + k]
+  const HistEntry *hist_cur;
+  const int32_t *hcnt_cur;
+  HistEntry *hist_dst;
+  int32_t *hcnt_dst;
+  int32_t hcap;          // entries per slot
+  int32_t *overflow;     // [2]: most contacts a particle had beyond hcap
 };
 
 // Arguments of the spatial re-sort (counting sort of the slots by cell).
@@ -155,6 +176,13 @@ struct SortArgs {
   int32_t *cellid;      // [slots]
   int32_t *inslot;      // [slots]
   int32_t *perm0;       // [slots]
+  // friction history, moved with its particle (null when no system has friction)
+  const HistEntry *hist_src;
+  const int32_t *hcnt_src;
+  HistEntry *hist_dst;
+  int32_t *hcnt_dst;
+  int32_t hcap;
+  int64_t stride;       // slots
 };
 
 }  // namespace vb

@@ -193,7 +193,7 @@ __device__ __forceinline__ void nt_store32(T *dst, const T &val) {
 
 // ------------------------------------------------------------------ k_step
 
-template <int UNROLL>
+template <int UNROLL, bool FRIC>
 __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   const int64_t t = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   const int s = a.tile_sys[t];
@@ -234,6 +234,15 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const float4 b = nt_load(&a.bp[k]);
     rowlen = nt_load(&a.cnt[k]);
     double fx = 0.0, fy = 0.0, fz = 0.0;
+    // friction history: this particle's contacts of the previous step (partner
+    // ascending) are merged with this step's contacts, which come in the same
+    // order; the new history holds exactly this step's contacts
+    const bool fric = FRIC && S.friction;
+    const int hn = fric ? a.hcnt_cur[k] : 0;
+    int hp = 0, hc = 0;
+    HistEntry hold;
+    hold.orig = 0xFFFFFFFFu;
+    if (hn > 0) hold = a.hist_cur[k];
     auto contact = [&](const PX &o, const PV &ov) {
       double dx, dy, dz, d, delta;
       if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
@@ -245,6 +254,58 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         fy += fm * ny;
         fz += fm * nz;
         ++ncon;
+        if constexpr (FRIC) {
+          if (fric) {
+            // tangential linear spring-dashpot with a Coulomb limit: the spring
+            // of the previous step, turned into the tangent plane, grows by
+            // v_t dt; a force beyond mu F_n is cut back to the cone and the
+            // spring set to the one that gives it
+            while (hp < hn && hold.orig < o.orig) {
+              ++hp;
+              if (hp < hn) hold = a.hist_cur[(int64_t)hp * st + k];
+            }
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            if (hp < hn && hold.orig == o.orig) {
+              sx = hold.sx;
+              sy = hold.sy;
+              sz = hold.sz;
+            }
+            const double vtx = (mv.vx - ov.vx) - vn * nx;
+            const double vty = (mv.vy - ov.vy) - vn * ny;
+            const double vtz = (mv.vz - ov.vz) - vn * nz;
+            const double sn = sx * nx + sy * ny + sz * nz;
+            sx = (sx - sn * nx) + vtx * S.dt;
+            sy = (sy - sn * ny) + vty * S.dt;
+            sz = (sz - sn * nz) + vtz * S.dt;
+            double ftx = -S.kt * sx - S.gamma_t * vtx;
+            double fty = -S.kt * sy - S.gamma_t * vty;
+            double ftz = -S.kt * sz - S.gamma_t * vtz;
+            const double ftn = sqrt(ftx * ftx + fty * fty + ftz * ftz);
+            const double lim = S.mu * (fm > 0.0 ? fm : 0.0);
+            if (ftn > lim) {
+              const double sc = lim / ftn;
+              ftx *= sc;
+              fty *= sc;
+              ftz *= sc;
+              sx = S.kt > 0.0 ? -(ftx + S.gamma_t * vtx) / S.kt : 0.0;
+              sy = S.kt > 0.0 ? -(fty + S.gamma_t * vty) / S.kt : 0.0;
+              sz = S.kt > 0.0 ? -(ftz + S.gamma_t * vtz) / S.kt : 0.0;
+            }
+            fx += ftx;
+            fy += fty;
+            fz += ftz;
+            if (hc < a.hcap) {
+              HistEntry e;
+              e.sx = sx;
+              e.sy = sy;
+              e.sz = sz;
+              e.orig = o.orig;
+              e.pad = 0;
+              a.hist_dst[(int64_t)hc * st + k] = e;
+            }
+            ++hc;
+          }
+        }
       }
     };
     // Two passes over each segment of MAX_CAND row entries.  The scan walks the
@@ -291,6 +352,12 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
 #pragma unroll
         for (int u = 0; u < CONTACT_UNROLL; ++u)
           if (i0 + u < nc) contact(o[u], ov[u]);
+      }
+    }
+    if constexpr (FRIC) {
+      if (fric) {
+        a.hcnt_dst[k] = hc < a.hcap ? hc : a.hcap;
+        if (hc > a.hcap) atomicMax(&a.overflow[2], hc);
       }
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
@@ -813,6 +880,12 @@ __global__ __launch_bounds__(TILE) void k_sort_place(SortArgs a) {
   for (int64_t m = cs; m < ce; ++m) rank += a.px_src[S.p_off + a.perm0[m]].orig < me.orig;
   a.px_dst[cs + rank] = me;
   a.pv_dst[cs + rank] = a.pv_src[S.p_off + q];
+  if (a.hist_src) {  // the friction history moves with its particle
+    const int hn = a.hcnt_src[S.p_off + q];
+    a.hcnt_dst[cs + rank] = hn;
+    for (int c = 0; c < hn; ++c)
+      a.hist_dst[(int64_t)c * a.stride + cs + rank] = a.hist_src[(int64_t)c * a.stride + S.p_off + q];
+  }
 }
 
 // ------------------------------------------------------------------ statistics
@@ -1040,14 +1113,22 @@ static void launch_timed(K kernel, dim3 g, dim3 b, uint32_t lds, hipStream_t st,
   else hipLaunchKernelGGL(kernel, g, b, lds, st, a);
 }
 
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st, hipEvent_t t0,
-                       hipEvent_t t1) {
-  if (n_tiles <= 0) return hipSuccess;
+template <bool FRIC>
+static void launch_step_t(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st,
+                          hipEvent_t t0, hipEvent_t t1) {
   const dim3 g((unsigned)n_tiles), b(TILE);
-  if (unroll >= 8) launch_timed(k_step<8>, g, b, 0, st, t0, t1, a);
-  else if (unroll >= 4) launch_timed(k_step<4>, g, b, 0, st, t0, t1, a);
-  else if (unroll >= 2) launch_timed(k_step<2>, g, b, 0, st, t0, t1, a);
-  else launch_timed(k_step<1>, g, b, 0, st, t0, t1, a);
+  if (unroll >= 8) launch_timed(k_step<8, FRIC>, g, b, 0, st, t0, t1, a);
+  else if (unroll >= 4) launch_timed(k_step<4, FRIC>, g, b, 0, st, t0, t1, a);
+  else if (unroll >= 2) launch_timed(k_step<2, FRIC>, g, b, 0, st, t0, t1, a);
+  else launch_timed(k_step<1, FRIC>, g, b, 0, st, t0, t1, a);
+}
+
+// friction: 1 if some system of the batch has friction (its history is kept)
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, hipStream_t st,
+                       hipEvent_t t0, hipEvent_t t1) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (friction) launch_step_t<true>(a, n_tiles, unroll, st, t0, t1);
+  else launch_step_t<false>(a, n_tiles, unroll, st, t0, t1);
   return hipGetLastError();
 }
 

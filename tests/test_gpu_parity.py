@@ -384,3 +384,49 @@ def test_plane_parameters_are_checked():
                    [(0.0, 0.0, 1.0, 0.0, 0.0)] * 5):
         with pytest.raises((vb.VbError, ValueError)):
             vb.vb_create(dict(s.params, planes=planes), s.n)
+
+
+# ---------------------------------------------------------------- friction
+def _frictional(s, mu=0.4):
+    return {"kt": 0.5 * s.params["kn"], "gamma_t": 0.5 * s.params["gamma_n"], "mu": mu}
+
+
+@pytest.mark.parametrize("name,scale,steps", [("M1", 1.0, 200), ("H125", 0.3, 1200)])
+def test_friction_parity_with_oracle(name, scale, steps):
+    """Tangential spring-dashpot with Coulomb limit and per-contact history: GPU vs
+    oracle, element by element (a collisional flow; a hopper under gravity)."""
+    s = synth.config_systems(name, seed=1, scale=scale)[0]
+    fr = _frictional(s)
+    say(f"friction on {name}: N={s.n}, {steps} steps, {fr}")
+    xg, vg, hg = gpu_trajectory([s], steps, **fr)
+    xo, vo, ho, _ = oracle_run(s, steps, **fr)
+    assert_close(s, xg, vg, xo, vo, name + " with friction")
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert ho["contacts"].max() > 20
+    # friction changes the trajectory
+    xf, _, _ = gpu_trajectory([s], steps)
+    assert not np.array_equal(xf, xg)
+
+
+def test_friction_k_invariance_sorts_and_history_regrow_bitwise():
+    """The springs belong to the contacts, not to the Verlet list: K = 200, K = 20
+    and the broad phase at every step give the same bits; so do periodic storage
+    re-sorts (the history moves with its particle) and a history table that
+    starts with room for one contact and is grown by vb_run."""
+    s = synth.config_systems("M1", seed=6)[0]
+    fr = _frictional(s, mu=0.3)
+    ref = gpu_trajectory([s], 180, skin_mode=2, **fr)
+    for name, ov in (("K=200", {}), ("K=20", {"K": 20.0}), ("re-sort every 25", {"reorder_interval": 25}),
+                     ("capacity 1", {"contact_capacity": 1})):
+        say(f"friction, {name}")
+        x, v, h = gpu_trajectory([s], 180, **dict(fr, **ov))
+        assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), name
+        assert np.array_equal(h[0]["contacts"], ref[2][0]["contacts"]), name
+
+
+def test_friction_parameters_are_checked():
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", scale=0.25)[0]
+    for bad in ({"mu": -0.1}, {"kt": float("nan"), "mu": 0.3}, {"contact_capacity": 65}):
+        with pytest.raises(vb.VbError):
+            vb.vb_create(dict(s.params, **bad), s.n)
