@@ -108,6 +108,15 @@ struct vb_ctx {
   int loaded = 0;
   int xcd_remap = 0;
   int step_unroll = 8;
+  // replay of STATS_RING steps as one HIP graph (launch-bound small systems);
+  // one cached graph per ping-pong parity, keyed by what the graph bakes in
+  int use_graphs = 1;
+  hipStream_t cap_stream = nullptr;
+  int32_t *step_base_d = nullptr;  // first step of the replayed block
+  int graph_mode = 0;              // queue_* build graph nodes: step = *step_base_d + graph_off
+  int32_t graph_off = 0;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  uint64_t graph_key[2] = {0, 0};
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -150,6 +159,10 @@ static void free_all(vb_ctx *c) {
                   c->pair_counts, c->pair_offsets, c->pair_total};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  for (int b = 0; b < 2; ++b)
+    if (c->graph_exec[b]) (void)hipGraphExecDestroy(c->graph_exec[b]);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->step_base_d) (void)hipFree(c->step_base_d);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
 }
@@ -281,6 +294,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   const char *env = std::getenv("VBUF_XCD_REMAP");
   if (env) c->xcd_remap = std::atoi(env) != 0;
   if ((env = std::getenv("VBUF_STEP_UNROLL"))) c->step_unroll = std::atoi(env);
+  if ((env = std::getenv("VBUF_GRAPHS"))) c->use_graphs = std::atoi(env) != 0;
   vb_status st = VB_OK;
   auto bail = [&](vb_status code) {
     g_create_error = c->msg;
@@ -414,6 +428,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->flags, 2 * n_sys);
   ALLOC(c->go, n_sys);
   ALLOC(c->overflow, 3);
+  ALLOC(c->step_base_d, 1);
   ALLOC(c->err, 1);
   ALLOC(c->stats, (int64_t)STATS_RING * std::max<int64_t>(c->n_tiles, 1));
   ALLOC(c->rebuilt_ring, (int64_t)STATS_RING * n_sys);
@@ -423,6 +438,10 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
 #undef ALLOC
   if ((st = alloc_rows(c, width)) != VB_OK) return bail(st);
   if (c->any_friction && (st = alloc_hist_tables(c, c->hcap)) != VB_OK) return bail(st);
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->msg = "stream creation failed";
+    return bail(VB_EDEVICE);
+  }
   if ((st = alloc_bins(c, bcap)) != VB_OK) return bail(st);
   if ((st = alloc_hist(c, STATS_RING)) != VB_OK) return bail(st);
   if (hipMemcpy(c->sys_d, c->sys_h.data(), sizeof(SysDev) * n_sys, hipMemcpyHostToDevice) !=
@@ -514,17 +533,13 @@ static BroadArgs broad_args(vb_ctx *c, int force) {
   a.brick_sys = c->brick_sys;
   a.n_bricks = c->n_bricks;
   a.pmax = c->pmax;
-  a.host_need = force || c->any_no_buffer;
-  if (c->any_fixed)
-    for (int s = 0; s < c->n_sys; ++s)
-      if (c->sys_h[s].skin_mode == VB_FIXED_INTERVAL && c->step % c->sys_h[s].fixed_interval == 0)
-        a.host_need = 1;
   a.inv = c->inv;
   a.flags = c->flags;
   a.go = c->go;
   a.rebuilt_ring = c->rebuilt_ring;
   a.overflow = c->overflow;
-  a.step = (int32_t)c->step;
+  a.step = c->graph_mode ? c->graph_off : (int32_t)c->step;
+  a.step_base = c->graph_mode ? c->step_base_d : nullptr;
   a.force = force;
   return a;
 }
@@ -587,7 +602,8 @@ static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = 
   a.n_sys = c->n_sys;
   a.stats = c->stats;
   a.n_tiles = c->n_tiles;
-  a.step = (int32_t)c->step;
+  a.step = c->graph_mode ? c->graph_off : (int32_t)c->step;
+  a.step_base = c->graph_mode ? c->step_base_d : nullptr;
   a.first = c->first;
   a.xcd_remap = c->xcd_remap;
   a.width = c->width;
@@ -611,13 +627,91 @@ static vb_status ensure_events(vb_ctx *c, size_t n) {
 }
 
 // Queues n_steps steps; records go to hist_d[r * n_sys + s].
+// What a captured block of steps bakes in: buffers, sizes, launch shapes.
+static uint64_t graph_key(const vb_ctx *c, int cur) {
+  const uint64_t parts[] = {(uint64_t)(uintptr_t)c->px[cur], (uint64_t)(uintptr_t)c->nbr,
+                            (uint64_t)(uintptr_t)c->bins_bp, (uint64_t)(uintptr_t)c->bins_so,
+                            (uint64_t)(uintptr_t)c->hist[cur], (uint64_t)(uintptr_t)c->hist[cur ^ 1],
+                            (uint64_t)(uintptr_t)c->stream, (uint64_t)c->width, (uint64_t)c->pmax,
+                            (uint64_t)c->bin_cap, (uint64_t)c->hcap, (uint64_t)c->step_unroll,
+                            (uint64_t)cur};
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the words
+  for (uint64_t w : parts)
+    for (int b = 0; b < 8; ++b) h = (h ^ ((w >> (8 * b)) & 0xff)) * 1099511628211ull;
+  return h | 1;
+}
+
+// Captures STATS_RING steps (broad-phase gate, pair search, step kernel each)
+// starting from ping-pong parity cur, with the step read from step_base_d.
+static vb_status capture_block(vb_ctx *c, int cur) {
+  if (c->graph_exec[cur]) (void)hipGraphExecDestroy(c->graph_exec[cur]);
+  c->graph_exec[cur] = nullptr;
+  c->graph_key[cur] = 0;
+  const hipStream_t saved_stream = c->stream;
+  const int saved_cur = c->cur;
+  c->stream = c->cap_stream;
+  c->cur = cur;
+  c->graph_mode = 1;
+  vb_status st = VB_OK;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    st = fail(c, VB_EDEVICE, "hipStreamBeginCapture failed");
+  } else {
+    for (int32_t i = 0; i < STATS_RING && st == VB_OK; ++i) {
+      c->graph_off = i;
+      BroadArgs b = broad_args(c, 0);
+      if (launch_broad_phase(b, c->broad_grid, c->pairs_grid, c->stream, nullptr, nullptr) !=
+          hipSuccess)
+        st = fail(c, VB_EDEVICE, "capture of the broad phase failed");
+      else if ((st = queue_step(c)) == VB_OK)
+        c->cur ^= 1;
+    }
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st == VB_OK && e != hipSuccess) st = fail(c, VB_EDEVICE, "hipStreamEndCapture failed");
+  }
+  if (st == VB_OK && hipGraphInstantiate(&c->graph_exec[cur], g, nullptr, nullptr, 0) != hipSuccess)
+    st = fail(c, VB_EDEVICE, "hipGraphInstantiate failed");
+  if (g) (void)hipGraphDestroy(g);
+  c->graph_mode = 0;
+  c->graph_off = 0;
+  c->stream = saved_stream;
+  c->cur = saved_cur;
+  if (st == VB_OK) c->graph_key[cur] = graph_key(c, cur);
+  return st;
+}
+
+// Queues n_steps steps; records go to hist_d[r * n_sys + s].  Blocks of
+// STATS_RING steps run as one replayed graph when nothing in them needs the
+// host (no timing, first step, forced broad phase or storage re-sort).
 static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
   vb_status st;
   // with timing on, four events per step take the kernels' own start and end
   // times: binning start and pair-search end, step-kernel start and end
   if (c->timing && (st = ensure_events(c, 4 * (size_t)n_steps)) != VB_OK) return st;
   int32_t pending = 0;
-  for (int32_t i = 0; i < n_steps; ++i) {
+  for (int32_t i = 0; i < n_steps;) {
+    const bool block = c->use_graphs && !c->timing && !c->first && !c->force_pending &&
+                       n_steps - i >= STATS_RING && c->n_tiles > 0 &&
+                       (c->next_sort < 0 || c->next_sort >= c->step + STATS_RING);
+    if (block && pending > 0) {  // close the records of the steps before the block
+      HIP_OK(c, launch_stats_reduce(c->sys_d, c->stats, c->rebuilt_ring, c->n_tiles, c->n_sys,
+                                    (int32_t)(c->step - pending), pending,
+                                    c->hist_d + (int64_t)(i - pending) * c->n_sys, c->stream));
+      pending = 0;
+    }
+    if (block) {
+      const int cur = c->cur;
+      if (!c->graph_exec[cur] || c->graph_key[cur] != graph_key(c, cur))
+        if ((st = capture_block(c, cur)) != VB_OK) return st;
+      HIP_OK(c, launch_fill_i32(c->step_base_d, 1, (int32_t)c->step, c->stream));
+      HIP_OK(c, hipGraphLaunch(c->graph_exec[cur], c->stream));
+      c->step += STATS_RING;  // an even count: the ping-pong parity is back to cur
+      HIP_OK(c, launch_stats_reduce(c->sys_d, c->stats, c->rebuilt_ring, c->n_tiles, c->n_sys,
+                                    (int32_t)(c->step - STATS_RING), STATS_RING,
+                                    c->hist_d + (int64_t)i * c->n_sys, c->stream));
+      i += STATS_RING;
+      continue;
+    }
     hipEvent_t *e = c->timing ? &c->ev[4 * (size_t)i] : nullptr;
     if ((st = queue_broad_phase(c, e ? e[0] : nullptr, e ? e[1] : nullptr)) != VB_OK) return st;
     if ((st = queue_step(c, e ? e[2] : nullptr, e ? e[3] : nullptr)) != VB_OK) return st;
@@ -632,6 +726,7 @@ static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
                                     c->stream));
       pending = 0;
     }
+    ++i;
   }
   return VB_OK;
 }

@@ -116,13 +116,13 @@ struct BroadArgs {
   const int32_t *brick_sys;  // [bricks] system of each brick
   int64_t n_bricks;
   int32_t pmax;         // candidates a workgroup can stage in LDS
-  int32_t host_need;    // 1 if some system needs a broad phase regardless of the flags
   int32_t *inv;         // [slots] inv[p_off + orig] = local slot
   const int32_t *flags; // [2][n_sys] validity-violation flags; slot (step & 1) is read
   int32_t *go;          // [n_sys] 1 if the system runs a broad phase at this step
   int32_t *rebuilt_ring;  // [STATS_RING][n_sys]
   int32_t *overflow;    // [0] longest row beyond W, [1] fullest bin beyond bin_cap
-  int32_t step;
+  int32_t step;         // the step, or its offset from *step_base when step_base is set
+  const int32_t *step_base;  // device step counter of a replayed graph (else null)
   int32_t force;        // 1: broad phase for every system regardless of flags
 };
 
@@ -146,7 +146,8 @@ struct StepArgs {
   int32_t n_sys;
   TileStats *stats;      // [STATS_RING][n_tiles_total]
   int64_t n_tiles;
-  int32_t step;
+  int32_t step;          // the step, or its offset from *step_base when step_base is set
+  const int32_t *step_base;  // device step counter of a replayed graph (else null)
   int32_t first;         // 1: the velocities are the full-step v^0 (no first half kick)
   int32_t xcd_remap;     // 1: give each XCD a contiguous range of tiles
   int32_t width;         // row capacity W (entries below it are allocated)

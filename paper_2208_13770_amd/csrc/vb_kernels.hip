@@ -204,6 +204,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   const int64_t k = S.p_off + local;
   const PX *__restrict__ px = a.px_cur;
   const PV *__restrict__ pv = a.pv_cur;
+  const int step = a.step + (a.step_base ? *a.step_base : 0);
   __shared__ int32_t s_cand[MAX_CAND * TILE];  // per-thread lists of contact candidates
 
   // after a broad phase: empty this tile's share of the system's cell bins and
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const int chunk = (S.nkeys + S.n_tiles - 1) / S.n_tiles;
     const int c1 = min(S.nkeys, (lt + 1) * chunk);
     for (int c = lt * chunk + (int)threadIdx.x; c < c1; c += TILE) a.bin_count[S.c_off + c] = 0;
-    if (lt == 0 && threadIdx.x == 0) a.flags[(a.step & 1) * a.n_sys + s] = 0;
+    if (lt == 0 && threadIdx.x == 0) a.flags[(step & 1) * a.n_sys + s] = 0;
   }
 
   double ke = 0.0;
@@ -455,9 +456,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       stt.violators += s_i[2][i];
       stt.max_excess = fmaxf(stt.max_excess, s_x[i]);
     }
-    a.stats[(int64_t)(a.step % STATS_RING) * a.n_tiles + t] = stt;
+    a.stats[(int64_t)(step % STATS_RING) * a.n_tiles + t] = stt;
     if (stt.violators > 0 && (S.skin_mode == 0 || S.skin_mode == 1))
-      atomicOr(&a.flags[((a.step + 1) & 1) * a.n_sys + s], 1);
+      atomicOr(&a.flags[((step + 1) & 1) * a.n_sys + s], 1);
   }
 }
 
@@ -467,26 +468,28 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
 // a broad phase at this step.  Grid-stride over tiles.
 __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
   const int tid = threadIdx.x;
-  int any = a.host_need;
-  for (int s = tid; s < a.n_sys; s += TILE) any |= a.flags[(a.step & 1) * a.n_sys + s];
+  const int step = a.step + (a.step_base ? *a.step_base : 0);
+  int any = a.force;
+  for (int s = tid; s < a.n_sys; s += TILE)
+    any |= needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, step, a.force);
   if (!__syncthreads_or(any)) {  // the same decision in every workgroup
     if (blockIdx.x == 0)
       for (int s = tid; s < a.n_sys; s += TILE) {
         a.go[s] = 0;
-        a.rebuilt_ring[(a.step % STATS_RING) * a.n_sys + s] = 0;
+        a.rebuilt_ring[(step % STATS_RING) * a.n_sys + s] = 0;
       }
     return;
   }
   if (blockIdx.x == 0)
     for (int s = tid; s < a.n_sys; s += TILE) {
-      const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, a.step, a.force);
+      const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, step, a.force);
       a.go[s] = nd;
-      a.rebuilt_ring[(a.step % STATS_RING) * a.n_sys + s] = nd;
+      a.rebuilt_ring[(step % STATS_RING) * a.n_sys + s] = nd;
     }
   for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const int s = a.tile_sys[t];
     const SysDev &S = a.sys[s];
-    if (!needs_broad_phase(S, a.flags, a.n_sys, s, a.step, a.force)) continue;
+    if (!needs_broad_phase(S, a.flags, a.n_sys, s, step, a.force)) continue;
     const int local = (int)(t - S.tile_off) * TILE + tid;
     int64_t key = -1;
     float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
