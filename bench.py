@@ -17,9 +17,10 @@ oracle.
 
 Prints ONE JSON line:
   value       whole-job throughput, Mparticle*step/s, of the method (K = 200) with
-              the state resident in HBM;
-  roofline    the step kernel's algorithmic bytes per launch over its mean HIP-event
-              duration, against the 8 TB/s HBM peak;
+              the state resident in HBM (a run without instrumentation);
+  roofline    the step kernel's algorithmic bytes per launch over its mean duration,
+              taken by HIP events on the kernel in an identical second run, against
+              the 8 TB/s HBM peak;
   plain       the same steps with the broad phase at every step ("without Verlet
               buffer"), and Eq. impr between the two;
   cpu_baseline the FP64 oracle on a bounded sample of the same workload, one core.
@@ -167,8 +168,13 @@ def main():
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
 
-    wall, hist, pt, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, True)
+    # the throughput comes from a run without instrumentation; the kernel
+    # durations from an identical run with HIP events on every kernel (the
+    # events cost a few per cent of wall time)
+    wall, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False)
     value = n * args.steps / wall / 1e6
+    wall_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True)
+    assert np.array_equal(hist_ev["contacts"], hist["contacts"])
     rebuilt = hist["rebuilt"].astype(bool)            # [n_sys, steps]
     n_rebuild = int(rebuilt.sum())                     # broad phases over all systems
     any_rebuild = int(rebuilt.any(axis=0).sum())       # steps at which some system rebuilt
@@ -182,8 +188,10 @@ def main():
 
     plain = None
     if not args.no_plain:
-        wall_p, hist_p, pt_p, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
-                                           {"skin_mode": vb.VB_NO_BUFFER}, True)
+        wall_p, hist_p, _, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
+                                        {"skin_mode": vb.VB_NO_BUFFER}, False)
+        _, _, pt_p, _ = run_mode(vb, torch, systems, args.steps, 0,
+                                 {"skin_mode": vb.VB_NO_BUFFER}, True)
         plain = {
             "time_s": wall_p,
             "value": n * args.steps / wall_p / 1e6,
@@ -237,7 +245,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step", "bytes_per_launch": bytes_per_launch,
-                     "mean_launch_us": step_ms * 1e3, "copy_bandwidth_gbs": copy_gbs},
+                     "mean_launch_us": step_ms * 1e3, "copy_bandwidth_gbs": copy_gbs,
+                     "events_run_ms": wall_ev * 1e3},
         "broad_phases": n_rebuild,
         "executed_broad_phase_pct": report.executed_fraction(n_rebuild, args.steps * len(systems)),
         "broad_phase_ms_total": pt["ms_rebuild"],
