@@ -430,3 +430,82 @@ def test_friction_parameters_are_checked():
     for bad in ({"mu": -0.1}, {"kt": float("nan"), "mu": 0.3}, {"contact_capacity": 65}):
         with pytest.raises(vb.VbError):
             vb.vb_create(dict(s.params, **bad), s.n)
+
+
+# ---------------------------------------------------------------- degenerate cases
+def test_particles_at_rest_on_gpu():
+    """v = 0 (Eq. skin_formulus1 gives skin 0): one broad phase at step 0, none
+    after, nothing moves, and the list is exactly the pairs within
+    R_C,i + R_C,j + eps (brute force); exactly touching spheres (delta = 0, the
+    spacing of this lattice without jitter) feel no force."""
+    s = synth.lattice_system(16, 12, 8, 0, 0, 0.0, seed=9)
+    h = 2.0 ** -5                                     # dyadic spacing: distances are exact
+    idx = np.round(s.pos_r[:, :3] / s.meta["a"]) - 1.0
+    s.pos_r[:, :3] = (idx + 1.0) * h
+    s.pos_r[:, 3] = 0.5 * h                           # neighbours exactly touching
+    x, v, rc, invm = host_arrays([s])
+    with GpuRun([s]) as g:
+        hist = g.run(60)
+        xo, vo, _ = g.state()
+        lst, _ = g.pairs(0, 0)
+        con, _ = g.pairs(0, 1)
+    say(f"at rest: {hist[0]['rebuilt'].sum()} broad phases, list {len(lst)}, contacts {len(con)}")
+    assert hist[0]["rebuilt"].tolist() == [1] + [0] * 59
+    assert np.array_equal(xo, x.astype(np.float32).astype(np.float64)) and not vo.any()
+    assert len(con) == 0 and hist[0]["contacts"].max() == 0
+    ref = oracle.broadphase_brute(xo, rc, s.params["eps"])
+    assert np.array_equal(lst, ref)
+
+
+def test_cell_face_placements_broad_phase():
+    """Particles placed exactly on cell faces and corners (dyadic coordinates on
+    the cell grid): the GPU list contains every pair the oracle's brute-force
+    broad phase finds with a margin, and nothing beyond the eps band."""
+    import paper_2208_13770_amd as vb
+    rng = np.random.default_rng(11)
+    edge = 2.0 ** -4                      # 16 cells per axis: L_C (1 + 2^-10) + 2 eps <= 1/16
+    L_C = (edge - 4.5e-6) / (1 + 2.0 ** -10)
+    n = 3000
+    x = rng.integers(2, 30, size=(n, 3)) * (edge / 2)   # cell faces, edges, corners, centres
+    x = np.unique(x, axis=0)[:1500]
+    n = len(x)
+    R = np.full(n, 2.0 ** -6)             # grid neighbours exactly touch
+    v = rng.normal(0, 1e-3, size=(n, 3))
+    p = {"skin_mode": 0, "cap_mode": 0, "K": 50.0, "dt": 2.0 ** -10, "cell_size": L_C,
+         "skin_uniform": 0.0, "eps": 2e-6, "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1e3,
+         "gamma_n": 0.0, "g": (0, 0, 0), "max_neighbors": 64}
+
+    class Sys:  # the minimal system object GpuRun needs
+        pass
+    s = Sys()
+    s.pos_r = np.concatenate([x, R[:, None]], axis=1).astype(np.float32)
+    s.vel_m = np.concatenate([v, np.ones((n, 1))], axis=1).astype(np.float32)
+    s.params = p
+    s.n = n
+    s.meta = {"v_max": 1e-3}
+    xh, vh, rc, invm = host_arrays([s])
+    with GpuRun([s]) as g:
+        g.pairs(0, 1)
+        gl, _ = g.pairs(0, 0)
+    rnl, _ = oracle.rebuild_radii(p, vh, rc)
+    eps = p["eps"]
+    ol = oracle.broadphase_brute(xh, rnl + 1e-6, eps)
+
+    def margin(q):
+        d = np.linalg.norm(xh[q[:, 0]] - xh[q[:, 1]], axis=1)
+        return rnl[q[:, 0]] + rnl[q[:, 1]] + eps - d
+    gset = set(map(tuple, gl.tolist()))
+    sure = ol[margin(ol) > 1e-6]
+    assert len(sure) > 100
+    assert not [t for t in map(tuple, sure.tolist()) if t not in gset]
+    assert (margin(gl) > -1e-6).all()
+
+
+def test_k_zero_parity():
+    """K = 0: every particle that moves violates at once, the broad phase runs at
+    (nearly) every step, and the results still match the oracle."""
+    s = synth.config_systems("M1", seed=8, scale=0.6)[0]
+    xg, vg, hg = gpu_trajectory([s], 120, K=0.0)
+    xo, vo, ho, _ = oracle_run(s, 120, K=0.0)
+    assert_close(s, xg, vg, xo, vo, "K=0")
+    assert hg[0]["rebuilt"].mean() > 0.9
