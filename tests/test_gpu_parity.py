@@ -509,3 +509,17 @@ def test_k_zero_parity():
     xo, vo, ho, _ = oracle_run(s, 120, K=0.0)
     assert_close(s, xg, vg, xo, vo, "K=0")
     assert hg[0]["rebuilt"].mean() > 0.9
+
+
+def test_pair_search_beyond_lds_capacity():
+    """Cells four lattice spacings wide hold ~64 particles each, so a brick's
+    neighbourhood (6^3 cells) holds ~14,000: far more than the pair search stages
+    in LDS, which then reads the bins directly.  Results and contacts still match
+    the oracle, and the bins (16 at first) are grown on the way."""
+    s = synth.lattice_system(24, 24, 24, 6, 3, 0.1, seed=12, K=5.0, cell_factor=4.0)
+    say(f"large cells: N={s.n}, cell {s.params['cell_size']:.4f}")
+    xg, vg, hg = gpu_trajectory([s], 120)
+    xo, vo, ho, _ = oracle_run(s, 120)
+    assert_close(s, xg, vg, xo, vo, "large cells")
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert ho["contacts"].max() > 50
