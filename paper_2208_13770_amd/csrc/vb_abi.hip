@@ -5,9 +5,11 @@
 // return at once unless some system's list went invalid at the previous step
 // (Def. autoverlet), and the fused step kernel.  The host never reads the
 // validity flag; it synchronises once per vb_run call, to collect the per-step
-// records and to check that no Verlet-list row or cell bin overflowed.  Every
-// reorder_interval steps (and after a state is loaded) the host also queues a
-// counting sort of the particle storage by cell, followed by a broad phase.
+// records and to check that no Verlet-list row, cell bin or friction history
+// overflowed.  Every reorder_interval steps (and after a state is loaded) the
+// host also queues a counting sort of the particle storage by cell, followed by
+// a broad phase.  Blocks of STATS_RING steps that need nothing from the host
+// run as one replayed HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -7,12 +7,14 @@
 //            with the local skin of Eq. skin_formulus1 capped as in Eq.
 //            skin_formulus_mincell, the reference positions x0, and the
 //            binning of the particles into the uniform cells of Alg. 1;
-//   k_pairs  the linked-cell pair search of Alg. 1 on those spheres, one thread
-//            per particle over the cells within `ring` cells, each row kept
-//            sorted by original index;
-//   k_step   narrow phase (Eq. delta), normal spring-dashpot contact force, walls,
-//            velocity-Verlet integration and the displacement test of Eq. update
-//            for the next step, fused, one thread per particle.
+//   k_pairs  the linked-cell pair search of Alg. 1 on those spheres, one
+//            workgroup per brick of cells with the brick's neighbourhood staged
+//            in LDS, one thread per particle, each row sorted by original index;
+//   k_step   narrow phase (Eq. delta), normal spring-dashpot contact force (and
+//            the tangential one with its per-contact history when friction is
+//            on), box and planar walls, gravity, velocity-Verlet integration and
+//            the displacement test of Eq. update for the next step, fused, one
+//            thread per particle.
 // Both broad-phase kernels return at once when no system needs a broad phase,
 // so the host never waits on the validity flag.  A counting sort of the particle
 // storage by cell (k_sort_*) runs when the host schedules it, for locality.
