@@ -141,8 +141,10 @@ vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const 
  * [n_sys][n_steps] records.  A Verlet-list row or a cell bin that overflows is
  * grown and the call's steps are run again from the call's starting state
  * (results unchanged).  Synchronises the stream once, at the end.
- * Errors: VB_ECAPACITY if a row needs more than 128 entries or a bin more than
- * 256, VB_ENOMEM, VB_EDEVICE. */
+ * Errors: VB_ECAPACITY if a row needs more than 128 entries, a bin more than 256
+ * or a friction history more than 64 contacts; VB_ENONFINITE if the state
+ * becomes NaN or infinite (the context then needs vb_set_state again);
+ * VB_ENOMEM, VB_EDEVICE. */
 vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 
 /* Copy the state out, original order: d_x [N][3] positions x^n and d_v [N][3]

@@ -733,6 +733,23 @@ static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
   return VB_OK;
 }
 
+// Step records from the device.  A state that left the finite numbers (a time
+// step far too large for the contact stiffness, say) shows in the kinetic
+// energy of its step; the context then holds no usable state.
+static vb_status read_records(vb_ctx *c, std::vector<vb_step_record> &rec, int32_t n_steps,
+                              int64_t step0) {
+  HIP_OK(c, hipMemcpy(rec.data(), c->hist_d, sizeof(vb_step_record) * rec.size(),
+                      hipMemcpyDeviceToHost));
+  for (int32_t r = 0; r < n_steps; ++r)
+    for (int s = 0; s < c->n_sys; ++s)
+      if (!std::isfinite(rec[(size_t)r * c->n_sys + s].kinetic_energy)) {
+        c->loaded = 0;
+        return fail(c, VB_ENONFINITE, "system " + std::to_string(s) + ": the kinetic energy "
+                                      "is not finite at step " + std::to_string(step0 + r));
+      }
+  return VB_OK;
+}
+
 extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) {
   if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
   if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded (vb_set_state)");
@@ -773,6 +790,10 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     if (ovf[0] <= c->width && ovf[1] <= c->bin_cap && ovf[2] <= c->hcap) break;
+    {  // a diverged state piles up in the outermost cells: report that, not the bins
+      std::vector<vb_step_record> rec((size_t)n_steps * c->n_sys);
+      if ((st = read_records(c, rec, n_steps, step0)) != VB_OK) return st;
+    }
     if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || ovf[2] > MAX_HIST || attempt >= 4) {
       c->loaded = 0;
       return fail(c, VB_ECAPACITY,
@@ -812,8 +833,7 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     c->force_pending = 1;
   }
   std::vector<vb_step_record> rec((size_t)n_steps * c->n_sys);
-  HIP_OK(c, hipMemcpy(rec.data(), c->hist_d, sizeof(vb_step_record) * rec.size(),
-                      hipMemcpyDeviceToHost));
+  if ((st = read_records(c, rec, n_steps, step0)) != VB_OK) return st;
   if (h_hist)
     for (int s = 0; s < c->n_sys; ++s)
       for (int32_t r = 0; r < n_steps; ++r)

@@ -290,6 +290,37 @@ def test_error_paths():
     torch.cuda.synchronize()
 
 
+def test_diverged_state_is_reported():
+    """A state that leaves the finite numbers during a call (here a velocity whose
+    kinetic energy overflows) is reported as VB_ENONFINITE; the context then needs
+    a new state, after which it runs as a fresh one does (bitwise)."""
+    import torch
+    import paper_2208_13770_amd as vb
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    say("diverged state: 100 steps with |v| = 1e160 for one particle")
+    x, v, rc, invm = vb.state_tensors([s])
+    vbad = v.clone()
+    vbad[5, 0] = 1e160
+    ctx = vb.vb_create(s.params, s.n)
+    try:
+        vb.vb_set_state(ctx, x, vbad, rc, invm)
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_run(ctx, 100)
+        assert e.value.code == vb.VB_ENONFINITE
+        assert "step 0" in str(e.value)
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_run(ctx, 1)
+        assert e.value.code == vb.VB_EINVAL
+        vb.vb_set_state(ctx, x, v, rc, invm)
+        vb.vb_run(ctx, 100)
+        xa, va = torch.empty_like(x), torch.empty_like(v)
+        vb.vb_get_state(ctx, xa, va)
+    finally:
+        vb.vb_destroy(ctx)
+    xb, vb2, _ = gpu_trajectory([s], 100)
+    assert np.array_equal(xa.cpu().numpy(), xb) and np.array_equal(va.cpu().numpy(), vb2)
+
+
 def test_bin_overflow_is_regrown():
     """Cell bins smaller than the cells' occupancy: the call grows them and reruns;
     results are bit-identical."""
