@@ -18,6 +18,8 @@ oracle.
 Prints ONE JSON line:
   value       whole-job throughput, Mparticle*step/s, of the method (K = 200) with
               the state resident in HBM (a run without instrumentation);
+  repeats     mean, spread and range of the wall time over --repeats such runs
+              (the first is the one `value` comes from);
   roofline    the step kernel's algorithmic bytes per launch over its mean duration,
               taken by HIP events on the kernel in an identical second run, against
               the 8 TB/s HBM peak;
@@ -146,6 +148,8 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="also run every system of the batch in its own context, in turn")
     ap.add_argument("--scale", type=float, default=1.0, help="lattice scale (1 = full size)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="runs of the same steps without instrumentation, for the spread of the wall time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method's "
@@ -173,6 +177,11 @@ def main():
     # events cost a few per cent of wall time)
     wall, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False)
     value = n * args.steps / wall / 1e6
+    walls = [wall]
+    for _ in range(max(args.repeats, 1) - 1):
+        w_r, h_r, _, _ = run_mode(vb, torch, systems, args.steps, 0, {}, False)
+        assert np.array_equal(h_r["contacts"], hist["contacts"])
+        walls.append(w_r)
     wall_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True)
     assert np.array_equal(hist_ev["contacts"], hist["contacts"])
     rebuilt = hist["rebuilt"].astype(bool)            # [n_sys, steps]
@@ -247,6 +256,9 @@ def main():
                      "kernel": "k_step", "bytes_per_launch": bytes_per_launch,
                      "mean_launch_us": step_ms * 1e3, "copy_bandwidth_gbs": copy_gbs,
                      "events_run_ms": wall_ev * 1e3},
+        "repeats": {"n": len(walls), "ms_mean": float(np.mean(walls)) * 1e3,
+                    "ms_std": float(np.std(walls, ddof=1)) * 1e3 if len(walls) > 1 else 0.0,
+                    "ms_min": min(walls) * 1e3, "ms_max": max(walls) * 1e3},
         "broad_phases": n_rebuild,
         "executed_broad_phase_pct": report.executed_fraction(n_rebuild, args.steps * len(systems)),
         "broad_phase_ms_total": pt["ms_rebuild"],
