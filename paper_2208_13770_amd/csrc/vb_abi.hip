@@ -316,7 +316,8 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   c->n_cu = prop.multiProcessorCount;
   c->lds_limit = prop.sharedMemPerBlock;
   c->lds_cu = std::max(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
-  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144) / (PAIRS_T * sizeof(uint16_t)));
+  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144 - pairs_lds_bytes(0, 0)) /
+                                                         (PAIRS_T * sizeof(uint16_t)));
   c->n_sys = n_sys;
   c->sys_h.resize(n_sys);
   c->sort_interval = h_params[0].reorder_interval;

@@ -611,11 +611,11 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int HALF = PAIRS_T / 2;
   const int W = a.width;
-  float4 *s_pos = reinterpret_cast<float4 *>(lds);                          // [pmax]
-  int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax);             // [pmax]
+  float4 *s_pos = reinterpret_cast<float4 *>(lds);                          // [pmax + 4]
+  int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax + 4);         // [pmax]
   int32_t *s_slot = s_key + a.pmax;                                         // [pmax]
   unsigned char *rows = reinterpret_cast<unsigned char *>(s_slot + a.pmax);
-  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W][PAIRS_T]
+  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W + 1][PAIRS_T]
   int32_t *s_row32 = reinterpret_cast<int32_t *>(rows);                     // [W][HALF]
   __shared__ int s_cnt[8 * 8 * 8];
   __shared__ int s_off[8 * 8 * 8 + 1];
@@ -715,34 +715,32 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
           const float reach = me.w + S.eps;
           k = S.p_off + s_slot[me_e];
           // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
-          // row of the neighbourhood are one contiguous range of staged entries
+          // row of the neighbourhood are one contiguous range of staged entries.
+          // The range is read four entries at a time (up to three past its end:
+          // the staged array has four spare entries), and the test has no
+          // branch: every entry is written at the row's end, and the row grows
+          // only by the entries that pass (row W is a spare row for overflow).
+          uint16_t *myrow = s_row16 + tid;
+          const unsigned wend = (unsigned)W * PAIRS_T;
+          unsigned wofs = 0;  // count * PAIRS_T
           for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy) {
               const int vrow = v + (dz * E + dy) * E;
               const int e1 = s_off[vrow + r + 1];
-              int e = s_off[vrow - r];
-              for (; e + 4 <= e1; e += 4) {
+              for (int e = s_off[vrow - r]; e < e1; e += 4) {
                 const float4 o[4] = {s_pos[e], s_pos[e + 1], s_pos[e + 2], s_pos[e + 3]};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                   const float ex = me.x - o[u].x, ey = me.y - o[u].y, ez = me.z - o[u].z;
                   const float lim = reach + o[u].w;
-                  if (e + u != me_e && ex * ex + ey * ey + ez * ez <= lim * lim) {
-                    if (count < W) s_row16[count * PAIRS_T + tid] = (uint16_t)(e + u);
-                    ++count;
-                  }
-                }
-              }
-              for (; e < e1; ++e) {
-                const float4 o = s_pos[e];
-                const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
-                const float lim = reach + o.w;
-                if (e != me_e && ex * ex + ey * ey + ez * ez <= lim * lim) {
-                  if (count < W) s_row16[count * PAIRS_T + tid] = (uint16_t)e;
-                  ++count;
+                  const bool hit = (ex * ex + ey * ey + ez * ez <= lim * lim) & (e + u < e1) &
+                                   (e + u != me_e);
+                  myrow[min(wofs, wend)] = (uint16_t)(e + u);
+                  wofs += hit ? PAIRS_T : 0;
                 }
               }
             }
+          count = (int)(wofs / PAIRS_T);
           const int kept = count < W ? count : W;
           int32_t *out = a.nbr + k;
           // one sort for the whole wave, sized by its longest row (no divergence)
@@ -1137,12 +1135,13 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
   return hipGetLastError();
 }
 
-// Dynamic LDS of k_pairs: staged candidates (position and R_NL, original index,
-// slot) and the rows (16-bit staged indices, or 32-bit keys for half the
-// threads in the fallback path: the same bytes).
+// Dynamic LDS of k_pairs: staged candidates (position and R_NL with four spare
+// entries for the scan's reads past a range, original index, slot) and the rows
+// (W + 1 rows of 16-bit staged indices, the last a spare for full rows, or W
+// rows of 32-bit keys for half the threads in the fallback path).
 size_t pairs_lds_bytes(int width, int pmax) {
-  return (size_t)pmax * (sizeof(float4) + 2 * sizeof(int32_t)) +
-         (size_t)PAIRS_T * (size_t)width * sizeof(uint16_t);
+  return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * 2 * sizeof(int32_t) +
+         (size_t)PAIRS_T * (size_t)(width + 1) * sizeof(uint16_t);
 }
 
 // t0 takes the start of the binning kernel, t1 the end of the pair search
