@@ -539,10 +539,10 @@ __device__ __forceinline__ int row_insert(int32_t *s_row, int ld, int count, int
   return count + 1;
 }
 
-// Bitonic sort of N (key, value) pairs held in registers (all indices are
-// compile-time constants after unrolling), ascending by key.
+// Bitonic sort of N keys held in registers (all indices are compile-time
+// constants after unrolling), ascending.
 template <int N>
-__device__ __forceinline__ void bitonic_sort(int32_t (&key)[N], int32_t (&val)[N]) {
+__device__ __forceinline__ void bitonic_sort(int32_t (&key)[N]) {
 #pragma unroll
   for (int kk = 2; kk <= N; kk <<= 1)
 #pragma unroll
@@ -551,33 +551,31 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&key)[N], int32_t (&val)[N
       for (int i = 0; i < N; ++i) {
         const int l = i ^ j;
         if (l > i) {
+          const int32_t lo = min(key[i], key[l]), hi = max(key[i], key[l]);
           const bool up = (i & kk) == 0;
-          const int32_t ki = key[i], kl = key[l], vi = val[i], vl = val[l];
-          const bool sw = up ? ki > kl : ki < kl;
-          key[i] = sw ? kl : ki;
-          key[l] = sw ? ki : kl;
-          val[i] = sw ? vl : vi;
-          val[l] = sw ? vi : vl;
+          key[i] = up ? lo : hi;
+          key[l] = up ? hi : lo;
         }
       }
 }
 
 // Writes this thread's row of n <= N staged-entry indices (column threadIdx.x
 // of a [.][PAIRS_T] LDS array) to the Verlet list as slots, ordered by original
-// index; the sort runs in registers.
+// index: the original indices are sorted in registers, then turned into slots
+// through inv (inv[orig] = slot of the system's particle orig).
 template <int N>
 __device__ __forceinline__ void row_write_sorted(const uint16_t *s_row, const int32_t *s_key,
-                                                 const int32_t *s_slot, int n, int32_t *out,
-                                                 int64_t stride) {
-  int32_t key[N], val[N];
+                                                 const int32_t *__restrict__ inv, int n,
+                                                 int32_t *out, int64_t stride) {
+  int32_t key[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) val[q] = q < n ? s_row[q * PAIRS_T + threadIdx.x] : 0;
+  for (int q = 0; q < N; ++q) key[q] = q < n ? s_key[s_row[q * PAIRS_T + threadIdx.x]] : INT32_MAX;
+  bitonic_sort<N>(key);
 #pragma unroll
-  for (int q = 0; q < N; ++q) key[q] = q < n ? s_key[val[q]] : INT32_MAX;
-  bitonic_sort<N>(key, val);
+  for (int q = 0; q < N; ++q) key[q] = q < n ? inv[key[q]] : 0;
 #pragma unroll
   for (int q = 0; q < N; ++q)
-    if (q < n) out[(int64_t)q * stride] = s_slot[val[q]];
+    if (q < n) out[(int64_t)q * stride] = key[q];
 }
 
 // The same for a row of any length up to W: insertion sort in LDS.
@@ -744,10 +742,13 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
           const int kept = count < W ? count : W;
           int32_t *out = a.nbr + k;
           // one sort for the whole wave, sized by its longest row (no divergence)
+          const int32_t *inv = a.inv + S.p_off;
           if (!__any(kept > 8))
-            row_write_sorted<8>(s_row16, s_key, s_slot, kept, out, a.stride);
+            row_write_sorted<8>(s_row16, s_key, inv, kept, out, a.stride);
           else if (!__any(kept > 16))
-            row_write_sorted<16>(s_row16, s_key, s_slot, kept, out, a.stride);
+            row_write_sorted<16>(s_row16, s_key, inv, kept, out, a.stride);
+          else if (!__any(kept > 32))
+            row_write_sorted<32>(s_row16, s_key, inv, kept, out, a.stride);
           else
             row_write_sorted_lds(s_row16, s_key, s_slot, kept, out, a.stride);
         } else {
