@@ -29,6 +29,7 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
 hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st,
                               hipEvent_t t0, hipEvent_t t1);
 size_t pairs_lds_bytes(int width, int pmax);
+int pairs_blocks_per_cu(int width, int pmax);
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 int64_t scan_blocks(int64_t n_cells);
 hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
@@ -239,6 +240,11 @@ static vb_status alloc_rows(vb_ctx *c, int32_t width) {
   const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - 6144,
                                            std::max<int64_t>((int64_t)c->lds_cu / 2 - 5120, rows + 1024 * 24));
   c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
+  // the pair search walks the bricks grid-stride with exactly the workgroups
+  // that are resident at once, so that at any time they work on one window of
+  // consecutive bricks, whose staged neighbourhoods overlap in L2
+  c->pairs_grid = (int)std::max<int64_t>(
+      1, std::min<int64_t>(c->n_bricks, (int64_t)pairs_blocks_per_cu(width, c->pmax) * c->n_cu));
   return VB_OK;
 }
 
@@ -395,7 +401,6 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   // the broad-phase kernels walk the tiles grid-stride from a bounded grid, so
   // that a step without broad phase costs two short launches
   c->broad_grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_tiles, 8LL * c->n_cu));
-  c->pairs_grid = (int)std::max<int64_t>(1, std::min<int64_t>(c->n_bricks, 8LL * c->n_cu));
   std::vector<int32_t> ts(std::max<int64_t>(c->n_tiles, 1), 0);
   for (int s = 0; s < n_sys; ++s)
     for (int t = 0; t < c->sys_h[s].n_tiles; ++t) ts[c->sys_h[s].tile_off + t] = s;

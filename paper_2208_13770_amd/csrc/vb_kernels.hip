@@ -597,6 +597,36 @@ __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int3
   for (int q = 0; q < n; ++q) out[(int64_t)q * stride] = s_slot[s_row[q * PAIRS_T + threadIdx.x]];
 }
 
+// Four staged entries e..e+3 against the particle `me` (position and R_NL +
+// eps): each entry index is written at the row's end (offset wofs, capped at
+// the spare row wend), and the row grows by PAIRS_T for each entry within
+// reach.  TAIL masks entries at or past e1; OWN masks the particle's own entry.
+template <bool TAIL, bool OWN>
+__device__ __forceinline__ void pair_test4(const float4 *s_pos, int e, int e1, int me_e,
+                                           const float4 &me, float reach, uint16_t *myrow,
+                                           unsigned wend, unsigned &wofs) {
+  const float4 o[4] = {s_pos[e], s_pos[e + 1], s_pos[e + 2], s_pos[e + 3]};
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const float ex = me.x - o[u].x, ey = me.y - o[u].y, ez = me.z - o[u].z;
+    const float lim = reach + o[u].w;
+    bool hit = ex * ex + ey * ey + ez * ez <= lim * lim;
+    if (TAIL) hit = hit && e + u < e1;
+    if (OWN) hit = hit && e + u != me_e;
+    myrow[min(wofs, wend)] = (uint16_t)(e + u);
+    wofs += hit ? PAIRS_T : 0;
+  }
+}
+
+// The staged range [e, e1): groups of four, the last one masked.
+template <bool OWN>
+__device__ __forceinline__ void pair_scan_range(const float4 *s_pos, int e, int e1, int me_e,
+                                                const float4 &me, float reach, uint16_t *myrow,
+                                                unsigned wend, unsigned &wofs) {
+  for (; e + 4 <= e1; e += 4) pair_test4<false, OWN>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
+  if (e < e1) pair_test4<true, OWN>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
+}
+
 // Alg. 1 on the extended spheres, one workgroup per brick of cells: the bins of
 // the brick and of the cells within `ring` cells around it are staged in LDS,
 // then every particle of the brick is tested against the particles of the cells
@@ -714,29 +744,23 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
           k = S.p_off + s_slot[me_e];
           // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
           // row of the neighbourhood are one contiguous range of staged entries.
-          // The range is read four entries at a time (up to three past its end:
-          // the staged array has four spare entries), and the test has no
-          // branch: every entry is written at the row's end, and the row grows
-          // only by the entries that pass (row W is a spare row for overflow).
+          // The test has no branch: every entry is written at the row's end,
+          // and the row grows only by the entries that pass (row W is a spare
+          // row for overflow).  Ranges are read four entries at a time; the
+          // last group of a range is masked (reads past its end stay inside
+          // the staged array, which has four spare entries), and only the
+          // particle's own row of cells can hold the particle itself.
           uint16_t *myrow = s_row16 + tid;
           const unsigned wend = (unsigned)W * PAIRS_T;
           unsigned wofs = 0;  // count * PAIRS_T
           for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy) {
               const int vrow = v + (dz * E + dy) * E;
-              const int e1 = s_off[vrow + r + 1];
-              for (int e = s_off[vrow - r]; e < e1; e += 4) {
-                const float4 o[4] = {s_pos[e], s_pos[e + 1], s_pos[e + 2], s_pos[e + 3]};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                  const float ex = me.x - o[u].x, ey = me.y - o[u].y, ez = me.z - o[u].z;
-                  const float lim = reach + o[u].w;
-                  const bool hit = (ex * ex + ey * ey + ez * ez <= lim * lim) & (e + u < e1) &
-                                   (e + u != me_e);
-                  myrow[min(wofs, wend)] = (uint16_t)(e + u);
-                  wofs += hit ? PAIRS_T : 0;
-                }
-              }
+              const int e0 = s_off[vrow - r], e1 = s_off[vrow + r + 1];
+              if (dz == 0 && dy == 0)
+                pair_scan_range<true>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
+              else
+                pair_scan_range<false>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
             }
           count = (int)(wofs / PAIRS_T);
           const int kept = count < W ? count : W;
@@ -1143,6 +1167,15 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
 size_t pairs_lds_bytes(int width, int pmax) {
   return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * 2 * sizeof(int32_t) +
          (size_t)PAIRS_T * (size_t)(width + 1) * sizeof(uint16_t);
+}
+
+// Workgroups of the pair search resident on one CU at once (at least 1).
+int pairs_blocks_per_cu(int width, int pmax) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs, PAIRS_T, pairs_lds_bytes(width, pmax)) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
 }
 
 // t0 takes the start of the binning kernel, t1 the end of the pair search
