@@ -52,8 +52,8 @@ typedef int32_t vb_status;
 #define VB_EINVAL (-1)      /* invalid argument or parameter                       */
 #define VB_ENOMEM (-2)      /* device or host allocation failed                    */
 #define VB_EDEVICE (-3)     /* a HIP call failed                                   */
-#define VB_ECAPACITY (-4)   /* a list row overflowed and could not be grown        */
-#define VB_ENONFINITE (-5)  /* NaN or Inf in the state                             */
+#define VB_ECAPACITY (-4)   /* a list row, cell bin or friction history exceeded its maximum */
+#define VB_ENONFINITE (-5)  /* NaN or Inf in the state given, or reached during a run */
 
 /* How the broad-phase sphere of each particle is extended. */
 #define VB_SKIN_LOCAL 0     /* skin_p = K |v_p| dt, the paper's local skin (Eq. skin_formulus1)  */
@@ -131,8 +131,8 @@ vb_status vb_batch_create(const vb_params *h_params, const int64_t *h_n, int32_t
  *   d_rc   [N]    FP32 cut-off (contact) radius R_C > 0, with 2 R_C <= L_C (cap 0)
  *                 or R_C <= L_C (cap 1)
  *   d_invm [N]    FP32 inverse mass > 0
- * The step counter restarts at 0 and the next step runs a broad phase (R7: the
- * method assumes an initial broad phase).  Synchronises the stream.
+ * The step counter restarts at 0 and the next step runs a broad phase (the
+ * proof of Sec. 4.2 starts from one).  Synchronises the stream.
  * Errors: VB_ENONFINITE for NaN/Inf, VB_EINVAL for a radius or mass out of range. */
 vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const float *d_rc,
                        const float *d_invm, int32_t v_is_half_step);

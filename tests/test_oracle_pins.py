@@ -5,6 +5,8 @@ the oracle with itself by retyping its formulas: they use the theorem of Sec. 4.
 (results identical to the broad phase at every step), brute force, closed-form
 cadences, exact dyadic kinematics, textbook spring-dashpot solutions,
 conservation laws, symmetry, and the numbers printed in Tab. summary.
+Labels R1 to R13 name the readings of the paper listed in the header of
+oracle/orc.c.
 """
 import json
 import os
@@ -31,7 +33,7 @@ def colliding(seed=0, poly=False):
     return synth.lattice_system(8, 8, 6, 3, 2, 0.3, seed, polydisperse=poly)
 
 
-# ---------------------------------------------------------------- P1, P2
+# ---------------------------------------------------------------- exactness, list superset
 @pytest.mark.parametrize("seed", [0, 1])
 @pytest.mark.parametrize("mode,K,cap", [
     (0, 0.0, 0), (0, 10.0, 0), (0, 200.0, 0), (0, 5000.0, 0),
@@ -69,7 +71,7 @@ def test_k_zero_rebuilds_whenever_anything_moves(orc):
     assert h["rebuilt"].all()
 
 
-# ---------------------------------------------------------------- P3
+# ---------------------------------------------------------------- Alg. 1 completeness
 def _cell_edge_min(L_C, eps):
     return L_C * (1.0 + 1e-9) + eps
 
@@ -147,7 +149,7 @@ def test_literal_cap_needs_two_rings(orc):
     assert np.array_equal(two, bf)
 
 
-# ---------------------------------------------------------------- P4 cadence
+# ---------------------------------------------------------------- closed-form cadences
 @pytest.mark.parametrize("K", [0, 1, 7, 50, 200])
 def test_free_flight_cadence(orc, K):
     """Sec. 4.1 and Sec. 5.1: K is the number of skipped steps; with skin_p = K|v_p|dt
@@ -224,7 +226,7 @@ def test_constant_gravity_exact(orc):
         assert np.array_equal(vo[0], v0[0] + (n - 0.5) * dt * g)
 
 
-# ---------------------------------------------------------------- P5, R4
+# ---------------------------------------------------------------- fixed interval, capped skin (R4)
 def _two_body(v_b, gap, p_extra):
     """Particle A at rest, particle B approaching it along x."""
     R = 2.0 ** -6
@@ -263,7 +265,7 @@ def test_uncapped_skin_in_validity_test_breaks_theorem(orc):
     assert bad["missed"].sum() > 0
 
 
-# ---------------------------------------------------------------- P7, P8
+# ---------------------------------------------------------------- contact law
 def test_touching_spheres_exert_no_force(orc):
     """Eq. delta: the particles collide only if the overlap is positive; exactly
     touching spheres (delta = 0) are not in contact and feel no force."""
@@ -386,7 +388,7 @@ def test_walls_push_inward(orc):
     assert np.allclose(F, expect, rtol=0, atol=1e-15)
 
 
-# ---------------------------------------------------------------- P10
+# ---------------------------------------------------------------- Tab. summary formulas
 def test_summary_table_formulas():
     """Eq. impr and the overhead column reproduce Tab. summary (Sec. 5.4).  The
     printed improvements differ from the recomputed ones by up to 0.021 (Avalanche,
