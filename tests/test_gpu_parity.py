@@ -554,3 +554,28 @@ def test_pair_search_beyond_lds_capacity():
     assert_close(s, xg, vg, xo, vo, "large cells")
     assert np.array_equal(hg[0]["contacts"], ho["contacts"])
     assert ho["contacts"].max() > 50
+
+
+def test_long_rows_sorted_like_short_ones():
+    """Rows of 33 to 43 entries (cells of about 2.1 lattice spacings, K = 5000, so
+    every moving particle's sphere reaches the cap): the pair search sorts such
+    rows with its longest register network and in LDS.  The rows must really be
+    that long, and K = 5000 must still equal the broad phase at every step bit
+    for bit (Sec. 4.2), which holds only if every row is in canonical order."""
+    s = synth.lattice_system(18, 18, 18, 3, 2, 0.2, 5, cell_factor=2.2, K=5000.0,
+                             max_neighbors=64)
+    say(f"long rows: N={s.n}, 120 steps, K=5000 vs no buffer")
+    with GpuRun([s]) as g:
+        g.run(1)
+        pairs, _ = g.pairs(0, 0)
+    deg = np.bincount(pairs.ravel(), minlength=s.n)
+    say(f"  longest row {int(deg.max())}, rows over 32: {int((deg > 32).sum())}")
+    assert deg.max() > 32 and (deg > 32).sum() > 1000
+    xa, va, ha = gpu_trajectory([s], 120)
+    xb, vb_, hb = gpu_trajectory([s], 120, skin_mode=2)
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb_)
+    assert np.array_equal(ha[0]["contacts"], hb[0]["contacts"])
+    assert ha[0]["rebuilt"].sum() < hb[0]["rebuilt"].sum()
+    xo, vo, ho, _ = oracle_run(s, 120)
+    assert_close(s, xa, va, xo, vo, "long rows")
+    assert np.array_equal(ha[0]["contacts"], ho["contacts"])
