@@ -40,7 +40,7 @@ results = []
 survivors = 0
 for name, a, b in MUT:
     if os.path.exists(dst): shutil.rmtree(os.path.dirname(dst))
-    shutil.copytree(SRC, dst, ignore=shutil.ignore_patterns('.git', '_work', 'gpurun_out', '*.so', '__pycache__'))
+    shutil.copytree(SRC, dst, ignore=shutil.ignore_patterns('.git', '_work', '*_out', '*.so', '__pycache__'))
     p = os.path.join(dst, 'oracle/orc.c')
     s = open(p).read()
     assert a in s, name

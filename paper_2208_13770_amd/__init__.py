@@ -100,7 +100,7 @@ def lib():
         import torch  # noqa: F401  (loads the HIP runtime the library must share)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              "python -c 'import __graft_entry__ as g; g.build()'")
+                              "python -m paper_2208_13770_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(L, name)

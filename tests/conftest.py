@@ -9,7 +9,7 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
-    config.addinivalue_line("markers", "gpu: needs an MI355X (run through the GPU box)")
+    config.addinivalue_line("markers", "gpu: needs an AMD Instinct MI355X")
     config.addinivalue_line("markers", "slow: long CPU test")
 
 
