@@ -152,6 +152,34 @@ vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
  * Either pointer may be NULL.  *h_v_is_half_step (if not NULL) tells which. */
 vb_status vb_get_state(vb_ctx *ctx, double *d_x, double *d_v, int32_t *h_v_is_half_step);
 
+/* The friction history, for a checkpoint that resumes exactly: the contacts of
+ * the last step with their tangential springs (the state a frictional step
+ * carries besides positions and velocities; Sec. 5.1 names static friction,
+ * whose spring lasts as long as its contact).  In original order, all systems
+ * concatenated:
+ *   d_partner [N][cap] int32: particle g's partners (original index local to its
+ *             system), ascending, then -1 after the last one
+ *   d_spring  [N][cap][3] FP64: the spring of each of those contacts as seen
+ *             from particle g (0 after the last one)
+ * Systems without friction export no contacts.  *h_needed (may be NULL)
+ * receives the largest contact count of any particle.  Synchronises the stream.
+ * Errors: VB_EINVAL if no system has friction or no state is loaded;
+ * VB_ECAPACITY if a particle has more than cap contacts (then only the first
+ * cap of each are written). */
+vb_status vb_get_history(vb_ctx *ctx, int32_t *d_partner, double *d_spring, int32_t cap,
+                         int32_t *h_needed);
+
+/* Load a friction history in the layout of vb_get_history, right after
+ * vb_set_state and before any vb_run: with the state and the history of a
+ * checkpoint (vb_get_state, vb_get_history; v_is_half_step = 1), the run goes on
+ * bit for bit as the uninterrupted one.  Without it a resumed run starts every
+ * spring at zero.  Tables grow to the largest count.  Synchronises the stream.
+ * Errors: VB_EINVAL if no system has friction, if a step ran since vb_set_state,
+ * or for a partner out of range, equal to the particle or out of order;
+ * VB_ENONFINITE for a spring with NaN or Inf; VB_ECAPACITY beyond 64 contacts. */
+vb_status vb_set_history(vb_ctx *ctx, const int32_t *d_partner, const double *d_spring,
+                         int32_t cap);
+
 /* The canonical unique list of one system as pairs (i, j), i < j, in original
  * indices local to the system, sorted lexicographically:
  *   which = 0: the Verlet list of the last broad phase (Def. verletlist);

@@ -68,6 +68,8 @@ _SIGNATURES = {
     "vb_get_state": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
     "vb_get_pairs": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "vb_get_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "vb_set_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32]),
     "vb_force_rebuild": (ctypes.c_int32, [_P]),
     "vb_set_K": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_double]),
     "vb_set_timing": (ctypes.c_int32, [_P, ctypes.c_int32]),
@@ -195,6 +197,27 @@ def vb_get_pairs(ctx, sys, which, pairs=None, delta=None):
                               delta.data_ptr() if delta is not None else None, cap,
                               ctypes.byref(n)), ctx)
     return int(n.value)
+
+
+def vb_get_history(ctx, partner=None, spring=None):
+    """Fills partner (int32 [N, cap]) and spring (float64 [N, cap, 3]) device
+    tensors with the friction history; returns the largest contact count.  Call
+    with partner=None to get the count only."""
+    cap = int(partner.shape[1]) if partner is not None else 0
+    need = ctypes.c_int32(0)
+    code = lib().vb_get_history(ctx, partner.data_ptr() if partner is not None else None,
+                                spring.data_ptr() if spring is not None else None, cap,
+                                ctypes.byref(need))
+    if code == VB_ECAPACITY and partner is None:
+        return int(need.value)
+    _check(code, ctx)
+    return int(need.value)
+
+
+def vb_set_history(ctx, partner, spring):
+    """Loads a friction history (the tensors of vb_get_history) right after
+    vb_set_state."""
+    _check(lib().vb_set_history(ctx, partner.data_ptr(), spring.data_ptr(), int(partner.shape[1])), ctx)
 
 
 def vb_force_rebuild(ctx):

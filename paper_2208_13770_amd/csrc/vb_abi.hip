@@ -30,6 +30,15 @@ hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, 
                               hipEvent_t t0, hipEvent_t t1);
 size_t pairs_lds_bytes(int width, int pmax);
 int pairs_blocks_per_cu(int width, int pmax);
+hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                              const PX *px, const HistEntry *hist, const int32_t *hcnt,
+                              int64_t stride, int32_t hcap, int32_t *partner, double *spring,
+                              int32_t cap, int32_t *needed, hipStream_t st);
+hipError_t launch_check_history(const SysDev &S, const int32_t *partner, const double *spring,
+                                int32_t cap, int32_t *needed, int32_t *err, hipStream_t st);
+hipError_t launch_set_history(const SysDev &S, const int32_t *partner, const double *spring,
+                              int32_t cap, HistEntry *hist, int32_t *hcnt, int64_t stride,
+                              hipStream_t st);
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
 int64_t scan_blocks(int64_t n_cells);
 hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
@@ -109,6 +118,7 @@ struct vb_ctx {
   int64_t next_sort = 0;       // step at which the storage is re-sorted next (-1: never)
   int32_t sort_interval = 0;
   int loaded = 0;
+  int fresh = 0;               // a state was loaded and no step has run since
   int xcd_remap = 0;
   int step_unroll = 8;
   // replay of STATS_RING steps as one HIP graph (launch-bound small systems);
@@ -437,7 +447,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->go, n_sys);
   ALLOC(c->overflow, 3);
   ALLOC(c->step_base_d, 1);
-  ALLOC(c->err, 1);
+  ALLOC(c->err, 2);
   ALLOC(c->stats, (int64_t)STATS_RING * std::max<int64_t>(c->n_tiles, 1));
   ALLOC(c->rebuilt_ring, (int64_t)STATS_RING * n_sys);
   ALLOC(c->pair_counts, std::max<int32_t>(c->max_n, 1));
@@ -518,6 +528,7 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
   c->force_pending = 1;
   c->next_sort = 0;
   c->loaded = 1;
+  c->fresh = 1;
   return VB_OK;
 }
 
@@ -762,6 +773,7 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
   if (n_steps < 0) return fail(c, VB_EINVAL, "n_steps < 0");
   if (n_steps == 0) return VB_OK;
   if (c->step + n_steps > (int64_t)INT32_MAX) return fail(c, VB_EINVAL, "step counter overflow");
+  c->fresh = 0;
   vb_status st;
   if ((st = alloc_hist(c, n_steps)) != VB_OK) return st;
   if (!c->snap_px) {
@@ -868,6 +880,62 @@ extern "C" vb_status vb_get_state(vb_ctx *c, double *d_x, double *d_v,
                              d_x, d_v, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (h_v_is_half_step) *h_v_is_half_step = c->first ? 0 : 1;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_history(vb_ctx *c, int32_t *d_partner, double *d_spring, int32_t cap,
+                                    int32_t *h_needed) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->any_friction) return fail(c, VB_EINVAL, "no system of this context has friction");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded");
+  if (cap < 0 || (cap > 0 && (!d_partner || !d_spring)))
+    return fail(c, VB_EINVAL, "bad output buffers");
+  HIP_OK(c, launch_fill_i32(c->err, 1, 0, c->stream));
+  HIP_OK(c, launch_get_history(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], c->hist[c->cur],
+                               c->hcnt[c->cur], c->slots, c->hcap, d_partner, d_spring, cap,
+                               c->err, c->stream));
+  int32_t needed = 0;
+  HIP_OK(c, hipMemcpyAsync(&needed, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (h_needed) *h_needed = needed;
+  if (needed > cap)
+    return fail(c, VB_ECAPACITY, "a particle has " + std::to_string(needed) + " contacts, cap is " +
+                                     std::to_string(cap));
+  return VB_OK;
+}
+
+extern "C" vb_status vb_set_history(vb_ctx *c, const int32_t *d_partner, const double *d_spring,
+                                    int32_t cap) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->any_friction) return fail(c, VB_EINVAL, "no system of this context has friction");
+  if (!c->loaded || !c->fresh)
+    return fail(c, VB_EINVAL, "a history is loaded right after vb_set_state, before any step");
+  if (cap < 0 || (cap > 0 && (!d_partner || !d_spring))) return fail(c, VB_EINVAL, "bad input buffers");
+  if (cap == 0) return VB_OK;
+  // count and check first (err[0]: largest count, err[1]: faults), then grow
+  // the tables if they are too small, then load
+  HIP_OK(c, launch_fill_i32(c->err, 2, 0, c->stream));
+  for (int s = 0; s < c->n_sys; ++s)
+    if (c->sys_h[s].friction)
+      HIP_OK(c, launch_check_history(c->sys_h[s], d_partner, d_spring, cap, c->err, c->err + 1,
+                                     c->stream));
+  int32_t chk[2] = {0, 0};
+  HIP_OK(c, hipMemcpyAsync(chk, c->err, sizeof(chk), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (chk[1] & 1) return fail(c, VB_ENONFINITE, "a spring holds NaN or Inf");
+  if (chk[1] & 2)
+    return fail(c, VB_EINVAL, "a partner is out of range, the particle itself, or out of order");
+  if (chk[0] > MAX_HIST)
+    return fail(c, VB_ECAPACITY, "a particle has " + std::to_string(chk[0]) + " contacts (limit " +
+                                     std::to_string(MAX_HIST) + ")");
+  vb_status st;
+  if (chk[0] > c->hcap && (st = alloc_hist_tables(c, std::min(MAX_HIST, (chk[0] + 3) / 4 * 4))) != VB_OK)
+    return st;
+  for (int s = 0; s < c->n_sys; ++s)
+    if (c->sys_h[s].friction)
+      HIP_OK(c, launch_set_history(c->sys_h[s], d_partner, d_spring, cap, c->hist[c->cur],
+                                   c->hcnt[c->cur], c->slots, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
   return VB_OK;
 }
 

@@ -1024,6 +1024,83 @@ __global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const dou
   pv[S.p_off + i] = q;
 }
 
+// Friction history to the caller's original order: particle g's contacts of
+// the last step (partner ascending) in partner[g][0..cap), -1 after the last,
+// with their springs; *needed receives the largest count of any particle.
+__global__ void k_get_history(const SysDev *sys, const int32_t *tile_sys, const PX *px,
+                              const HistEntry *hist, const int32_t *hcnt, int64_t stride,
+                              int32_t hcap, int32_t *partner, double *spring, int32_t cap,
+                              int32_t *needed) {
+  const int64_t t = blockIdx.x;
+  const SysDev &S = sys[tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const int64_t g = S.o_off + px[k].orig;
+  const int n = S.friction ? min(hcnt[k], hcap) : 0;
+  if (n > 0) atomicMax(needed, n);
+  for (int c = 0; c < cap; ++c) {
+    int32_t who = -1;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (c < n) {
+      const HistEntry e = hist[(int64_t)c * stride + k];
+      who = (int32_t)e.orig;
+      sx = e.sx;
+      sy = e.sy;
+      sz = e.sz;
+    }
+    partner[g * cap + c] = who;
+    spring[3 * (g * cap + c)] = sx;
+    spring[3 * (g * cap + c) + 1] = sy;
+    spring[3 * (g * cap + c) + 2] = sz;
+  }
+}
+
+// Checks a history in original order for one system (partners ascending, in
+// the system, not the particle itself; springs finite) and takes the largest
+// count.  err: 1 for a spring that is not finite, 2 for a bad partner.
+__global__ void k_check_history(SysDev S, const int32_t *partner, const double *spring,
+                                int32_t cap, int32_t *needed, int32_t *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const int64_t g = S.o_off + i;
+  int n = 0, prev = -1, e = 0;
+  for (int c = 0; c < cap; ++c) {
+    const int32_t who = partner[g * cap + c];
+    if (who < 0) break;
+    if (who >= S.n || who == (int32_t)i || who <= prev) e |= 2;
+    const double *sp = spring + 3 * (g * cap + c);
+    if (!isfinite(sp[0]) || !isfinite(sp[1]) || !isfinite(sp[2])) e |= 1;
+    prev = who;
+    ++n;
+  }
+  if (n > 0) atomicMax(needed, n);
+  if (e) atomicOr(err, e);
+}
+
+// Loads a checked history into the tables of a state just loaded by
+// k_set_state (particle i of the system sits at slot p_off + i).
+__global__ void k_set_history(SysDev S, const int32_t *partner, const double *spring, int32_t cap,
+                              HistEntry *hist, int32_t *hcnt, int64_t stride) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const int64_t g = S.o_off + i, k = S.p_off + i;
+  int n = 0;
+  for (int c = 0; c < cap; ++c) {
+    const int32_t who = partner[g * cap + c];
+    if (who < 0) break;
+    HistEntry e;
+    e.sx = spring[3 * (g * cap + c)];
+    e.sy = spring[3 * (g * cap + c) + 1];
+    e.sz = spring[3 * (g * cap + c) + 2];
+    e.orig = (uint32_t)who;
+    e.pad = 0;
+    hist[(int64_t)c * stride + k] = e;
+    ++n;
+  }
+  hcnt[k] = n;
+}
+
 // Copy the state back to the caller's original order.
 __global__ void k_get_state(const SysDev *sys, const int32_t *tile_sys, const PX *px, const PV *pv,
                             double *x, double *v) {
@@ -1240,6 +1317,33 @@ hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t 
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_get_state, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
                      pv, x, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                              const PX *px, const HistEntry *hist, const int32_t *hcnt,
+                              int64_t stride, int32_t hcap, int32_t *partner, double *spring,
+                              int32_t cap, int32_t *needed, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_get_history, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
+                     hist, hcnt, stride, hcap, partner, spring, cap, needed);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_history(const SysDev &S, const int32_t *partner, const double *spring,
+                                int32_t cap, int32_t *needed, int32_t *err, hipStream_t st) {
+  if (S.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_history, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, st, S,
+                     partner, spring, cap, needed, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_history(const SysDev &S, const int32_t *partner, const double *spring,
+                              int32_t cap, HistEntry *hist, int32_t *hcnt, int64_t stride,
+                              hipStream_t st) {
+  if (S.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_history, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, st, S,
+                     partner, spring, cap, hist, hcnt, stride);
   return hipGetLastError();
 }
 

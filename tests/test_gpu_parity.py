@@ -609,3 +609,84 @@ def test_graph_replay_equals_eager_launches(name, scale, friction):
     finally:
         eager.close()
         graph.close()
+
+
+def test_checkpoint_resume_with_friction_history_bitwise():
+    """A frictional run checkpointed with its state and its friction history
+    (vb_get_history) and resumed in a new context (vb_set_history) continues
+    bit-identically; resumed without the history, every spring starts at zero
+    and the run departs from the uninterrupted one."""
+    import torch
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=8)[0]
+    fr = _frictional(s)
+    say(f"checkpoint/resume with friction: N={s.n}")
+    xa, va, _ = gpu_trajectory([s], 200, **fr)
+    with GpuRun([s], fr) as g:
+        g.run(120)
+        x1, v1, half = g.state()
+        assert half
+        need = vb.vb_get_history(g.ctx)
+        assert need > 0
+        partner = torch.empty((s.n, need + 1), dtype=torch.int32, device="cuda")
+        spring = torch.empty((s.n, need + 1, 3), dtype=torch.float64, device="cuda")
+        assert vb.vb_get_history(g.ctx, partner, spring) == need
+        small = torch.empty((s.n, need - 1), dtype=torch.int32, device="cuda")
+        small3 = torch.empty((s.n, need - 1, 3), dtype=torch.float64, device="cuda")
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_get_history(g.ctx, small, small3)
+        assert e.value.code == vb.VB_ECAPACITY
+    p = partner.cpu().numpy()
+    assert (p[:, -1] == -1).all() and (p >= -1).all()
+    say(f"  {int((p >= 0).sum())} contacts carried, at most {need} per particle")
+    xt, vt = torch.from_numpy(x1).cuda(), torch.from_numpy(v1).cuda()
+    with GpuRun([s], fr) as g:
+        vb.vb_set_state(g.ctx, xt, vt, g.rc, g.invm, v_is_half_step=True)
+        vb.vb_set_history(g.ctx, partner, spring)
+        g.run(80)
+        xb, vb2, _ = g.state()
+        with pytest.raises(vb.VbError) as e:  # only right after vb_set_state
+            vb.vb_set_history(g.ctx, partner, spring)
+        assert e.value.code == vb.VB_EINVAL
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb2)
+    with GpuRun([s], fr) as g:
+        vb.vb_set_state(g.ctx, xt, vt, g.rc, g.invm, v_is_half_step=True)
+        g.run(80)
+        xc, _, _ = g.state()
+    assert not np.array_equal(xa, xc)
+
+
+def test_history_input_is_checked():
+    import torch
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("H125", seed=3, scale=0.3)[0]
+    fr = _frictional(s)
+    say("history input checks")
+    partner = torch.full((s.n, 3), -1, dtype=torch.int32, device="cuda")
+    spring = torch.zeros((s.n, 3, 3), dtype=torch.float64, device="cuda")
+    with GpuRun([s]) as g:  # no friction
+        with pytest.raises(vb.VbError):
+            vb.vb_set_history(g.ctx, partner, spring)
+    with GpuRun([s], fr) as g:
+        vb.vb_set_history(g.ctx, partner, spring)  # an empty history is fine
+        for bad in ([5, 5], [7, 3], [0, s.n], [1, -1, 2]):
+            q = partner.clone()
+            q[0, :len(bad)] = torch.tensor(bad, dtype=torch.int32)
+            if bad == [1, -1, 2]:
+                vb.vb_set_history(g.ctx, q, spring)  # entries after -1 are ignored
+                continue
+            with pytest.raises(vb.VbError) as e:
+                vb.vb_set_history(g.ctx, q, spring)
+            assert e.value.code == vb.VB_EINVAL, bad
+        q = partner.clone()
+        q[1, 0] = 0
+        sp = spring.clone()
+        sp[1, 0, 2] = float("nan")
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_set_history(g.ctx, q, sp)
+        assert e.value.code == vb.VB_ENONFINITE
+        q = partner.clone()
+        q[0, 0] = 0  # the particle itself
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_set_history(g.ctx, q, spring)
+        assert e.value.code == vb.VB_EINVAL
