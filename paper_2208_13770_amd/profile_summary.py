@@ -8,6 +8,12 @@
       then WRITE_SIZE, KiB per dispatch).  Each counter is scaled by what it reads
       for the largest device-to-device copy in the same run (a plain copy kernel of
       known size, 4 GiB read + 4 GiB written by bench.py's bandwidth probe).
+  python -m paper_2208_13770_amd.profile_summary sq CSV [CSV ...] OUT.md --kernel k_pairs \
+      --cmd "..." [--cmd "..."]
+      instruction-mix counters (SQ_*) of one kernel from `rocprofv3 --pmc` runs,
+      averaged over the dispatches that did work (those issuing at least a tenth
+      of the busiest dispatch's VALU instructions; a broad-phase kernel that finds
+      nothing to do exits at once), with per-wave and per-lane ratios.
 """
 import argparse
 import csv
@@ -79,6 +85,54 @@ def traffic(args):
     json.dump(out, open(args.out, "w"), indent=1)
 
 
+def sq(args):
+    # each counter run is filtered and averaged on its own (dispatch ids of two
+    # runs need not correspond); a counter present in several runs is averaged
+    name, sums, n_busy, n_all = None, {}, [], []
+    for path in args.csv:
+        per = {}  # dispatch id -> counter -> value
+        for r in csv.DictReader(open(path)):
+            if args.kernel not in r["Kernel_Name"]:
+                continue
+            name = r["Kernel_Name"]
+            per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        if not per:
+            continue
+        valu_max = max(d.get("SQ_INSTS_VALU", 0.0) for d in per.values())
+        busy = [d for d in per.values() if d.get("SQ_INSTS_VALU", 0.0) >= 0.1 * valu_max]
+        n_busy.append(len(busy))
+        n_all.append(len(per))
+        for k in {k for d in busy for k in d}:
+            sums.setdefault(k, []).append(statistics.mean(d[k] for d in busy if k in d))
+    if not sums:
+        raise SystemExit(f"kernel {args.kernel} not found")
+    keys = sorted(sums)
+    mean = {k: statistics.mean(v) for k, v in sums.items()}
+    busy = n_busy
+    out = [f"# Instruction-mix counters: {args.title or name}", "",
+           *[f"Command: `{c}`" for c in args.cmd], "",
+           f"Kernel source sha256[:16]: {kernel_hash()}", "",
+           f"Kernel: `{name}`; dispatches that did work, per run: "
+           f"{', '.join(f'{b} of {t}' for b, t in zip(n_busy, n_all))} (averaged below).", "",
+           "| counter | mean per working dispatch |", "|---|---:|"]
+    out += [f"| {k} | {mean[k]:.4g} |" for k in keys]
+    waves = mean.get("SQ_WAVES")
+    ratios = []
+    if waves:
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD"):
+            if k in mean:
+                ratios.append((f"{k} per wave", mean[k] / waves))
+    if mean.get("SQ_ACTIVE_INST_VALU") and "SQ_THREAD_CYCLES_VALU" in mean:
+        ratios.append(("VALU lanes active (SQ_THREAD_CYCLES_VALU / 64 SQ_ACTIVE_INST_VALU)",
+                       mean["SQ_THREAD_CYCLES_VALU"] / (64.0 * mean["SQ_ACTIVE_INST_VALU"])))
+    if mean.get("SQ_ACTIVE_INST_LDS") and "SQ_LDS_BANK_CONFLICT" in mean:
+        ratios.append(("LDS bank-conflict cycles per active LDS instruction cycle",
+                       mean["SQ_LDS_BANK_CONFLICT"] / mean["SQ_ACTIVE_INST_LDS"]))
+    if ratios:
+        out += ["", "| ratio | value |", "|---|---:|"] + [f"| {k} | {v:.3g} |" for k, v in ratios]
+    open(args.out, "w").write("\n".join(out) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -94,8 +148,14 @@ def main():
     t.add_argument("--kernel", default="k_step")
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("csv", nargs="+")
+    q.add_argument("out")
+    q.add_argument("--kernel", default="k_pairs")
+    q.add_argument("--cmd", action="append", required=True)
+    q.add_argument("--title", default="")
     a = ap.parse_args()
-    stats(a) if a.what == "stats" else traffic(a)
+    {"stats": stats, "traffic": traffic, "sq": sq}[a.what](a)
 
 
 if __name__ == "__main__":
