@@ -37,6 +37,14 @@
  *     use from several host threads at once.
  *   - Units are the caller's; the synthetic workloads use box units (the longest
  *     box side is 1).
+ *   - Environment variables read at create, for tuning: VBUF_GRAPHS=0 (results
+ *     bit-identical) launches every step on its own instead of
+ *     replaying blocks of 64 steps as one captured HIP graph; VBUF_STEP_UNROLL
+ *     = 1, 2, 4 or 8 (default 8) sets the partner gathers each thread of the
+ *     step kernel keeps in flight; VBUF_XCD_REMAP=1 gives each of the 8 XCDs a
+ *     contiguous range of the step kernel's tiles.  A different VBUF_STEP_UNROLL
+ *     is different machine code, which may round the force arithmetic
+ *     differently in the last bits.
  */
 #ifndef VBUF_H
 #define VBUF_H
