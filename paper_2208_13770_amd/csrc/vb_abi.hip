@@ -36,7 +36,8 @@ hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_
                               int32_t cap, int32_t *needed, hipStream_t st);
 hipError_t launch_check_history(const SysDev &S, const int32_t *partner, const double *spring,
                                 int32_t cap, int32_t *needed, int32_t *err, hipStream_t st);
-hipError_t launch_set_history(const SysDev &S, const int32_t *partner, const double *spring,
+hipError_t launch_set_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                              const PX *px, const int32_t *partner, const double *spring,
                               int32_t cap, HistEntry *hist, int32_t *hcnt, int64_t stride,
                               hipStream_t st);
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
@@ -931,10 +932,8 @@ extern "C" vb_status vb_set_history(vb_ctx *c, const int32_t *d_partner, const d
   vb_status st;
   if (chk[0] > c->hcap && (st = alloc_hist_tables(c, std::min(MAX_HIST, (chk[0] + 3) / 4 * 4))) != VB_OK)
     return st;
-  for (int s = 0; s < c->n_sys; ++s)
-    if (c->sys_h[s].friction)
-      HIP_OK(c, launch_set_history(c->sys_h[s], d_partner, d_spring, cap, c->hist[c->cur],
-                                   c->hcnt[c->cur], c->slots, c->stream));
+  HIP_OK(c, launch_set_history(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], d_partner,
+                               d_spring, cap, c->hist[c->cur], c->hcnt[c->cur], c->slots, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return VB_OK;
 }

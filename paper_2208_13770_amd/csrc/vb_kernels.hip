@@ -1078,13 +1078,17 @@ __global__ void k_check_history(SysDev S, const int32_t *partner, const double *
   if (e) atomicOr(err, e);
 }
 
-// Loads a checked history into the tables of a state just loaded by
-// k_set_state (particle i of the system sits at slot p_off + i).
-__global__ void k_set_history(SysDev S, const int32_t *partner, const double *spring, int32_t cap,
+// Loads a checked history into the tables: each slot takes the contacts of
+// the particle it holds (whatever the storage order).
+__global__ void k_set_history(const SysDev *sys, const int32_t *tile_sys, const PX *px,
+                              const int32_t *partner, const double *spring, int32_t cap,
                               HistEntry *hist, int32_t *hcnt, int64_t stride) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.n) return;
-  const int64_t g = S.o_off + i, k = S.p_off + i;
+  const int64_t t = blockIdx.x;
+  const SysDev &S = sys[tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n || !S.friction) return;
+  const int64_t k = S.p_off + local;
+  const int64_t g = S.o_off + px[k].orig;
   int n = 0;
   for (int c = 0; c < cap; ++c) {
     const int32_t who = partner[g * cap + c];
@@ -1338,11 +1342,12 @@ hipError_t launch_check_history(const SysDev &S, const int32_t *partner, const d
   return hipGetLastError();
 }
 
-hipError_t launch_set_history(const SysDev &S, const int32_t *partner, const double *spring,
+hipError_t launch_set_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                              const PX *px, const int32_t *partner, const double *spring,
                               int32_t cap, HistEntry *hist, int32_t *hcnt, int64_t stride,
                               hipStream_t st) {
-  if (S.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_history, dim3((unsigned)((S.n + 255) / 256)), dim3(256), 0, st, S,
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_history, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
                      partner, spring, cap, hist, hcnt, stride);
   return hipGetLastError();
 }

@@ -642,6 +642,7 @@ def test_checkpoint_resume_with_friction_history_bitwise():
     xt, vt = torch.from_numpy(x1).cuda(), torch.from_numpy(v1).cuda()
     with GpuRun([s], fr) as g:
         vb.vb_set_state(g.ctx, xt, vt, g.rc, g.invm, v_is_half_step=True)
+        g.pairs(0, 1)  # runs the storage sort first: the history follows the particles
         vb.vb_set_history(g.ctx, partner, spring)
         g.run(80)
         xb, vb2, _ = g.state()
