@@ -23,7 +23,16 @@
  *       list invalid iff displacement > skin.
  *   R7  a broad phase always runs at step 0.
  *   R10 the broad-phase inclusion test is inflated by an absolute eps.
+ *   R12 the contact law is a normal linear spring-dashpot (Sec. 5.1 names the
+ *       model, not its constants, which are inputs here), against particles and
+ *       against the walls (box faces and planar walls) alike.
  *   R13 the dashpot uses the half-step velocity available when forces are evaluated.
+ *   R14 the forces on a particle are summed in ascending partner index, then
+ *       the box faces (-x, +x, -y, +y, -z, +z), then the planar walls in order,
+ *       so that the sum does not depend on what the Verlet list holds.
+ *   R16 friction, when on, is a translational tangential spring-dashpot capped
+ *       by Coulomb's law, with a spring per contact that starts at zero when the
+ *       contact forms (Sec. 5.1 names static friction without its form).
  */
 #include "orc.h"
 
