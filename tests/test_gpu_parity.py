@@ -691,3 +691,69 @@ def test_history_input_is_checked():
         with pytest.raises(vb.VbError) as e:
             vb.vb_set_history(g.ctx, q, spring)
         assert e.value.code == vb.VB_EINVAL
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_mixes_against_oracle(seed):
+    """Seeded random mixes of the options in one uneven batch: lattice, hopper and
+    incline systems, mono- or polydisperse, K in {0, 10, 200, 5000} (at most 10
+    with the literal cap, whose spheres reach L_C), both cap modes, local or
+    uniform skin, friction on or off, narrow rows and bins that must grow.  Every system against the oracle (the 1e-5 bars, contact counts
+    exact at every step), and the batch against the broad phase at every step,
+    bit for bit (Sec. 4.2)."""
+    import torch
+    import paper_2208_13770_amd as vb
+    rng = np.random.default_rng(1000 + seed)
+    systems, params = [], []
+    for _ in range(int(rng.integers(1, 4))):
+        kind, sd = int(rng.integers(0, 3)), int(rng.integers(0, 1 << 30))
+        K = float(rng.choice([0.0, 10.0, 200.0, 5000.0]))
+        if kind == 0:
+            dims = [int(rng.integers(4, 15)) for _ in range(3)]
+            cap = int(rng.integers(0, 2))
+            if cap == 1:  # spheres up to L_C: rows past the 128-entry limit at large K
+                K = min(K, 10.0)
+            s = synth.lattice_system(*dims, int(rng.integers(0, 4)), int(rng.integers(0, 3)),
+                                     float(rng.uniform(0.02, 0.3)), sd,
+                                     polydisperse=bool(rng.integers(0, 2)), K=K, cap_mode=cap)
+        elif kind == 1:
+            s = synth.hopper_system(int(rng.integers(400, 2500)), sd, K=K)
+        else:
+            s = synth.incline_system(int(rng.integers(400, 2500)), sd, K=K)
+        p = dict(s.params, max_neighbors=int(rng.choice([4, 16, 32])),
+                 bin_capacity=int(rng.choice([2, 8, 16])))
+        if rng.random() < 0.3:
+            p["skin_mode"] = vb.VB_SKIN_UNIFORM
+            p["skin_uniform"] = float(0.1 * s.meta["a"])
+        if rng.random() < 0.4:
+            p.update(_frictional(s))
+        systems.append(s)
+        params.append(p)
+    steps = 600
+    say(f"random mix {seed}: " + ", ".join(
+        f"{s.meta.get('kind', 'lattice')} N={s.n} K={p['K']:g} cap={p.get('cap_mode', 0)} "
+        f"skin={p.get('skin_mode', 0)} mu={p.get('mu', 0.0):g}" for s, p in zip(systems, params)))
+    x, v, rc, invm = vb.state_tensors(systems)
+
+    def run(plist):
+        ctx = vb.vb_batch_create(plist, [s.n for s in systems])
+        try:
+            vb.vb_set_state(ctx, x, v, rc, invm)
+            h = vb.vb_run(ctx, steps)
+            xo, vo = torch.empty_like(x), torch.empty_like(v)
+            vb.vb_get_state(ctx, xo, vo)
+        finally:
+            vb.vb_destroy(ctx)
+        return xo.cpu().numpy(), vo.cpu().numpy(), h
+
+    xg, vg, hg = run(params)
+    off = np.cumsum([0] + [s.n for s in systems])
+    for b, (s, p) in enumerate(zip(systems, params)):
+        sl = slice(int(off[b]), int(off[b + 1]))
+        X, Vv, R, M = host_arrays([s])
+        xo, vo, ho, _ = oracle.run(p, X, Vv, R, M, steps)
+        assert_close(s, xg[sl], vg[sl], xo, vo, f"system {b}")
+        assert np.array_equal(hg[b]["contacts"], ho["contacts"]), b
+    xn, vn, hn = run([dict(p, skin_mode=vb.VB_NO_BUFFER) for p in params])
+    assert np.array_equal(xg, xn) and np.array_equal(vg, vn)
+    assert np.array_equal(hg["contacts"], hn["contacts"])
