@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="also run every system of the batch in its own context, in turn")
     ap.add_argument("--scale", type=float, default=1.0, help="lattice scale (1 = full size)")
+    ap.add_argument("--friction", type=float, default=0.0, metavar="MU",
+                    help="tangential friction with Coulomb coefficient MU (kt = kn/2, "
+                         "gamma_t = gamma_n/2) on every system; 0: none")
     ap.add_argument("--repeats", type=int, default=5,
                     help="runs of the same steps without instrumentation, for the spread of the wall time")
     args = ap.parse_args()
@@ -165,6 +168,10 @@ def main():
     t0 = time.perf_counter()
     systems = synth.config_systems(args.workload, seed=0, scale=args.scale,
                                    workers=min(16, os.cpu_count() or 1))
+    if args.friction > 0.0:
+        for s in systems:
+            s.params.update(kt=0.5 * s.params["kn"], gamma_t=0.5 * s.params["gamma_n"],
+                            mu=args.friction)
     n = sum(s.n for s in systems)
     log(f"{args.workload} input: {len(systems)} system(s), {n} particles generated in "
         f"{time.perf_counter() - t0:.1f}s")
@@ -225,14 +232,15 @@ def main():
             f"(batch {t_seq / wall:.2f}x faster)")
 
     cpu = None
-    if args.workload == "M2" and not args.no_cpu and args.cpu_steps > 0:
+    if args.workload == "M2" and args.friction == 0 and not args.no_cpu and args.cpu_steps > 0:
         v_cpu, dt_cpu = cpu_baseline(systems[0], args.cpu_steps)
         cpu = {"value": v_cpu, "unit": "Mparticle*step/s", "cores": 1, "kind": "oracle",
                "sample": f"M2 workload ({n} particles), first {args.cpu_steps} steps, K=200, "
                          f"FP64 oracle, single thread, {dt_cpu:.1f} s"}
         log(f"cpu oracle: {v_cpu:.3f} Mparticle*step/s ({dt_cpu:.1f} s)")
 
-    traffic = measured_traffic() if args.workload == "M2" and args.scale == 1.0 else None
+    traffic = (measured_traffic()
+               if args.workload == "M2" and args.scale == 1.0 and args.friction == 0 else None)
     out = {
         "metric": "Mpixel·iter/s (% HBM peak) + time-to-1e-4 residual, plain vs batched+learned",
         "metric_note": "restated for the paper's DEM method: Mparticle*step/s (% HBM peak) of "
@@ -248,7 +256,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload].format(n=n),
+        "config": {"workload": WORKLOADS[args.workload].format(n=n) + (
+                       f", tangential friction mu={args.friction:g}" if args.friction > 0 else ""),
                    "particles": n, "systems": len(systems), "steps": args.steps,
                    "K": systems[0].params["K"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
