@@ -141,6 +141,28 @@ def test_contacts_equal_brute_force_after_run():
     assert np.abs(gd - d).max() < 1e-15
 
 
+def test_pair_export_into_a_short_buffer():
+    """vb_get_pairs reports the full count and writes the first cap pairs of the
+    canonical (sorted) list when the buffer is shorter; NULL buffers give the
+    count alone."""
+    import torch
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=6)[0]
+    with GpuRun([s]) as g:
+        g.run(40)
+        full, fd = g.pairs(0, 0)
+        n = len(full)
+        assert n > 100 and vb.vb_get_pairs(g.ctx, 0, 0) == n
+        cap = n // 3
+        p = torch.full((cap, 2), -7, dtype=torch.int32, device="cuda")
+        d = torch.zeros(cap, dtype=torch.float64, device="cuda")
+        assert vb.vb_get_pairs(g.ctx, 0, 0, p, d) == n
+        assert np.array_equal(p.cpu().numpy(), full[:cap])
+        assert np.array_equal(d.cpu().numpy(), fd[:cap])
+        assert (full[:, 0] < full[:, 1]).all()
+        assert (np.diff(full[:, 0] * (s.n + 1) + full[:, 1]) > 0).all()
+
+
 # --------------------------------------------------------------------- cadence
 
 @pytest.mark.parametrize("K", [0, 7, 50])
