@@ -779,3 +779,34 @@ def test_random_mixes_against_oracle(seed):
     xn, vn, hn = run([dict(p, skin_mode=vb.VB_NO_BUFFER) for p in params])
     assert np.array_equal(xg, xn) and np.array_equal(vg, vn)
     assert np.array_equal(hg["contacts"], hn["contacts"])
+
+
+def test_forced_rebuild_timing_and_info():
+    """vb_force_rebuild runs a broad phase at the next step and changes no result
+    (Sec. 4.2); vb_set_timing / vb_phase_times count exactly the timed steps and
+    the steps with a broad phase; vb_get_info reports sizes and the step counter;
+    vb_last_error gives the message of a failed call."""
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=11)[0]
+    say("forced rebuild, timing, info")
+    xr, vr, hr = gpu_trajectory([s], 61)
+    with GpuRun([s]) as g:
+        h1 = g.run(30)
+        vb.vb_force_rebuild(g.ctx)
+        h2 = g.run(1)
+        assert h2[0]["rebuilt"][0] == 1
+        vb.vb_set_timing(g.ctx, 1)
+        h3 = g.run(30)
+        pt = vb.vb_phase_times(g.ctx)
+        assert pt["steps"] == 30 and pt["ms_step"] > 0.0 and pt["ms_rebuild"] > 0.0
+        assert pt["rebuild_steps"] == int(h3[0]["rebuilt"].sum())
+        info = g.info()
+        assert info["n_total"] == s.n and info["n_sys"] == 1 and info["step"] == 61
+        assert info["row_width"] >= s.params.get("max_neighbors", 32)
+        x, v, _ = g.state()
+        with pytest.raises(vb.VbError):
+            vb.vb_set_K(g.ctx, 5, 100.0)  # no system 5
+        assert "sys" in vb.vb_last_error(g.ctx)
+    assert np.array_equal(x, xr) and np.array_equal(v, vr)
+    contacts = np.concatenate([h1[0]["contacts"], h2[0]["contacts"], h3[0]["contacts"]])
+    assert np.array_equal(contacts, hr[0]["contacts"])
