@@ -157,7 +157,8 @@ vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 
 /* Copy the state out, original order: d_x [N][3] positions x^n and d_v [N][3]
  * velocities (v^{n-1/2} after at least one step, else the loaded velocities).
- * Either pointer may be NULL.  *h_v_is_half_step (if not NULL) tells which. */
+ * Either pointer may be NULL.  *h_v_is_half_step (if not NULL) tells which.
+ * Synchronises the stream.  Errors: VB_EINVAL without a loaded state. */
 vb_status vb_get_state(vb_ctx *ctx, double *d_x, double *d_v, int32_t *h_v_is_half_step);
 
 /* The friction history, for a checkpoint that resumes exactly: the contacts of
@@ -199,7 +200,9 @@ vb_status vb_set_history(vb_ctx *ctx, const int32_t *d_partner, const double *d_
 vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs,
                        double *d_delta, int64_t cap, int64_t *h_n);
 
-/* Request a broad phase at the next step (all systems). */
+/* Request a broad phase at the next step (all systems), as if a validity test
+ * had failed (Def. autoverlet); by the theorem of Sec. 4.2 this changes no
+ * result.  Errors: VB_EINVAL for a NULL ctx. */
 vb_status vb_force_rebuild(vb_ctx *ctx);
 
 /* Set the skin factor K of Eq. skin_formulus1 for system sys (every system when
@@ -211,8 +214,9 @@ vb_status vb_force_rebuild(vb_ctx *ctx);
  * Errors: VB_EINVAL if K is negative or not finite, or sys >= the system count. */
 vb_status vb_set_K(vb_ctx *ctx, int32_t sys, double K);
 
-/* Enable (1) or disable (0) per-kernel HIP-event timing of vb_run, and read the
- * totals since timing was enabled.  The events take the kernels' own start and
+/* Enable (1) or disable (0) per-kernel HIP-event timing of vb_run (the per-phase
+ * split the paper reports, Sec. 5.4), and read the totals since timing was
+ * enabled.  The events take the kernels' own start and
  * end times (as a kernel-trace profiler reports them, launch gaps excluded):
  * milliseconds from the start of the binning kernel to the end of the pair
  * search at every step (including the launches that found no system to rebuild;
@@ -222,7 +226,8 @@ vb_status vb_set_timing(vb_ctx *ctx, int32_t on);
 vb_status vb_phase_times(vb_ctx *ctx, double *h_ms_rebuild, double *h_ms_step,
                          int64_t *h_steps, int64_t *h_rebuild_steps);
 
-/* Sizes: total particles N, systems, current row width, current step counter. */
+/* Sizes: total particles N, systems, current row width, current step counter.
+ * Any output pointer may be NULL.  Errors: VB_EINVAL for a NULL ctx. */
 vb_status vb_get_info(vb_ctx *ctx, int64_t *h_n_total, int32_t *h_n_sys,
                       int32_t *h_row_width, int64_t *h_step);
 
