@@ -810,3 +810,27 @@ def test_forced_rebuild_timing_and_info():
     assert np.array_equal(x, xr) and np.array_equal(v, vr)
     contacts = np.concatenate([h1[0]["contacts"], h2[0]["contacts"], h3[0]["contacts"]])
     assert np.array_equal(contacts, hr[0]["contacts"])
+
+
+def test_fixed_interval_schedule_on_gpu():
+    """The fixed-update practice the automatic scheme replaces (Sec. 1, Sec. 2):
+    with VB_FIXED_INTERVAL the broad phase runs exactly every F steps whatever
+    the particles do, and with a skin too small for the flow it misses contacts.
+    At the first step where the contact count departs from the exact run it is
+    lower: a stale list can miss a contact, never make one."""
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=12)[0]
+    F = 25
+    say(f"fixed interval {F} on M1")
+    ov = {"skin_mode": vb.VB_FIXED_INTERVAL, "fixed_interval": F,
+          "skin_uniform": float(1e-3 * s.meta["a"])}
+    _, _, hf = gpu_trajectory([s], 150, **ov)
+    _, _, he = gpu_trajectory([s], 150, skin_mode=vb.VB_NO_BUFFER)
+    steps = np.arange(150)
+    assert np.array_equal(hf[0]["rebuilt"].astype(bool), steps % F == 0)
+    cf, ce = hf[0]["contacts"], he[0]["contacts"]
+    diff = np.nonzero(cf != ce)[0]
+    say(f"  first departure at step {diff[0] if len(diff) else None}")
+    assert len(diff) > 0
+    assert cf[diff[0]] < ce[diff[0]]
+    assert diff[0] % F != 0
