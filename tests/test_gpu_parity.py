@@ -834,3 +834,25 @@ def test_fixed_interval_schedule_on_gpu():
     assert len(diff) > 0
     assert cf[diff[0]] < ce[diff[0]]
     assert diff[0] % F != 0
+
+
+def test_context_without_particles():
+    """A context of one empty system loads, runs and reports without launching
+    work: records of zeros, an empty pair list."""
+    import torch
+    import paper_2208_13770_amd as vb
+    s = synth.lattice_system(2, 2, 2, 0, 0, 0.0, 5)
+    say("empty context")
+    ctx = vb.vb_create(s.params, 0)
+    try:
+        e3 = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+        e1 = torch.empty((0,), dtype=torch.float32, device="cuda")
+        vb.vb_set_state(ctx, e3, e3, e1, e1)
+        h = vb.vb_run(ctx, 10)
+        assert h.shape == (1, 10)
+        assert (h["contacts"] == 0).all() and (h["list_pairs"] == 0).all()
+        assert vb.vb_get_pairs(ctx, 0, 0) == 0 and vb.vb_get_pairs(ctx, 0, 1) == 0
+        vb.vb_get_state(ctx, e3, e3)
+        assert vb.vb_get_info(ctx)["n_total"] == 0
+    finally:
+        vb.vb_destroy(ctx)
