@@ -856,3 +856,33 @@ def test_context_without_particles():
         assert vb.vb_get_info(ctx)["n_total"] == 0
     finally:
         vb.vb_destroy(ctx)
+
+
+@pytest.mark.parametrize("env", [{"VBUF_STEP_UNROLL": "1"}, {"VBUF_STEP_UNROLL": "2"},
+                                 {"VBUF_STEP_UNROLL": "4"}, {"VBUF_XCD_REMAP": "1"}])
+def test_tuning_variants_against_oracle(env):
+    """The step kernel's other instantiations (1, 2 or 4 gathers in flight per
+    thread) and the XCD tile order, chosen at create through the environment:
+    each matches the oracle and is K-invariant bit for bit (with and without
+    friction)."""
+    import os
+    s = synth.config_systems("M1", seed=13)[0]
+    fr = _frictional(s)
+    say(f"tuning variant {env}")
+    os.environ.update(env)
+    try:
+        xg, vg, hg = gpu_trajectory([s], 120)
+        xn, vn, _ = gpu_trajectory([s], 120, skin_mode=2)
+        xf, vf, hf = gpu_trajectory([s], 120, **fr)
+        xfn, vfn, _ = gpu_trajectory([s], 120, skin_mode=2, **fr)
+    finally:
+        for k in env:
+            del os.environ[k]
+    xo, vo, ho, _ = oracle_run(s, 120)
+    assert_close(s, xg, vg, xo, vo, "variant")
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert np.array_equal(xg, xn) and np.array_equal(vg, vn)
+    xo, vo, ho, _ = oracle_run(s, 120, **fr)
+    assert_close(s, xf, vf, xo, vo, "variant with friction")
+    assert np.array_equal(hf[0]["contacts"], ho["contacts"])
+    assert np.array_equal(xf, xfn) and np.array_equal(vf, vfn)
