@@ -46,7 +46,8 @@ hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const 
                                int64_t n_tiles, int32_t n_sys, int32_t step0, int32_t nsteps,
                                RecordDev *out, hipStream_t st);
 hipError_t launch_set_state(const SysDev &S, PX *px, PV *pv, const double *x, const double *v,
-                            const float *rc, const float *invm, int32_t *err, hipStream_t st);
+                            const float *rc, const float *invm, int32_t *err, int32_t *r_lo,
+                            int32_t *r_hi, hipStream_t st);
 hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
                             const PX *px, const PV *pv, double *x, double *v, hipStream_t st);
 hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const int32_t *nbr,
@@ -54,7 +55,8 @@ hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const
                         int64_t *total, int64_t cap, int32_t *pairs, double *delta,
                         hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
-hipError_t launch_pos32(const PX *px, float4 *pos32, int64_t n, hipStream_t st);
+hipError_t launch_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
+                       const PX *px, uint64_t *posq, int64_t n, hipStream_t st);
 }  // namespace vb
 
 using namespace vb;
@@ -73,7 +75,8 @@ struct vb_ctx {
   int32_t *tile_sys = nullptr;
   PX *px[2] = {nullptr, nullptr};
   PV *pv[2] = {nullptr, nullptr};
-  float4 *pos32[2] = {nullptr, nullptr};  // FP32 copies of px[0], px[1]
+  uint64_t *posq[2] = {nullptr, nullptr};  // coded positions of px[0], px[1]
+  int32_t *rrange = nullptr;               // [2][n_sys] smallest and largest R_C (FP32 bits)
   // friction history (allocated only when some system has friction)
   int any_friction = 0;
   int32_t hcap = 0;
@@ -163,8 +166,8 @@ static hipError_t dalloc(T **p, int64_t count) {
 }
 
 static void free_all(vb_ctx *c) {
-  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->pos32[0],
-                  c->pos32[1], c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
+  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->posq[0],
+                  c->posq[1], c->rrange, c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
                   c->hcnt_snap, c->snap_px,
                   c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
                   c->brick_sys, c->cellid, c->inv,
@@ -379,11 +382,15 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.n_planes = p.n_planes;
     for (int w = 0; w < p.n_planes; ++w)
       for (int c = 0; c < 5; ++c) S.planes[w][c] = p.planes[w][c];
-    {  // 2^-14 of the largest coordinate a particle can reach (box plus a cell)
-      double bound = 0.0;
-      for (int a = 0; a < 3; ++a)
-        bound = std::max(bound, std::max(std::fabs(p.lo[a]), std::fabs(p.hi[a])) + 2.0 * p.cell_size);
-      S.margin32 = (float)std::ldexp(bound, -14);
+    {  // grid of the coded positions: the box and two cells beyond each face,
+       // 2^19 - 1 steps along its longest edge
+      double span = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        S.qlo[a] = p.lo[a] - 2.0 * p.cell_size;
+        span = std::max(span, p.hi[a] - p.lo[a] + 4.0 * p.cell_size);
+      }
+      S.qinv = (double)((1 << 19) - 1) / span;
+      S.qinv32 = (float)S.qinv;
     }
     p_off += (int64_t)S.n_tiles * TILE;
     t_off += S.n_tiles;
@@ -431,8 +438,9 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   for (int b = 0; b < 2; ++b) {
     ALLOC(c->px[b], c->slots);
     ALLOC(c->pv[b], c->slots);
-    ALLOC(c->pos32[b], c->slots);
+    ALLOC(c->posq[b], c->slots);
   }
+  ALLOC(c->rrange, 2 * n_sys);
   ALLOC(c->bp, c->slots);
   ALLOC(c->cnt, c->slots);
   ALLOC(c->bin_count, c->n_cells);
@@ -491,6 +499,12 @@ extern "C" vb_status vb_create(const vb_params *h_params, int64_t n, void *strea
   return vb_batch_create(h_params, &n, 1, stream, out);
 }
 
+// Coded positions of px[b] for the step kernel's pre-test.
+static hipError_t fill_posq(vb_ctx *c, int b) {
+  return launch_posq(c->sys_d, c->tile_sys, c->rrange, c->n_sys, c->px[b], c->posq[b], c->slots,
+                     c->stream);
+}
+
 // Clears the per-run control state on the stream: no pending violation, no
 // broad phase under way, empty bins, no overflow.
 static vb_status reset_control(vb_ctx *c) {
@@ -508,11 +522,13 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
   if (c->n_total > 0 && (!d_x || !d_v || !d_rc || !d_invm))
     return fail(c, VB_EINVAL, "state pointers must not be NULL");
   HIP_OK(c, launch_fill_i32(c->err, 1, 0, c->stream));
+  HIP_OK(c, launch_fill_i32(c->rrange, c->n_sys, 0x7F800000, c->stream));  // +inf
+  HIP_OK(c, launch_fill_i32(c->rrange + c->n_sys, c->n_sys, 0, c->stream));
   for (int s = 0; s < c->n_sys; ++s)
     HIP_OK(c, launch_set_state(c->sys_h[s], c->px[0], c->pv[0], d_x, d_v, d_rc, d_invm, c->err,
-                               c->stream));
+                               c->rrange + s, c->rrange + c->n_sys + s, c->stream));
   HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
-  HIP_OK(c, launch_pos32(c->px[0], c->pos32[0], c->slots, c->stream));
+  HIP_OK(c, fill_posq(c, 0));
   if (c->any_friction) HIP_OK(c, launch_fill_i32(c->hcnt[0], c->slots, 0, c->stream));
   vb_status st = reset_control(c);
   if (st != VB_OK) return st;
@@ -592,7 +608,7 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.stride = c->slots;
     HIP_OK(c, launch_sort(s, c->stream));
     c->cur ^= 1;
-    HIP_OK(c, launch_pos32(c->px[c->cur], c->pos32[c->cur], c->slots, c->stream));
+    HIP_OK(c, fill_posq(c, c->cur));
     c->force_pending = 1;  // slots moved: every row must be rebuilt
     c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
   }
@@ -610,8 +626,9 @@ static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = 
   a.pv_cur = c->pv[c->cur];
   a.px_dst = c->px[c->cur ^ 1];
   a.pv_dst = c->pv[c->cur ^ 1];
-  a.pos32_cur = c->pos32[c->cur];
-  a.pos32_dst = c->pos32[c->cur ^ 1];
+  a.posq_cur = c->posq[c->cur];
+  a.posq_dst = c->posq[c->cur ^ 1];
+  a.rrange = c->rrange;
   a.bp = c->bp;
   a.cnt = c->cnt;
   a.nbr = c->nbr;
@@ -837,7 +854,7 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots,
                              hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
-    HIP_OK(c, launch_pos32(c->px[0], c->pos32[0], c->slots, c->stream));
+    HIP_OK(c, fill_posq(c, 0));
     if (c->any_friction) {  // entries c < snap_hcap sit at the same place in a wider table
       HIP_OK(c, hipMemcpyAsync(c->hist[0], c->hist_snap, sizeof(HistEntry) * c->slots * snap_hcap,
                                hipMemcpyDeviceToDevice, c->stream));

@@ -61,7 +61,11 @@ struct SysDev {
   int32_t skin_mode;
   int32_t fixed_interval;
   int32_t ring;       // cell rings searched: 1 (cap mode 0) or 2 (cap mode 1)
-  float margin32;     // margin of the step kernel's FP32 contact pre-test
+  // grid of the step kernel's coded positions: 19-bit coordinates of pitch
+  // 1/qinv from qlo, covering the box and two cells beyond each face
+  double qlo[3];
+  double qinv;
+  float qinv32;       // qinv rounded to FP32, for the pre-test
   int32_t n_planes;   // planar walls besides the box faces
   int32_t friction;   // 1: tangential spring-dashpot with Coulomb limit on the contacts
   double planes[VB_MAX_PLANES][5];  // (n_x, n_y, n_z, d, z_min) as in vb_params
@@ -134,8 +138,9 @@ struct StepArgs {
   const PV *pv_cur;
   PX *px_dst;
   PV *pv_dst;
-  const float4 *pos32_cur;  // FP32 copies (x, y, z, R_C) of px_cur
-  float4 *pos32_dst;        // written with px_dst
+  const uint64_t *posq_cur;  // coded positions and radius bounds of px_cur
+  uint64_t *posq_dst;        // written with px_dst
+  const int32_t *rrange;     // [2][n_sys] FP32 bits of each system's smallest and largest R_C
   const float4 *bp;
   const int32_t *cnt;
   const int32_t *nbr;

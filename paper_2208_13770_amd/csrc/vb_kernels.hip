@@ -97,14 +97,76 @@ __device__ __forceinline__ bool overlap_positive(const PX &a, const PX &b, doubl
   return delta > 0.0;
 }
 
-// FP32 pre-test of a contact on the FP32 position copies (x, y, z, R_C): true
-// whenever the exact FP64 test can be.  The margin (2^-14 of the largest
-// coordinate) is some 200 times the rounding of the FP32 copies and of this
-// arithmetic, so a pair it rejects is farther apart than R_i + R_j.
-__device__ __forceinline__ bool contact_candidate(const float4 &a, const float4 &b, float margin) {
-  const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-  const float reach = a.w + b.w + margin;
-  return dx * dx + dy * dy + dz * dz <= reach * reach;
+// Coded positions of the step kernel's pre-test, 8 B per particle.  The centre
+// is rounded to a grid of pitch h = 1/qinv (19 bits per axis: x in bits 0-18,
+// y in 19-37, z in 38-56); bits 57-63 hold a code c whose bound
+// rlo + c (rhi - rlo)/126, on the system's range [rlo, rhi] of R_C, is at
+// least R_C.  Code 127 marks a centre off the grid or a radius without a code:
+// such a particle passes every pre-test it takes part in.
+constexpr int QBITS = 19;
+constexpr uint32_t QMASK = (1u << QBITS) - 1u;
+constexpr uint32_t QFREE = 127u;
+// Margin of the pre-test in grid steps.  Rounding each centre moves the
+// difference of two centres by at most sqrt(3) h; the FP32 arithmetic of the
+// test adds under 0.1 h, since a reach is below 2^18 h (the grid spans at
+// least four cells and R_C is at most one cell).
+constexpr float QMARGIN = 2.5f;
+
+__device__ __forceinline__ float radius_step(float rlo, float rhi) {
+  return (rhi - rlo) * (1.0f / 126.0f);
+}
+__device__ __forceinline__ float radius_bound(float rlo, float step, uint32_t c) {
+  return __fmaf_rn((float)c, step, rlo);
+}
+
+__device__ __forceinline__ uint64_t posq_encode(const SysDev &S, float rlo, float rhi, double x,
+                                                double y, double z, float rc) {
+  const double lim = (double)QMASK;  // t < 2^19 - 1 keeps floor(t + 1/2) within 19 bits
+  const double tx = (x - S.qlo[0]) * S.qinv;
+  const double ty = (y - S.qlo[1]) * S.qinv;
+  const double tz = (z - S.qlo[2]) * S.qinv;
+  if (!(tx >= 0.0 && tx < lim && ty >= 0.0 && ty < lim && tz >= 0.0 && tz < lim))
+    return (uint64_t)QFREE << 57;
+  uint32_t c = QFREE;
+  const float step = radius_step(rlo, rhi);
+  if (rc <= rlo) {
+    c = 0;
+  } else if (step > 0.0f) {
+    const float t = ceilf((rc - rlo) / step);
+    uint32_t c0 = t < 126.0f ? (uint32_t)t : 126u;
+    while (c0 < 126u && radius_bound(rlo, step, c0) < rc) ++c0;
+    if (radius_bound(rlo, step, c0) >= rc) c = c0;
+  }
+  const uint64_t qx = (uint32_t)(tx + 0.5), qy = (uint32_t)(ty + 0.5), qz = (uint32_t)(tz + 0.5);
+  return qx | (qy << QBITS) | (qz << (2 * QBITS)) | ((uint64_t)c << 57);
+}
+
+// One side of the pre-test, decoded once per particle: grid coordinates and
+// R_C in grid steps plus the margin (infinite for a particle without a code).
+struct QSelf {
+  int x, y, z;
+  float reach0;
+};
+__device__ __forceinline__ QSelf posq_self(uint64_t q, float rc, float qinv32) {
+  QSelf m;
+  m.x = (int)(q & QMASK);
+  m.y = (int)((q >> QBITS) & QMASK);
+  m.z = (int)((q >> (2 * QBITS)) & QMASK);
+  m.reach0 = (uint32_t)(q >> 57) == QFREE ? INFINITY : __fmaf_rn(rc, qinv32, QMARGIN);
+  return m;
+}
+
+// Pre-test of a contact on coded positions: true whenever the exact FP64 test
+// of Eq. delta can be.  rlo_q and step_q are the radius code's origin and step
+// in grid steps.
+__device__ __forceinline__ bool posq_candidate(const QSelf &m, uint64_t o, float rlo_q,
+                                               float step_q) {
+  const float dx = (float)(m.x - (int)(o & QMASK));
+  const float dy = (float)(m.y - (int)((o >> QBITS) & QMASK));
+  const float dz = (float)(m.z - (int)((o >> (2 * QBITS)) & QMASK));
+  const uint32_t c = (uint32_t)(o >> 57);
+  const float reach = c == QFREE ? INFINITY : m.reach0 + __fmaf_rn((float)c, step_q, rlo_q);
+  return __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz)) <= reach * reach;
 }
 
 // Maps a workgroup index to a tile so that each of the 8 XCDs (which receive
@@ -233,7 +295,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? nt_load(&row[(int64_t)u * st]) : 0;
     const PX me = px[k];
     const PV mv = pv[k];
-    const float4 me32 = make_float4((float)me.x, (float)me.y, (float)me.z, me.rc);
+    const float rlo = __int_as_float(a.rrange[s]), rhi = __int_as_float(a.rrange[a.n_sys + s]);
+    const QSelf mq = posq_self(posq_encode(S, rlo, rhi, me.x, me.y, me.z, me.rc), me.rc, S.qinv32);
+    const float rlo_q = rlo * S.qinv32, step_q = radius_step(rlo, rhi) * S.qinv32;
     const float4 b = nt_load(&a.bp[k]);
     rowlen = nt_load(&a.cnt[k]);
     double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -312,27 +376,27 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       }
     };
     // Two passes over each segment of MAX_CAND row entries.  The scan walks the
-    // row (ascending original index) with UNROLL gathers of the 16-byte FP32
-    // position copies in flight, requesting the next chunk's row entries
-    // meanwhile, and lists in LDS the partners that pass a conservative FP32
-    // pre-test.  The flush then requests the FP64 positions and the velocities
-    // of the listed partners together, runs the exact test and adds the contact
-    // forces in list (= row) order.
+    // row (ascending original index) with UNROLL gathers of the 8-byte coded
+    // positions in flight, requesting the next chunk's row entries meanwhile,
+    // and lists in LDS the partners that pass the conservative pre-test.  The
+    // flush then requests the FP64 positions and the velocities of the listed
+    // partners together, runs the exact test and adds the contact forces in
+    // list (= row) order.
     for (int q0 = 0; q0 < rowlen; q0 += MAX_CAND) {
       const int q1 = min(rowlen, q0 + MAX_CAND);
       int nc = 0;
       for (int q = q0; q < q1; q += UNROLL) {
-        float4 o[UNROLL];
+        uint64_t o[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-          if (q + u < q1) o[u] = a.pos32_cur[S.p_off + j[u]];
+          if (q + u < q1) o[u] = a.posq_cur[S.p_off + j[u]];
         int32_t jn[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           jn[u] = q + UNROLL + u < rowlen ? nt_load(&row[(int64_t)(q + UNROLL + u) * st]) : 0;
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-          if (q + u < q1 && contact_candidate(me32, o[u], S.margin32)) {
+          if (q + u < q1 && posq_candidate(mq, o[u], rlo_q, step_q)) {
             s_cand[nc * TILE + threadIdx.x] = j[u];
             ++nc;
           }
@@ -415,7 +479,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     outv.pad = 0;
     nt_store32(&a.px_dst[k], outx);
     nt_store32(&a.pv_dst[k], outv);
-    nt_store(&a.pos32_dst[k], make_float4((float)xn[0], (float)xn[1], (float)xn[2], me.rc));
+    __builtin_nontemporal_store(posq_encode(S, rlo, rhi, xn[0], xn[1], xn[2], me.rc), &a.posq_dst[k]);
     ke = 0.5 * (vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2]) / im;
     // Eq. update for the next step: straight-line displacement since the last
     // broad phase against the skin left after the cap (R_NL - R_C)
@@ -974,23 +1038,30 @@ __global__ __launch_bounds__(TILE) void k_stats_reduce(const SysDev *sys, const 
 
 // ------------------------------------------------------------------ state I/O
 
-// Load one system from the caller's original order; flags bad values in *err:
-// bit 0 non-finite, bit 1 radius out of range, bit 2 non-positive inverse mass.
-// FP32 copies (x, y, z, R_C) of the positions, for the step kernel's pre-test.
-__global__ void k_pos32(const PX *px, float4 *pos32, int64_t n) {
+// Coded positions of every slot, for the step kernel's pre-test.
+__global__ void k_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
+                       const PX *px, uint64_t *posq, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int s = tile_sys[i / TILE];
   const PX p = px[i];
-  pos32[i] = make_float4((float)p.x, (float)p.y, (float)p.z, p.rc);
+  posq[i] = posq_encode(sys[s], __int_as_float(rrange[s]), __int_as_float(rrange[n_sys + s]), p.x,
+                        p.y, p.z, p.rc);
 }
 
+// Load one system from the caller's original order; flags bad values in *err:
+// bit 0 non-finite, bit 1 radius out of range, bit 2 non-positive inverse mass.
+// The smallest and largest valid R_C go to *r_lo and *r_hi (FP32 bits; positive
+// floats order like their bits).
 __global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const double *v,
-                            const float *rc, const float *invm, int32_t *err) {
+                            const float *rc, const float *invm, int32_t *err, int32_t *r_lo,
+                            int32_t *r_hi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t padded = (int64_t)S.n_tiles * TILE;
-  if (i >= padded) return;
+  if (i >= padded) return;  // padded is a multiple of the block size: whole waves
   PX p;
   PV q;
+  float rmin = INFINITY, rmax = 0.0f;
   if (i < S.n) {
     const int64_t g = S.o_off + i;
     p.x = x[3 * g];
@@ -1012,6 +1083,7 @@ __global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const dou
       if (!(q.invm > 0.0f)) e |= 4;
     }
     if (e) atomicOr(err, e);
+    else rmin = rmax = p.rc;
   } else {
     p.x = p.y = p.z = 0.0;
     p.rc = 0.0f;
@@ -1022,6 +1094,12 @@ __global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const dou
   }
   px[S.p_off + i] = p;
   pv[S.p_off + i] = q;
+  rmin = -wave_max(-rmin);
+  rmax = wave_max(rmax);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && rmax > 0.0f) {
+    atomicMin(r_lo, __float_as_int(rmin));
+    atomicMax(r_hi, __float_as_int(rmax));
+  }
 }
 
 // Friction history to the caller's original order: particle g's contacts of
@@ -1308,11 +1386,12 @@ hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const 
 }
 
 hipError_t launch_set_state(const SysDev &S, PX *px, PV *pv, const double *x, const double *v,
-                            const float *rc, const float *invm, int32_t *err, hipStream_t st) {
+                            const float *rc, const float *invm, int32_t *err, int32_t *r_lo,
+                            int32_t *r_hi, hipStream_t st) {
   const int64_t padded = (int64_t)S.n_tiles * TILE;
   if (padded == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_state, dim3((unsigned)((padded + 255) / 256)), dim3(256), 0, st, S, px,
-                     pv, x, v, rc, invm, err);
+  hipLaunchKernelGGL(k_set_state, dim3((unsigned)(padded / 256)), dim3(256), 0, st, S, px, pv, x, v,
+                     rc, invm, err, r_lo, r_hi);
   return hipGetLastError();
 }
 
@@ -1368,9 +1447,11 @@ hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const
   return hipGetLastError();
 }
 
-hipError_t launch_pos32(const PX *px, float4 *pos32, int64_t n, hipStream_t st) {
+hipError_t launch_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
+                       const PX *px, uint64_t *posq, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pos32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, px, pos32, n);
+  hipLaunchKernelGGL(k_posq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sys, tile_sys,
+                     rrange, n_sys, px, posq, n);
   return hipGetLastError();
 }
 

@@ -554,6 +554,62 @@ def test_cell_face_placements_broad_phase():
     assert (margin(gl) > -1e-6).all()
 
 
+@pytest.mark.parametrize("radii", ["polydisperse", "monodisperse"])
+def test_contact_pretest_at_near_touching_distances(radii):
+    """Pairs placed a hair inside or outside touching distance (relative gaps
+    from 1e-9 to 1e-4), some of them with centres off the grid of the coded
+    positions that the step kernel's pre-test reads (beyond two cells outside
+    the box, and one pair across that grid's edge): the contacts the step
+    kernel finds equal a brute-force count at every step and the oracle's."""
+    rng = np.random.default_rng(21 if radii == "polydisperse" else 22)
+    L_C = 0.02
+    sites = np.stack(np.meshgrid(*[np.arange(0.05, 0.96, 0.05)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    sites = sites[rng.permutation(len(sites))[:2400]]
+    off = np.array([[-0.1, 0.5, 0.5], [0.5, -0.12, 0.3], [0.4, 0.6, 1.1], [1.15, 1.15, 1.15],
+                    [-0.04, 0.3, 0.3]])        # the last straddles the grid edge at lo - 2 cells
+    centres = np.concatenate([sites, off], axis=0)
+    m = len(centres)
+    if radii == "polydisperse":
+        R = rng.uniform(0.004, 0.008, size=(m, 2))
+    else:
+        R = np.full((m, 2), 0.006)
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    u[-1] = (1.0, 0.0, 0.0)
+    rel = rng.choice([1e-9, 1e-7, 1e-5, 1e-4], size=m) * rng.choice([-1.0, 1.0], size=m)
+    d = (R[:, 0] + R[:, 1]) * (1.0 + rel)
+    x = np.concatenate([centres - 0.5 * d[:, None] * u, centres + 0.5 * d[:, None] * u])
+    rc = np.concatenate([R[:, 0], R[:, 1]])
+    n = len(rc)
+    v = rng.normal(0, 1e-3, size=(n, 3))
+    p = {"skin_mode": 0, "cap_mode": 0, "K": 50.0, "dt": 2.0 ** -12, "cell_size": L_C,
+         "skin_uniform": 0.0, "eps": 2e-6, "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1e3,
+         "gamma_n": 0.0, "g": (0, 0, 0), "max_neighbors": 32}
+
+    class Sys:  # the minimal system object GpuRun needs
+        pass
+    s = Sys()
+    s.pos_r = np.concatenate([x, rc[:, None]], axis=1).astype(np.float32)
+    s.vel_m = np.concatenate([v, np.ones((n, 1))], axis=1).astype(np.float32)
+    s.params = p
+    s.n = n
+    s.meta = {"v_max": 1e-3}
+    xh, vh, rch, invm = host_arrays([s])
+    brute0 = len(oracle.contacts_brute(xh, rch))
+    say(f"pre-test at near-touching distances ({radii}): {n} particles, {brute0} contacts at step 0")
+    assert 0.3 * m < brute0 < 0.7 * m
+    steps = 6
+    with GpuRun([s]) as g:
+        h = g.run(steps)[0]
+        xg, vg, _ = g.state()
+    xo, vo, ho, _ = oracle_run(s, steps)
+    assert h["contacts"][0] == brute0
+    assert np.array_equal(h["contacts"], ho["contacts"])
+    assert_close(s, xg, vg, xo, vo, "near-touching pairs")
+    x1, _, _, _ = oracle_run(s, steps - 1)
+    assert h["contacts"][-1] == len(oracle.contacts_brute(x1, rch))
+
+
 def test_k_zero_parity():
     """K = 0: every particle that moves violates at once, the broad phase runs at
     (nearly) every step, and the results still match the oracle."""
