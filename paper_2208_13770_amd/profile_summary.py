@@ -13,8 +13,13 @@
       instruction-mix counters (SQ_*) of one kernel from `rocprofv3 --pmc` runs,
       averaged over the dispatches that did work (those issuing at least a tenth
       of the busiest dispatch's VALU instructions; a broad-phase kernel that finds
-      nothing to do exits at once), with per-wave and per-lane ratios.
+      nothing to do exits at once), with per-wave and per-lane ratios.  Runs of
+      memory-pipeline counters (TA_*, TD_*, TCP_*, GRBM_GUI_ACTIVE) are averaged
+      over all dispatches of the kernel and give busy and stall fractions per CU,
+      latencies and the vector memory instructions in flight.
 """
+N_CU = 256   # compute units; the _sum counters add one instance per CU
+N_XCD = 8    # GRBM_GUI_ACTIVE adds one count per XCD
 import argparse
 import csv
 import hashlib
@@ -109,7 +114,8 @@ def sq(args):
     keys = sorted(sums)
     mean = {k: statistics.mean(v) for k, v in sums.items()}
     busy = n_busy
-    out = [f"# Instruction-mix counters: {args.title or name}", "",
+    kind = "Instruction-mix" if any(k.startswith("SQ_") for k in keys) else "Memory-pipeline"
+    out = [f"# {kind} counters: {args.title or name}", "",
            *[f"Command: `{c}`" for c in args.cmd], "",
            f"Kernel source sha256[:16]: {kernel_hash()}", "",
            f"Kernel: `{name}`; dispatches that did work, per run: "
@@ -128,6 +134,30 @@ def sq(args):
     if mean.get("SQ_ACTIVE_INST_LDS") and "SQ_LDS_BANK_CONFLICT" in mean:
         ratios.append(("LDS bank-conflict cycles per active LDS instruction cycle",
                        mean["SQ_LDS_BANK_CONFLICT"] / mean["SQ_ACTIVE_INST_LDS"]))
+    cycles = mean.get("GRBM_GUI_ACTIVE", 0.0) / N_XCD  # GPU cycles of one dispatch
+    if cycles:
+        ratios.append(("GPU cycles per dispatch (GRBM_GUI_ACTIVE / 8 XCDs)", cycles))
+        if "TA_BUSY_avr" in mean:
+            ratios.append(("TA busy, fraction of the cycles (TA_BUSY_avr)", mean["TA_BUSY_avr"] / cycles))
+        for k, what in (("TD_TD_BUSY_sum", "TD processing or waiting for data"),
+                        ("TD_TC_STALL_sum", "TD stalled by the L1 (TCP)"),
+                        ("TCP_PENDING_STALL_CYCLES_sum", "L1 stalled on data pending from L2"),
+                        ("TCP_TCP_TA_DATA_STALL_CYCLES_sum", "L1 stalling the TA data interface"),
+                        ("TA_ADDR_STALLED_BY_TC_CYCLES_sum", "TA address path stalled by the L1"),
+                        ("TA_DATA_STALLED_BY_TC_CYCLES_sum", "TA data path stalled by the L1")):
+            if k in mean:
+                ratios.append((f"{what}, fraction of the cycles per CU ({k} / {N_CU})",
+                               mean[k] / N_CU / cycles))
+    if mean.get("TCP_TCC_READ_REQ_sum") and "TCP_TCC_READ_REQ_LATENCY_sum" in mean:
+        ratios.append(("L1-to-L2 read latency, cycles (TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum)",
+                       mean["TCP_TCC_READ_REQ_LATENCY_sum"] / mean["TCP_TCC_READ_REQ_sum"]))
+    if mean.get("TA_TOTAL_WAVEFRONTS_sum") and "TCP_TCP_LATENCY_sum" in mean:
+        lat = mean["TCP_TCP_LATENCY_sum"] / mean["TA_TOTAL_WAVEFRONTS_sum"]
+        ratios.append(("vector memory instruction latency in the L1, cycles "
+                       "(TCP_TCP_LATENCY_sum / TA_TOTAL_WAVEFRONTS_sum)", lat))
+        if cycles:
+            ratios.append(("vector memory instructions in flight per CU (Little's law)",
+                           mean["TA_TOTAL_WAVEFRONTS_sum"] / N_CU * lat / cycles))
     if ratios:
         out += ["", "| ratio | value |", "|---|---:|"] + [f"| {k} | {v:.3g} |" for k, v in ratios]
     open(args.out, "w").write("\n".join(out) + "\n")
