@@ -80,9 +80,11 @@ def copy_bandwidth(torch, nbytes=4 << 30):
     return 2 * nbytes / dt / 1e9
 
 
-def run_mode(vb, torch, systems, steps, warmup, overrides, timing):
+def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500):
     """One context over `systems` (a batch when more than one); returns the wall
-    time of `steps` timed steps, the [n_sys, steps] records, phase times and info."""
+    time of `steps` timed steps, the [n_sys, steps] records, phase times and info.
+    The steps go to vb_run in calls of at most `call_steps`: a call in which a
+    row or a cell bin outgrows its capacity is run again from its own start."""
     params = [dict(s.params, **overrides) for s in systems]
     ctx = vb.vb_batch_create(params, [s.n for s in systems])
     try:
@@ -95,7 +97,10 @@ def run_mode(vb, torch, systems, steps, warmup, overrides, timing):
         vb.vb_set_timing(ctx, timing)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hist = vb.vb_run(ctx, steps)
+        parts = []
+        for k in range(0, steps, max(1, call_steps)):
+            parts.append(vb.vb_run(ctx, min(max(1, call_steps), steps - k)))
+        hist = np.concatenate(parts, axis=1) if parts else vb.vb_run(ctx, 0)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         pt = vb.vb_phase_times(ctx)
@@ -151,6 +156,9 @@ def main():
     ap.add_argument("--friction", type=float, default=0.0, metavar="MU",
                     help="tangential friction with Coulomb coefficient MU (kt = kn/2, "
                          "gamma_t = gamma_n/2) on every system; 0: none")
+    ap.add_argument("--call-steps", type=int, default=500,
+                    help="steps per vb_run call (a call whose rows or cell bins overflow runs "
+                         "again from its own start)")
     ap.add_argument("--repeats", type=int, default=5,
                     help="runs of the same steps without instrumentation, for the spread of the wall time")
     args = ap.parse_args()
@@ -182,14 +190,15 @@ def main():
     # the throughput comes from a run without instrumentation; the kernel
     # durations from an identical run with HIP events on every kernel (the
     # events cost a few per cent of wall time)
-    wall, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False)
+    cs = args.call_steps
+    wall, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False, cs)
     value = n * args.steps / wall / 1e6
     walls = [wall]
     for _ in range(max(args.repeats, 1) - 1):
-        w_r, h_r, _, _ = run_mode(vb, torch, systems, args.steps, 0, {}, False)
+        w_r, h_r, _, _ = run_mode(vb, torch, systems, args.steps, 0, {}, False, cs)
         assert np.array_equal(h_r["contacts"], hist["contacts"])
         walls.append(w_r)
-    wall_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True)
+    wall_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True, cs)
     assert np.array_equal(hist_ev["contacts"], hist["contacts"])
     rebuilt = hist["rebuilt"].astype(bool)            # [n_sys, steps]
     n_rebuild = int(rebuilt.sum())                     # broad phases over all systems
@@ -205,9 +214,9 @@ def main():
     plain = None
     if not args.no_plain:
         wall_p, hist_p, _, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
-                                        {"skin_mode": vb.VB_NO_BUFFER}, False)
+                                        {"skin_mode": vb.VB_NO_BUFFER}, False, cs)
         _, _, pt_p, _ = run_mode(vb, torch, systems, args.steps, 0,
-                                 {"skin_mode": vb.VB_NO_BUFFER}, True)
+                                 {"skin_mode": vb.VB_NO_BUFFER}, True, cs)
         plain = {
             "time_s": wall_p,
             "value": n * args.steps / wall_p / 1e6,
@@ -224,7 +233,7 @@ def main():
     if args.sequential and len(systems) > 1:
         t_seq = 0.0
         for s in systems:
-            w, _, _, _ = run_mode(vb, torch, [s], args.steps, 0, {}, False)
+            w, _, _, _ = run_mode(vb, torch, [s], args.steps, 0, {}, False, cs)
             t_seq += w
         sequential = {"time_s": t_seq, "value": n * args.steps / t_seq / 1e6,
                       "batch_speedup": t_seq / wall}
@@ -259,7 +268,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload].format(n=n) + (
                        f", tangential friction mu={args.friction:g}" if args.friction > 0 else ""),
                    "particles": n, "systems": len(systems), "steps": args.steps,
-                   "K": systems[0].params["K"]},
+                   "steps_per_call": cs, "K": systems[0].params["K"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_step", "bytes_per_launch": bytes_per_launch,

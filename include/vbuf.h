@@ -146,9 +146,14 @@ vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const 
                        const float *d_invm, int32_t v_is_half_step);
 
 /* Advance every system n_steps time steps.  h_hist, if not NULL, receives
- * [n_sys][n_steps] records.  A Verlet-list row or a cell bin that overflows is
- * grown and the call's steps are run again from the call's starting state
- * (results unchanged).  Synchronises the stream once, at the end.
+ * [n_sys][n_steps] records.  A Verlet-list row, a cell bin or a friction
+ * history that overflows is grown and the call's steps are run again from the
+ * call's starting state (results unchanged).  The overflow counters are read
+ * back after every block of 64 steps, one block behind the device, and a call
+ * stops launching steps once they show an overflow; a late overflow still
+ * repeats the steps before it, so long simulations are best run as calls of a
+ * few hundred steps.  Synchronises the stream at the end, and waits on each
+ * block's counters one block behind.
  * Errors: VB_ECAPACITY if a row needs more than 128 entries, a bin more than 256
  * or a friction history more than 64 contacts; VB_ENONFINITE if the state
  * becomes NaN or infinite (the context then needs vb_set_state again);

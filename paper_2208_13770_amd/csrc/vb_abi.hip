@@ -87,6 +87,11 @@ struct vb_ctx {
   int32_t hist_snap_cap = 0;   // entries per slot hist_snap holds
   PX *snap_px = nullptr;
   PV *snap_pv = nullptr;
+  // overflow counters read back after each block of steps (pinned, two slots),
+  // so that a call stops launching once a row, a bin or a history overflowed
+  int32_t *ovf_host = nullptr;
+  hipEvent_t ovf_ev[2] = {nullptr, nullptr};
+  int32_t ovf_n = 0;    // read-backs requested in the current pass of vb_run
   float4 *bp = nullptr;
   int32_t *cnt = nullptr, *nbr = nullptr;
   int32_t width = 0;
@@ -182,6 +187,9 @@ static void free_all(vb_ctx *c) {
   if (c->step_base_d) (void)hipFree(c->step_base_d);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
+  for (hipEvent_t e : c->ovf_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->ovf_host) (void)hipHostFree(c->ovf_host);
 }
 
 static std::string check_params(const vb_params &p, int64_t n) {
@@ -720,11 +728,43 @@ static vb_status capture_block(vb_ctx *c, int cur) {
 // Queues n_steps steps; records go to hist_d[r * n_sys + s].  Blocks of
 // STATS_RING steps run as one replayed graph when nothing in them needs the
 // host (no timing, first step, forced broad phase or storage re-sort).
-static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
+// After a block of steps: requests the overflow counters and looks at those
+// requested after the block before, which has finished by then (one block
+// stays queued ahead, so the device does not wait).  *seen is set when they
+// show a row, a bin or a history beyond its capacity: the rest of the call
+// would be run again anyway.
+static vb_status overflow_seen(vb_ctx *c, bool *seen) {
+  *seen = false;
+  if (!c->ovf_host) {
+    HIP_OK(c, hipHostMalloc(reinterpret_cast<void **>(&c->ovf_host), 6 * sizeof(int32_t)));
+    for (hipEvent_t &e : c->ovf_ev) HIP_OK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  if (c->ovf_n > 0) {
+    const int prev = (c->ovf_n - 1) & 1;
+    HIP_OK(c, hipEventSynchronize(c->ovf_ev[prev]));
+    const int32_t *o = c->ovf_host + 3 * prev;
+    if (o[0] > c->width || o[1] > c->bin_cap || o[2] > c->hcap) {
+      *seen = true;
+      return VB_OK;
+    }
+  }
+  const int k = c->ovf_n & 1;
+  HIP_OK(c, hipMemcpyAsync(c->ovf_host + 3 * k, c->overflow, 3 * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipEventRecord(c->ovf_ev[k], c->stream));
+  ++c->ovf_n;
+  return VB_OK;
+}
+
+// Queues n_steps steps; *done receives the steps queued, fewer than n_steps
+// when an overflow stopped the call early.  With timing on, four events per
+// step take the kernels' own start and end times: binning start and
+// pair-search end, step-kernel start and end.
+static vb_status run_steps(vb_ctx *c, int32_t n_steps, int32_t *done) {
   vb_status st;
-  // with timing on, four events per step take the kernels' own start and end
-  // times: binning start and pair-search end, step-kernel start and end
-  if (c->timing && (st = ensure_events(c, 4 * (size_t)n_steps)) != VB_OK) return st;
+  bool seen = false;
+  c->ovf_n = 0;
+  *done = 0;
   int32_t pending = 0;
   for (int32_t i = 0; i < n_steps;) {
     const bool block = c->use_graphs && !c->timing && !c->first && !c->force_pending &&
@@ -747,6 +787,9 @@ static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
                                     (int32_t)(c->step - STATS_RING), STATS_RING,
                                     c->hist_d + (int64_t)i * c->n_sys, c->stream));
       i += STATS_RING;
+      *done = i;
+      if ((st = overflow_seen(c, &seen)) != VB_OK) return st;
+      if (seen) return VB_OK;
       continue;
     }
     hipEvent_t *e = c->timing ? &c->ev[4 * (size_t)i] : nullptr;
@@ -762,9 +805,15 @@ static vb_status run_steps(vb_ctx *c, int32_t n_steps) {
                                     c->hist_d + (int64_t)(i + 1 - pending) * c->n_sys,
                                     c->stream));
       pending = 0;
+      *done = i + 1;
+      if (i + 1 < n_steps) {
+        if ((st = overflow_seen(c, &seen)) != VB_OK) return st;
+        if (seen) return VB_OK;
+      }
     }
     ++i;
   }
+  *done = n_steps;
   return VB_OK;
 }
 
@@ -794,6 +843,7 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
   c->fresh = 0;
   vb_status st;
   if ((st = alloc_hist(c, n_steps)) != VB_OK) return st;
+  if (c->timing && (st = ensure_events(c, 4 * (size_t)n_steps)) != VB_OK) return st;
   if (!c->snap_px) {
     HIP_OK(c, dalloc(&c->snap_px, c->slots));
     HIP_OK(c, dalloc(&c->snap_pv, c->slots));
@@ -821,14 +871,18 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
   const int64_t step0 = c->step, sort0 = c->next_sort;
   const int first0 = c->first;
   for (int attempt = 0;; ++attempt) {
-    if ((st = run_steps(c, n_steps)) != VB_OK) return st;
+    int32_t done = 0;
+    if ((st = run_steps(c, n_steps, &done)) != VB_OK) return st;
     int32_t ovf[3] = {0, 0, 0};
     HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    if (ovf[0] <= c->width && ovf[1] <= c->bin_cap && ovf[2] <= c->hcap) break;
-    {  // a diverged state piles up in the outermost cells: report that, not the bins
-      std::vector<vb_step_record> rec((size_t)n_steps * c->n_sys);
-      if ((st = read_records(c, rec, n_steps, step0)) != VB_OK) return st;
+    if (ovf[0] <= c->width && ovf[1] <= c->bin_cap && ovf[2] <= c->hcap) {
+      if (done != n_steps) return fail(c, VB_EDEVICE, "internal: a call stopped without overflow");
+      break;
+    }
+    if (done > 0) {  // a diverged state piles up in the outermost cells: report that, not the bins
+      std::vector<vb_step_record> rec((size_t)done * c->n_sys);
+      if ((st = read_records(c, rec, done, step0)) != VB_OK) return st;
     }
     if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || ovf[2] > MAX_HIST || attempt >= 4) {
       c->loaded = 0;

@@ -254,6 +254,29 @@ def test_row_overflow_is_regrown():
     assert np.array_equal(xw, xn) and np.array_equal(vw, vn)
 
 
+def test_overflow_stops_a_long_call_early():
+    """A 1,100-step call whose rows overflow at once stops launching after its
+    first blocks of steps, grows the rows and runs again from its start: the
+    state is bit-identical to wide rows, and the records and timing cover every
+    step of the call (contacts and kinetic energy equal those of the wide run)."""
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=5)[0]
+    say("overflow in a long call")
+    n = 1100
+    xw, vw, hw = gpu_trajectory([s], n, max_neighbors=64)
+    with GpuRun([s], {"max_neighbors": 2}) as g:
+        vb.vb_set_timing(g.ctx, 1)
+        h = g.run(n)
+        pt = vb.vb_phase_times(g.ctx)
+        xn, vn, _ = g.state()
+        assert g.info()["row_width"] > 2 and g.info()["step"] == n
+    assert np.array_equal(xw, xn) and np.array_equal(vw, vn)
+    assert len(h[0]) == n and h[0]["step"].tolist() == list(range(n))
+    assert np.array_equal(h[0]["contacts"], hw[0]["contacts"])
+    assert np.array_equal(h[0]["kinetic_energy"], hw[0]["kinetic_energy"])
+    assert pt["steps"] == n and pt["rebuild_steps"] == int(h[0]["rebuilt"].sum())
+
+
 def test_checkpoint_resume_bitwise():
     """Resume from (x^n, v^{n-1/2}) in a new context continues bit-identically."""
     import torch
