@@ -34,6 +34,11 @@ MUT = [
  ("friction history dropped", "          for (int c = 0; c < 3; c++) s[c] = old->xi[3 * h + c];", "          ;"),
  ("friction tangent not projected", "          s[c] = (s[c] - sn * nrm[c]) + vt[c] * p->dt;", "          s[c] = s[c] + vt[c] * p->dt;"),
  ("plane damping sign", "double fm = p->kn * delta - p->gamma_n * vn;\n        f[0] += fm * pl[0];", "double fm = p->kn * delta + p->gamma_n * vn;\n        f[0] += fm * pl[0];"),
+ ("kinetic energy of the half-step velocity", "ke += 0.5 * (vfull[0] * vfull[0] + vfull[1] * vfull[1] + vfull[2] * vfull[2]) / invm[i];", "ke += 0.5 * (vh[3 * i] * vh[3 * i] + vh[3 * i + 1] * vh[3 * i + 1] + vh[3 * i + 2] * vh[3 * i + 2]) / invm[i];"),
+ ("kinetic energy without 1/2", "ke += 0.5 * (vfull[0] * vfull[0]", "ke += (vfull[0] * vfull[0]"),
+ ("max_excess without the skin", "double excess = disp - skin_test[i];", "double excess = disp;"),
+ ("list_pairs as contact count", "r->list_pairs = p->skin_mode == ORC_NAIVE ? 0 : list_pairs;", "r->list_pairs = p->skin_mode == ORC_NAIVE ? 0 : C.n;"),
+ ("violators off by one", "if (disp > skin_test[i]) viol++;", "if (disp > skin_test[i]) viol += 2;"),
 ]
 dst = os.path.join(tempfile.mkdtemp(prefix='orc_mut_'), 'repo')
 results = []

@@ -10,6 +10,7 @@ oracle/orc.c.
 """
 import json
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -224,6 +225,103 @@ def test_constant_gravity_exact(orc):
         xo, vo, _, _ = orc.run(p, x0, v0, np.array([2.0 ** -6]), np.array([1.0]), n)
         assert np.array_equal(xo[0], x0[0] + n * dt * v0[0] + 0.5 * n * n * dt * dt * g)
         assert np.array_equal(vo[0], v0[0] + (n - 0.5) * dt * g)
+
+
+# ---------------------------------------------------------------- the step record
+def _exact(frac):
+    """float of a Fraction that FP64 holds exactly (the closed forms below are
+    chosen so that it does)."""
+    f = float(frac)
+    assert Fraction(f) == frac
+    return f
+
+
+def test_kinetic_energy_record_is_exact_under_gravity(orc):
+    """The record of step n holds sum_p m_p |v^n_p|^2 / 2 with the full-step
+    velocity v^n of velocity Verlet (Sec. 3.1, Sec. 5.1).  Under constant gravity
+    and without contacts, v^n = v^0 + n dt g exactly; with dyadic data every term
+    and every partial sum is exact, so the record equals the closed form bit for
+    bit.  Masses 2, 1/2 and 1 make a missing factor 1/2 or the half-step velocity
+    v^{n+1/2} visible."""
+    dt = Fraction(1, 2 ** 10)
+    g = (Fraction(0), Fraction(-1, 4), Fraction(1, 8))
+    x0 = np.array([[0.5, 0.5, 0.5], [0.25, 0.75, 0.5], [0.75, 0.25, 0.5]])
+    v0 = [(Fraction(1, 32), Fraction(1, 16), Fraction(-1, 64)),
+          (Fraction(-3, 64), Fraction(0), Fraction(5, 128)),
+          (Fraction(0), Fraction(-7, 256), Fraction(1, 16))]
+    invm = [Fraction(1, 2), Fraction(2), Fraction(1)]
+    p = {"skin_mode": 0, "K": 200.0, "dt": float(dt), "cell_size": 2.0 ** -3, "eps": 0.0,
+         "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1.0, "gamma_n": 0.0,
+         "g": tuple(float(t) for t in g)}
+    steps = 300
+    _, _, h, _ = orc.run(p, x0, np.array([[float(c) for c in v] for v in v0]),
+                         np.full(3, 2.0 ** -6), np.array([float(m) for m in invm]), steps)
+    assert h["contacts"].sum() == 0
+    for n in range(steps):
+        ke = sum(Fraction(1, 2) / m * sum((v[a] + n * dt * g[a]) ** 2 for a in range(3))
+                 for v, m in zip(v0, invm))
+        assert h["kinetic_energy"][n] == _exact(ke), n
+
+
+@pytest.mark.parametrize("K", [3, 50, 200])
+def test_max_excess_record_in_free_flight(orc, K):
+    """Eq. update in free flight: after the broad phase at step r the list holds the
+    skins K |v_p| dt (Eq. skin_formulus1, uncapped here), and after step n particle p
+    is (n + 1 - r) |v_p| dt from x0 (a straight line, Sec. 2).  The record's
+    max_excess is therefore max_p (n + 1 - r - K) |v_p| dt: taken by the fastest
+    particle once the skins are exceeded and by the slowest before.  The violator
+    count is every particle exactly when n + 1 - r > K.  Dyadic data: exact."""
+    speeds = [2.0 ** -4, 2.0 ** -5, 2.0 ** -6]
+    s = synth.free_flight_system(4, speeds, seed=K + 11, K=float(K))
+    x, v, rc, invm = arrays(s)
+    moving = np.abs(v).max(axis=1)
+    vmin, vmax = Fraction(moving.min()), Fraction(moving.max())
+    assert vmin < vmax
+    dt = Fraction(s.params["dt"])
+    steps = 3 * (K + 1) + 7
+    _, _, h, _ = orc.run(s.params, x, v, rc, invm, steps)
+    r = 0
+    for n in range(steps):
+        if h["rebuilt"][n]:
+            r = n
+        k = n + 1 - r - K
+        expect = k * (vmax if k >= 0 else vmin) * dt
+        assert h["max_excess"][n] == _exact(expect), n
+        assert h["violators"][n] == (len(moving) if k > 0 else 0), n
+
+
+def test_list_pairs_record_counts_the_lattice_bonds(orc):
+    """A lattice at rest with spacing exactly 2 R_C: every nearest-neighbour pair
+    touches (delta = 0: no contact, Eq. delta) and lies within R_NL,i + R_NL,j of
+    Alg. 1 (skin 0 at rest, Eq. skin_formulus1), diagonal pairs do not.  The record's
+    list_pairs is then the closed-form number of lattice bonds at every step, its
+    contact count 0, and the list returned is that many pairs."""
+    nx, ny, nz = 5, 4, 3
+    R = 2.0 ** -6
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    x = (np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1) + 8.0) * 2 * R
+    n = len(x)
+    p = {"skin_mode": 0, "K": 200.0, "dt": 2.0 ** -10, "cell_size": 2.0 ** -3, "eps": 2e-6,
+         "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1.0, "gamma_n": 0.0, "g": (0, 0, 0)}
+    bonds = (nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)
+    _, _, h, lst = orc.run(p, x, np.zeros((n, 3)), np.full(n, R), np.ones(n), 20, want_list=True)
+    assert (h["list_pairs"] == bonds).all()
+    assert (h["contacts"] == 0).all()
+    assert len(lst) == bonds
+
+
+def test_list_pairs_record_is_the_list_in_use(orc):
+    """The record of the last step counts the pairs of the list that step used,
+    which is the list orc_run returns (Def. verletlist); at every step it holds
+    at least the contacts (superset, Sec. 4.2)."""
+    s = colliding(8)
+    x, v, rc, invm = arrays(s)
+    _, _, h, lst = orc.run(dict(s.params, check_superset=1), x, v, rc, invm, 150, want_list=True)
+    assert h["list_pairs"][-1] == len(lst)
+    assert (h["list_pairs"] >= h["contacts"]).all() and h["missed"].sum() == 0
+    # the count changes only at a broad phase
+    changed = np.nonzero(np.diff(h["list_pairs"]))[0] + 1
+    assert h["rebuilt"][changed].all()
 
 
 # ---------------------------------------------------------------- fixed interval, capped skin (R4)
