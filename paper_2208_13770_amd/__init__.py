@@ -165,10 +165,43 @@ def vb_batch_create(params_list, n_list, stream=None):
     return ctx
 
 
+def _device_ptrs(*specs):
+    """Addresses of the tensors in specs, (name, tensor, dtype, shape) each, after
+    checking that every one is a contiguous tensor of its dtype and shape on the
+    GPU: the library writes or reads exactly that many elements there, so a wrong
+    buffer is refused here, before any device access.  A shape may be a callable
+    (evaluated once the checks that need no context have passed).  Layouts are
+    checked for every tensor before the device of any."""
+    import torch
+    for name, t, dtype, _ in specs:
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name} must be a torch tensor, not {type(t).__name__}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, not {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    for name, t, _, shape in specs:
+        want = tuple(shape() if callable(shape) else shape)
+        if tuple(t.shape) != want:
+            raise ValueError(f"{name} must have shape {list(want)}, not {list(t.shape)}")
+    for name, t, _, _ in specs:
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a GPU tensor")
+    return [t.data_ptr() for _, t, _, _ in specs]
+
+
+def _n_total(ctx):
+    return vb_get_info(ctx)["n_total"]
+
+
 def vb_set_state(ctx, x, v, rc, invm, v_is_half_step=False):
     """x, v: float64 [N,3] device tensors; rc, invm: float32 [N] device tensors."""
-    _check(lib().vb_set_state(ctx, x.data_ptr(), v.data_ptr(), rc.data_ptr(), invm.data_ptr(),
-                              int(bool(v_is_half_step))), ctx)
+    import torch
+    n = lambda: (_n_total(ctx),)  # noqa: E731
+    px, pv, pr, pm = _device_ptrs(("x", x, torch.float64, lambda: n() + (3,)),
+                                  ("v", v, torch.float64, lambda: n() + (3,)),
+                                  ("rc", rc, torch.float32, n), ("invm", invm, torch.float32, n))
+    _check(lib().vb_set_state(ctx, px, pv, pr, pm, int(bool(v_is_half_step))), ctx)
 
 
 def vb_run(ctx, n_steps, want_history=True):
@@ -181,21 +214,38 @@ def vb_run(ctx, n_steps, want_history=True):
 
 
 def vb_get_state(ctx, x=None, v=None):
+    """Fills x, v (float64 [N,3] device tensors, either may be None); returns True
+    when v holds the half-step velocity."""
+    import torch
+    shape = lambda: (_n_total(ctx), 3)  # noqa: E731
+    specs = [(name, t, torch.float64, shape) for name, t in (("x", x), ("v", v)) if t is not None]
+    ptrs = iter(_device_ptrs(*specs))
+    px = next(ptrs) if x is not None else None
+    pv = next(ptrs) if v is not None else None
     half = ctypes.c_int32(0)
-    _check(lib().vb_get_state(ctx, x.data_ptr() if x is not None else None,
-                              v.data_ptr() if v is not None else None, ctypes.byref(half)), ctx)
+    _check(lib().vb_get_state(ctx, px, pv, ctypes.byref(half)), ctx)
     return bool(half.value)
 
 
 def vb_get_pairs(ctx, sys, which, pairs=None, delta=None):
     """Fills pairs (int32 [cap,2]) and delta (float64 [cap]) device tensors; returns
     the total count.  Call with pairs=None to get the count only."""
+    import torch
     n = ctypes.c_int64(0)
-    cap = int(pairs.shape[0]) if pairs is not None else 0
-    _check(lib().vb_get_pairs(ctx, int(sys), int(which),
-                              pairs.data_ptr() if pairs is not None else None,
-                              delta.data_ptr() if delta is not None else None, cap,
-                              ctypes.byref(n)), ctx)
+    cap = 0
+    pp = pd = None
+    if pairs is not None:
+        if not isinstance(pairs, torch.Tensor) or pairs.dim() != 2:
+            raise ValueError("pairs must be a [cap, 2] tensor")
+        cap = int(pairs.shape[0])
+        specs = [("pairs", pairs, torch.int32, (cap, 2))]
+        if delta is not None:
+            specs.append(("delta", delta, torch.float64, (cap,)))
+        ptrs = _device_ptrs(*specs)
+        pp, pd = ptrs[0], (ptrs[1] if delta is not None else None)
+    elif delta is not None:
+        raise ValueError("delta needs pairs")
+    _check(lib().vb_get_pairs(ctx, int(sys), int(which), pp, pd, cap, ctypes.byref(n)), ctx)
     return int(n.value)
 
 
@@ -203,21 +253,37 @@ def vb_get_history(ctx, partner=None, spring=None):
     """Fills partner (int32 [N, cap]) and spring (float64 [N, cap, 3]) device
     tensors with the friction history; returns the largest contact count.  Call
     with partner=None to get the count only."""
-    cap = int(partner.shape[1]) if partner is not None else 0
+    cap, pp, ps = _history_ptrs(ctx, partner, spring)
     need = ctypes.c_int32(0)
-    code = lib().vb_get_history(ctx, partner.data_ptr() if partner is not None else None,
-                                spring.data_ptr() if spring is not None else None, cap,
-                                ctypes.byref(need))
+    code = lib().vb_get_history(ctx, pp, ps, cap, ctypes.byref(need))
     if code == VB_ECAPACITY and partner is None:
         return int(need.value)
     _check(code, ctx)
     return int(need.value)
 
 
+def _history_ptrs(ctx, partner, spring):
+    """(cap, partner address, spring address) of a friction history: partner int32
+    [N, cap], spring float64 [N, cap, 3] (both None: cap 0)."""
+    import torch
+    if partner is None and spring is None:
+        return 0, None, None
+    if partner is None or spring is None:
+        raise ValueError("partner and spring go together")
+    if not isinstance(partner, torch.Tensor) or partner.dim() != 2:
+        raise ValueError("partner must be an [N, cap] tensor")
+    cap = int(partner.shape[1])
+    n = lambda: (_n_total(ctx), cap)  # noqa: E731
+    pp, ps = _device_ptrs(("partner", partner, torch.int32, n),
+                          ("spring", spring, torch.float64, lambda: n() + (3,)))
+    return cap, pp, ps
+
+
 def vb_set_history(ctx, partner, spring):
     """Loads a friction history (the tensors of vb_get_history) right after
     vb_set_state."""
-    _check(lib().vb_set_history(ctx, partner.data_ptr(), spring.data_ptr(), int(partner.shape[1])), ctx)
+    cap, pp, ps = _history_ptrs(ctx, partner, spring)
+    _check(lib().vb_set_history(ctx, pp, ps, cap), ctx)
 
 
 def vb_force_rebuild(ctx):
