@@ -113,14 +113,8 @@ def main(argv=None):
     try:
         vb.vb_set_state(ctx, x, v, rc, invm)
 
-        def run_window(K, steps):
-            vb.vb_set_K(ctx, K)
-            t1 = time.perf_counter()
-            h = vb.vb_run(ctx, steps)
-            dt_ = time.perf_counter() - t1
-            rebuilds.append(int(h["rebuilt"].any(axis=0).sum()))
-            return dt_
-
+        run_window = autotune.window_runner(
+            vb, ctx, on_records=lambda h: rebuilds.append(int(h["rebuilt"].any(axis=0).sum())))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         windows, k_auto = autotune.tune(run_window, args.steps, K0=K_DEFAULT,
