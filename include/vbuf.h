@@ -66,7 +66,7 @@ typedef int32_t vb_status;
 /* How the broad-phase sphere of each particle is extended. */
 #define VB_SKIN_LOCAL 0     /* skin_p = K |v_p| dt, the paper's local skin (Eq. skin_formulus1)  */
 #define VB_SKIN_UNIFORM 1   /* skin_p = skin_uniform, the classic global Verlet skin (Eq. skin_val) */
-#define VB_NO_BUFFER 2      /* broad phase at every step with R_NL = R_C, "without Verlet buffer" */
+#define VB_NO_BUFFER 2      /* broad phase at every step with R_NL = R_C: the paper's plain baseline */
 #define VB_FIXED_INTERVAL 3 /* broad phase every fixed_interval steps with the uniform skin; the  */
                             /* fixed-update practice the automatic scheme replaces (Sec. 1, 4.2)  */
 
@@ -78,11 +78,12 @@ typedef struct vb_params {
   int32_t skin_mode;      /* VB_SKIN_LOCAL, VB_SKIN_UNIFORM, VB_NO_BUFFER or VB_FIXED_INTERVAL   */
   int32_t cap_mode;       /* 0: R_NL <= L_C/2, one-ring cell search (default);                   */
                           /* 1: R_NL <= L_C as printed in Eq. skin_formulus_mincell, two-ring    */
-  double K;               /* skin factor, "the prescribed number of skipped steps" (Sec. 4.1)   */
+  double K;               /* skin factor of Eq. skin_formulus1: the steps a skin lasts (Sec. 4.1)  */
   double dt;              /* time step                                                            */
   double cell_size;       /* L_C: the uniform cell edge of the linked-cell grid (Sec. 3.2)        */
   double skin_uniform;    /* skin of VB_SKIN_UNIFORM and VB_FIXED_INTERVAL                        */
-  double eps;             /* absolute margin of the FP32 broad-phase inclusion test (>= 0)        */
+  double eps;             /* absolute margin of the FP32 broad-phase inclusion test, at least     */
+                          /* 2^-19 max(|lo|, |hi|) (16 FP32 ulps of the largest coordinate)       */
   double lo[3], hi[3];    /* box corners; a planar wall on each face                               */
   double kn, gamma_n;     /* normal spring stiffness and dashpot coefficient                       */
   double gravity[3];      /* gravitational acceleration                                            */

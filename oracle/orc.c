@@ -18,7 +18,7 @@
  *   R4  the validity test compares the displacement with skin_eff = R_NL - R_C,
  *       the skin after the cap (the proof of the theorem needs R_NL = R_C + skin).
  *   R5  Alg. 1 also pairs particles inside the same cell (P_b before P_a), and
- *       "immediate neighbour" cells are the 26 Moore neighbours.
+ *       the neighbour cells of Alg. 1 are the 26 Moore neighbours.
  *   R6  inequalities exactly as printed: broad phase <=, contact iff delta > 0,
  *       list invalid iff displacement > skin.
  *   R7  a broad phase always runs at step 0.
@@ -197,8 +197,8 @@ static double overlap(const double *xi, const double *xj, double ri, double rj) 
   return ri + rj - dist3(xi, xj);
 }
 
-/* The contact set by definition: every pair whose overlap is positive (Eq. delta,
- * "if the overlap is positive, the two particles collide"). */
+/* The contact set by definition: every pair whose overlap exceeds zero (Eq. delta,
+ * Sec. 3.2: such a pair collides, one with zero or negative overlap does not). */
 static void contacts_brute(int64_t n, const double *x, const double *rc, pairvec *out) {
   for (int64_t i = 0; i < n; i++)
     for (int64_t j = i + 1; j < n; j++)

@@ -30,7 +30,7 @@
 enum {
   ORC_SKIN_LOCAL = 0,      /* skin_p = K |v_p| dt (the paper's method)              */
   ORC_SKIN_UNIFORM = 1,    /* skin_p = skin_uniform for every particle               */
-  ORC_NO_BUFFER = 2,       /* broad phase every step on R_NL = R_C ("without buffer") */
+  ORC_NO_BUFFER = 2,       /* broad phase every step on R_NL = R_C (plain baseline) */
   ORC_FIXED_INTERVAL = 3,  /* broad phase every fixed_interval steps, uniform skin   */
   ORC_NAIVE = 4            /* no list at all: contacts by brute force every step     */
 };

@@ -200,7 +200,6 @@ static std::string check_params(const vb_params &p, int64_t n) {
   if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return "dt must be positive";
   if (!(p.cell_size > 0.0) || !std::isfinite(p.cell_size)) return "cell_size must be positive";
   if (!(p.K >= 0.0) || !std::isfinite(p.K)) return "K must be >= 0";
-  if (!(p.eps >= 0.0) || !std::isfinite(p.eps)) return "eps must be >= 0";
   if (!(p.skin_uniform >= 0.0) || !std::isfinite(p.skin_uniform)) return "skin_uniform must be >= 0";
   if (!(p.kn >= 0.0) || !(p.gamma_n >= 0.0) || !std::isfinite(p.kn) || !std::isfinite(p.gamma_n))
     return "kn and gamma_n must be finite and >= 0";
@@ -209,6 +208,13 @@ static std::string check_params(const vb_params &p, int64_t n) {
       return "box must satisfy lo < hi";
     if (!std::isfinite(p.gravity[a])) return "gravity must be finite";
   }
+  // the FP32 inclusion test of the broad phase returns a superset of the exact
+  // list only with a positive margin: at least 16 FP32 ulps of the largest
+  // coordinate (the rounding of the reference positions and of the distance)
+  double xmax = 0.0;
+  for (int a = 0; a < 3; ++a) xmax = std::max(xmax, std::max(std::fabs(p.lo[a]), std::fabs(p.hi[a])));
+  if (!std::isfinite(p.eps) || !(p.eps >= std::ldexp(xmax, -19)))
+    return "eps must be at least 2^-19 times the largest box coordinate";
   if (p.max_neighbors < 1 || p.max_neighbors > MAX_ROW) return "max_neighbors must be 1..128";
   if (p.skin_mode == VB_FIXED_INTERVAL && p.fixed_interval < 1) return "fixed_interval must be >= 1";
   if (p.reorder_interval < 0) return "reorder_interval must be >= 0";

@@ -170,7 +170,7 @@ def free_flight_system(n_side: int, speeds, seed: int, K: float, dt: float = 2.0
     side = spacing * (n_side - 1) + 2 * 2.0 ** -1
     params = {
         "skin_mode": 0, "cap_mode": 0, "K": float(K), "dt": float(dt), "cell_size": cell_size,
-        "skin_uniform": 0.0, "eps": 0.0, "lo": (0.0, 0.0, 0.0), "hi": (side, side, side),
+        "skin_uniform": 0.0, "eps": 2.0 ** -17, "lo": (0.0, 0.0, 0.0), "hi": (side, side, side),
         "kn": 1.0, "gamma_n": 0.0, "g": (0.0, 0.0, 0.0), "max_neighbors": 32,
         "fixed_interval": 1,
     }

@@ -75,3 +75,18 @@ def test_params_from_generator_dict():
     q = vb.make_params(s.params)
     assert q.K == 200.0 and q.max_neighbors == 32 and q.hi[2] == s.params["hi"][2]
     assert q.cell_size == s.params["cell_size"]
+
+
+@pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")
+@pytest.mark.parametrize("eps", [0.0, 1.8e-6, float("nan")])
+def test_create_refuses_a_margin_below_the_fp32_floor(eps):
+    """R10: the FP32 broad phase returns a superset of the exact list only with a
+    positive margin of at least 16 FP32 ulps of the largest coordinate
+    (2^-19 = 1.907e-6 for a unit box).  The parameters are checked before any
+    device call, so this runs without a GPU."""
+    import synth
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    assert s.params["hi"][0] == 1.0 and s.params["eps"] >= 2.0 ** -19
+    with pytest.raises(vb.VbError) as e:
+        vb.vb_create(dict(s.params, eps=eps), s.n, stream=ctypes.c_void_p(0))
+    assert e.value.code == vb.VB_EINVAL and "eps" in str(e.value)
