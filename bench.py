@@ -17,15 +17,17 @@ oracle.
 
 Prints ONE JSON line:
   value       whole-job throughput, Mparticle*step/s, of the method (K = 200) with
-              the state resident in HBM (a run without instrumentation);
-  repeats     mean, spread and range of the wall time over --repeats such runs
-              (the first is the one `value` comes from);
+              the state resident in HBM: the mean over --repeats runs without
+              instrumentation, each of the same steps from step 0 (Sec. 5.3 averages
+              at least a hundred measurements);
+  repeats     mean, spread and range of the wall time over those runs;
   roofline    the step kernel's algorithmic bytes per launch over its mean duration,
-              taken by HIP events on the kernel in an identical second run, against
+              taken by HIP events on the kernel in an identical further run, against
               the 8 TB/s HBM peak;
   plain       the same steps with the broad phase at every step ("without Verlet
               buffer"), and Eq. impr between the two;
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload, one core.
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload, one core,
+              with the host's CPU model and core count.
 """
 import argparse
 import json
@@ -39,10 +41,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of one particle in one step of the fused kernel: read the
-# position record (32 B), velocity record (32 B), broad-phase record (16 B) and
-# row length (4 B); write position and velocity (64 B); plus 4 B per row entry.
-STEP_BYTES_FIXED = 148
+# Algorithmic bytes of one particle in one step of the fused step kernel (a1, a2,
+# a6), three counts, each plus 4 B per Verlet-list entry read (n_v entries per
+# particle, n_v = 2 list_pairs / N):
+#  - ALG: the hot-path scope's count for an FP32 state: read position and radius
+#    (16 B), velocity and inverse mass (16), reference position and extended
+#    radius (16) and the row length (4); write position and velocity (32).  The
+#    roofline's `frac` uses it.
+#  - FP64: the same with the FP64 state this library keeps (parity needs it):
+#    read x and v (48 B), R_C and 1/m (8), x0 and R_NL (16), row length (4);
+#    write x and v (48).
+#  - KERNEL: what the step kernel's records move: read the position record
+#    (32 B: x, R_C, original index), the velocity record (32: v, 1/m), x0 and
+#    R_NL (16) and the row length (4); write both records (64) and the coded
+#    position the next step's pre-test gathers (8).
+STEP_BYTES = {"alg": 84, "fp64": 124, "kernel": 156}
 STEP_BYTES_PER_ENTRY = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_M2_traffic.json")
 
@@ -80,35 +93,49 @@ def copy_bandwidth(torch, nbytes=4 << 30):
     return 2 * nbytes / dt / 1e9
 
 
-def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500):
-    """One context over `systems` (a batch when more than one); returns the wall
-    time of `steps` timed steps, the [n_sys, steps] records, phase times and info.
-    The steps go to vb_run in calls of at most `call_steps`: a call in which a
-    row or a cell bin outgrows its capacity is run again from its own start."""
+def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500, repeats=1):
+    """One context over `systems` (a batch when more than one).  After `warmup`
+    untimed steps, `repeats` timed runs of `steps` steps, each from the loaded
+    initial state (step 0, whose broad phase is timed).  Returns the wall times,
+    the first run's [n_sys, steps] records, phase times of the last run and the
+    context info.  The steps go to vb_run in calls of at most `call_steps`."""
     params = [dict(s.params, **overrides) for s in systems]
     ctx = vb.vb_batch_create(params, [s.n for s in systems])
+    walls, hist = [], None
     try:
         x, v, rc, invm = vb.state_tensors(systems)
         if warmup > 0:
             vb.vb_set_state(ctx, x, v, rc, invm)
             vb.vb_run(ctx, warmup, want_history=False)
-        vb.vb_set_state(ctx, x, v, rc, invm)  # the timed steps start at step 0
+        cs = max(1, call_steps)
+        for r in range(max(1, repeats)):
+            vb.vb_set_state(ctx, x, v, rc, invm)  # the timed steps start at step 0
+            vb.vb_set_timing(ctx, timing)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            parts = [vb.vb_run(ctx, min(cs, steps - k), want_history=(r == 0))
+                     for k in range(0, steps, cs)]
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            if r == 0:
+                hist = np.concatenate(parts, axis=1) if parts else vb.vb_run(ctx, 0)
         del x, v, rc, invm
-        vb.vb_set_timing(ctx, timing)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        parts = []
-        for k in range(0, steps, max(1, call_steps)):
-            parts.append(vb.vb_run(ctx, min(max(1, call_steps), steps - k)))
-        hist = np.concatenate(parts, axis=1) if parts else vb.vb_run(ctx, 0)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         pt = vb.vb_phase_times(ctx)
         info = vb.vb_get_info(ctx)
     finally:
         vb.vb_destroy(ctx)
         torch.cuda.synchronize()
-    return wall, hist, pt, info
+    return walls, hist, pt, info
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(system, steps):
@@ -159,8 +186,9 @@ def main():
     ap.add_argument("--call-steps", type=int, default=500,
                     help="steps per vb_run call (a call whose rows or cell bins overflow runs "
                          "again from its own start)")
-    ap.add_argument("--repeats", type=int, default=5,
-                    help="runs of the same steps without instrumentation, for the spread of the wall time")
+    ap.add_argument("--repeats", type=int, default=100,
+                    help="timed runs of the same steps without instrumentation, each from step 0 "
+                         "(value is their mean; the plain baseline runs a tenth as many)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method's "
@@ -187,38 +215,45 @@ def main():
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
 
-    # the throughput comes from a run without instrumentation; the kernel
-    # durations from an identical run with HIP events on every kernel (the
-    # events cost a few per cent of wall time)
+    # the throughput comes from runs without instrumentation (mean over the
+    # repeats, each from step 0 of the loaded state); the kernel durations from
+    # an identical run with HIP events on every kernel (the events cost a few
+    # per cent of wall time)
     cs = args.call_steps
-    wall, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False, cs)
+    walls, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False, cs,
+                                    repeats=args.repeats)
+    wall = float(np.mean(walls))
     value = n * args.steps / wall / 1e6
-    walls = [wall]
-    for _ in range(max(args.repeats, 1) - 1):
-        w_r, h_r, _, _ = run_mode(vb, torch, systems, args.steps, 0, {}, False, cs)
-        assert np.array_equal(h_r["contacts"], hist["contacts"])
-        walls.append(w_r)
-    wall_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True, cs)
+    walls_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True, cs)
+    wall_ev = walls_ev[0]
     assert np.array_equal(hist_ev["contacts"], hist["contacts"])
     rebuilt = hist["rebuilt"].astype(bool)            # [n_sys, steps]
     n_rebuild = int(rebuilt.sum())                     # broad phases over all systems
     any_rebuild = int(rebuilt.any(axis=0).sum())       # steps at which some system rebuilt
     pairs = hist["list_pairs"].sum(axis=0)             # per step, all systems
     step_ms = pt["ms_step"] / max(pt["steps"], 1)
-    bytes_per_launch = float(np.mean(STEP_BYTES_FIXED * n + 2 * STEP_BYTES_PER_ENTRY * pairs))
-    achieved = bytes_per_launch / (step_ms * 1e-3) / 1e9
-    log(f"method K=200: {wall * 1e3:.1f} ms for {args.steps} steps, {n_rebuild} broad phases "
-        f"({any_rebuild} steps with one), step kernel {step_ms * 1e3:.1f} us, broad-phase "
-        f"launches {pt['ms_rebuild']:.1f} ms total")
+    counts = {}
+    for key, fixed in STEP_BYTES.items():
+        b = float(np.mean(fixed * n + 2 * STEP_BYTES_PER_ENTRY * pairs))
+        a = b / (step_ms * 1e-3) / 1e9
+        counts[key] = {"bytes_per_particle": f"{fixed} + {STEP_BYTES_PER_ENTRY} n_v",
+                       "bytes_per_launch": b, "achieved": a, "frac": a / HBM_PEAK_GBS}
+    n_v = float(np.mean(2.0 * pairs / max(n, 1)))
+    log(f"method K=200: {wall * 1e3:.1f} ms mean of {len(walls)} runs of {args.steps} steps, "
+        f"{n_rebuild} broad phases ({any_rebuild} steps with one), step kernel "
+        f"{step_ms * 1e3:.1f} us, broad-phase launches {pt['ms_rebuild']:.1f} ms total")
 
     plain = None
     if not args.no_plain:
-        wall_p, hist_p, _, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
-                                        {"skin_mode": vb.VB_NO_BUFFER}, False, cs)
+        walls_p, hist_p, _, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
+                                         {"skin_mode": vb.VB_NO_BUFFER}, False, cs,
+                                         repeats=max(1, args.repeats // 10))
+        wall_p = float(np.mean(walls_p))
         _, _, pt_p, _ = run_mode(vb, torch, systems, args.steps, 0,
                                  {"skin_mode": vb.VB_NO_BUFFER}, True, cs)
         plain = {
             "time_s": wall_p,
+            "runs": len(walls_p),
             "value": n * args.steps / wall_p / 1e6,
             "broad_phase_ms_total": pt_p["ms_rebuild"],
             "step_kernel_ms_total": pt_p["ms_step"],
@@ -234,7 +269,7 @@ def main():
         t_seq = 0.0
         for s in systems:
             w, _, _, _ = run_mode(vb, torch, [s], args.steps, 0, {}, False, cs)
-            t_seq += w
+            t_seq += w[0]
         sequential = {"time_s": t_seq, "value": n * args.steps / t_seq / 1e6,
                       "batch_speedup": t_seq / wall}
         log(f"one context per system, in turn: {t_seq * 1e3:.1f} ms "
@@ -245,7 +280,8 @@ def main():
         v_cpu, dt_cpu = cpu_baseline(systems[0], args.cpu_steps)
         cpu = {"value": v_cpu, "unit": "Mparticle*step/s", "cores": 1, "kind": "oracle",
                "sample": f"M2 workload ({n} particles), first {args.cpu_steps} steps, K=200, "
-                         f"FP64 oracle, single thread, {dt_cpu:.1f} s"}
+                         f"FP64 oracle, single thread, {dt_cpu:.1f} s",
+               "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
         log(f"cpu oracle: {v_cpu:.3f} Mparticle*step/s ({dt_cpu:.1f} s)")
 
     traffic = (measured_traffic()
@@ -269,11 +305,17 @@ def main():
                        f", tangential friction mu={args.friction:g}" if args.friction > 0 else ""),
                    "particles": n, "systems": len(systems), "steps": args.steps,
                    "steps_per_call": cs, "K": systems[0].params["K"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step", "bytes_per_launch": bytes_per_launch,
-                     "mean_launch_us": step_ms * 1e3, "copy_bandwidth_gbs": copy_gbs,
-                     "events_run_ms": wall_ev * 1e3},
+        "roofline": {"bound": "hbm", "achieved": counts["alg"]["achieved"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": counts["alg"]["frac"], "traffic": traffic,
+                     "kernel": "k_step",
+                     "bytes_note": "algorithmic bytes per launch over the kernel's mean launch "
+                                   "duration; frac uses the scope table's count (84 + 4 n_v B "
+                                   "per particle, FP32 state); byte_counts also gives the FP64 "
+                                   "state's count and what the kernel's records move; traffic is "
+                                   "the measured HBM bytes per launch (rocprofv3 counters)",
+                     "bytes_per_launch": counts["alg"]["bytes_per_launch"], "n_v": n_v,
+                     "byte_counts": counts, "mean_launch_us": step_ms * 1e3,
+                     "copy_bandwidth_gbs": copy_gbs, "events_run_ms": wall_ev * 1e3},
         "repeats": {"n": len(walls), "ms_mean": float(np.mean(walls)) * 1e3,
                     "ms_std": float(np.std(walls, ddof=1)) * 1e3 if len(walls) > 1 else 0.0,
                     "ms_min": min(walls) * 1e3, "ms_max": max(walls) * 1e3},
