@@ -42,9 +42,9 @@
  *     replaying blocks of 64 steps as one captured HIP graph; VBUF_STEP_UNROLL
  *     = 1, 2, 4 or 8 (default 8) sets the partner gathers each thread of the
  *     step kernel keeps in flight; VBUF_XCD_REMAP=1 gives each of the 8 XCDs a
- *     contiguous range of the step kernel's tiles.  A different VBUF_STEP_UNROLL
- *     is different machine code, which may round the force arithmetic
- *     differently in the last bits.
+ *     contiguous range of the step kernel's tiles.  Results are bit-identical
+ *     for every setting: the FP64 contact law and integration round every
+ *     operation (no contraction), in one fixed order.
  */
 #ifndef VBUF_H
 #define VBUF_H

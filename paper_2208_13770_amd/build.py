@@ -1,8 +1,11 @@
 """Build libvbuf.so (the C-ABI library of HIP kernels for gfx950) in-tree.
 
 Every kernel is compiled for gfx950 only, with packed-FP32 instruction selection
-disabled (-packed-fp32-ops); hipcc's host pass warns that it does not know that
-feature, which is harmless.
+disabled (-packed-fp32-ops; hipcc's host pass warns that it does not know that
+feature, which is harmless) and without floating-point contraction
+(-ffp-contract=off): the FP64 contact and integration arithmetic then rounds
+after every operation whatever the launch shape, and fused multiply-adds appear
+only where the source writes them.
 """
 import os
 import subprocess
@@ -18,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 def build(verbose: bool = False) -> str:
     cmd = [
         HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
         "-Wall", "-Wno-unused-command-line-argument",
         "-I" + os.path.join(ROOT, "include"),
         "-o", LIB + ".tmp", *SOURCES,

@@ -313,8 +313,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     auto contact = [&](const PX &o, const PV &ov) {
       double dx, dy, dz, d, delta;
       if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
-        const double inv = 1.0 / d;
-        const double nx = dx * inv, ny = dy * inv, nz = dz * inv;
+        const double nx = dx / d, ny = dy / d, nz = dz / d;
         const double vn = (mv.vx - ov.vx) * nx + (mv.vy - ov.vy) * ny + (mv.vz - ov.vz) * nz;
         const double fm = S.kn * delta - S.gamma_n * vn;
         fx += fm * nx;
@@ -486,7 +485,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const float ddx = (float)(xn[0] - (double)b.x);
     const float ddy = (float)(xn[1] - (double)b.y);
     const float ddz = (float)(xn[2] - (double)b.z);
-    const float disp = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+    const float disp = sqrtf(__fmaf_rn(ddx, ddx, __fmaf_rn(ddy, ddy, ddz * ddz)));
     const float skin_eff = b.w - me.rc;
     viol = disp > skin_eff ? 1 : 0;
     excess = disp - skin_eff;
@@ -661,6 +660,16 @@ __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int3
   for (int q = 0; q < n; ++q) out[(int64_t)q * stride] = s_slot[s_row[q * PAIRS_T + threadIdx.x]];
 }
 
+// The FP32 inclusion test of Alg. 1 on the extended spheres, |x_i - x_j| <=
+// R_NL,i + R_NL,j + eps, on squares: me = (x0_i, R_NL,i), reach = R_NL,i + eps,
+// o = (x0_j, R_NL,j).  One rounding sequence (explicit fused multiply-adds) for
+// both the LDS-staged and the direct search, so that they find the same pairs.
+__device__ __forceinline__ bool within_reach(const float4 &me, const float4 &o, float reach) {
+  const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
+  const float lim = reach + o.w;
+  return __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, ez * ez)) <= lim * lim;
+}
+
 // Four staged entries e..e+3 against the particle `me` (position and R_NL +
 // eps): each entry index is written at the row's end (offset wofs, capped at
 // the spare row wend), and the row grows by PAIRS_T for each entry within
@@ -672,9 +681,7 @@ __device__ __forceinline__ void pair_test4(const float4 *s_pos, int e, int e1, i
   const float4 o[4] = {s_pos[e], s_pos[e + 1], s_pos[e + 2], s_pos[e + 3]};
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const float ex = me.x - o[u].x, ey = me.y - o[u].y, ez = me.z - o[u].z;
-    const float lim = reach + o[u].w;
-    bool hit = ex * ex + ey * ey + ez * ez <= lim * lim;
+    bool hit = within_reach(me, o[u], reach);
     if (TAIL) hit = hit && e + u < e1;
     if (OWN) hit = hit && e + u != me_e;
     myrow[min(wofs, wend)] = (uint16_t)(e + u);
@@ -854,10 +861,7 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
                     (S.c_off + cell_key(S, ox + ix + dx, oy + iy + dy, oz + iz + dz)) * a.bin_cap;
                 for (int e = 0; e < n2; ++e) {
                   if (v2 == v && e == i) continue;
-                  const float4 o = a.bins_bp[base + e];
-                  const float ex = me.x - o.x, ey = me.y - o.y, ez = me.z - o.z;
-                  const float lim = reach + o.w;
-                  if (ex * ex + ey * ey + ez * ez <= lim * lim)
+                  if (within_reach(me, a.bins_bp[base + e], reach))
                     count = row_insert(s_row32, HALF, count, W, a.bins_so[base + e].y);
                 }
               }

@@ -4,16 +4,19 @@ The workload is M2: 256x256x64 = 4,194,304 particles, K = 200, default launch
 parameters. The oracle runs the whole system (it is O(N) per step with linked
 cells), so every particle is compared, not just a sample. The tolerance is that
 of the small-size tests: positions within 1e-5 box units and velocities within
-1e-5 v_max, element by element. Contact counts are compared exactly at every
-step. The theorem of Sec. 4.2 (method == broad phase every step) is checked
-bitwise at full size.
+1e-5 v_max, element by element; positions and velocities are also asserted
+equal to the oracle's bit for bit (the GPU evaluates the FP64 contact law and
+integration in the oracle's order, every operation rounded). Contact counts are
+compared exactly at every step. The theorem of Sec. 4.2 (method == broad phase
+every step) is checked bitwise at full size.
 """
 import numpy as np
 import pytest
 
 import oracle
+import paper_2208_13770_amd as vb
 import synth
-from tests._gpu import gpu_trajectory, host_arrays, say
+from tests._gpu import GpuRun, gpu_trajectory, host_arrays, say
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +33,13 @@ def m2():
 def test_m2_full_size_parity_with_oracle(m2):
     s = m2
     say(f"M2 full size: N={s.n}, {STEPS} steps, GPU then oracle")
-    xg, vg, hg = gpu_trajectory([s], STEPS)
+    with GpuRun([s]) as g:
+        hg = g.run(STEPS)
+        xg, vg, _ = g.state()
+        n_list = vb.vb_get_pairs(g.ctx, 0, 0)
+    # the record's list_pairs (bench.py's byte count uses it) is the list in use
+    say(f"  list pairs: record {int(hg[0]['list_pairs'][-1])}, exported list {n_list}")
+    assert hg[0]["list_pairs"][-1] == n_list
     x, v, rc, invm = host_arrays([s])
     xo, vo, ho, _ = oracle.run(s.params, x, v, rc, invm, STEPS)
     ex = np.abs(xg - xo).max()
@@ -39,6 +48,7 @@ def test_m2_full_size_parity_with_oracle(m2):
         f"contacts at the last step {int(ho['contacts'][-1])}, "
         f"broad phases GPU {int(hg[0]['rebuilt'].sum())} oracle {int(ho['rebuilt'].sum())}")
     assert ex <= TOL_X and ev <= TOL_V
+    assert np.array_equal(xg, xo) and np.array_equal(vg, vo)
     assert np.array_equal(hg[0]["contacts"], ho["contacts"])
     assert ho["contacts"][-1] > 10000
     assert np.allclose(hg[0]["kinetic_energy"], ho["kinetic_energy"], rtol=1e-9, atol=0)
@@ -79,6 +89,7 @@ def test_m3_batch_parity_with_oracle():
         xo, vo, ho, _ = _oracle_system(s, steps)
         worst_x = max(worst_x, np.abs(xg[sl] - xo).max())
         worst_v = max(worst_v, np.abs(vg[sl] - vo).max() / s.meta["v_max"])
+        assert np.array_equal(xg[sl], xo) and np.array_equal(vg[sl], vo), i
         assert np.array_equal(hg[i]["contacts"], ho["contacts"]), i
     say(f"  max|dx| = {worst_x:.3e} box units, max|dv| = {worst_v:.3e} v_max over all systems")
     assert worst_x <= TOL_X and worst_v <= TOL_V
@@ -101,6 +112,7 @@ def test_m5_sampled_parity_with_oracle():
         ev = np.abs(vg[sl[i]] - vo).max() / s.meta["v_max"]
         say(f"  system {i}: max|dx| = {ex:.3e}, max|dv| = {ev:.3e} v_max")
         assert ex <= TOL_X and ev <= TOL_V
+        assert np.array_equal(xg[sl[i]], xo) and np.array_equal(vg[sl[i]], vo)
         assert np.array_equal(hg[i]["contacts"], ho["contacts"])
     assert hg["rebuilt"][:, 0].all()
 
@@ -117,4 +129,5 @@ def test_paper_size_gravity_workloads_parity(name, steps):
     ev = np.abs(vg - vo).max() / s.meta["v_max"]
     say(f"  max|dx| = {ex:.3e}, max|dv| = {ev:.3e} v_max, contacts at the end {int(ho['contacts'][-1])}")
     assert ex <= TOL_X and ev <= TOL_V
+    assert np.array_equal(xg, xo) and np.array_equal(vg, vo)
     assert np.array_equal(hg[0]["contacts"], ho["contacts"])

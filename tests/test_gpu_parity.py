@@ -1,19 +1,25 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle, on the GPU.
 
-Tolerance (stated once, used everywhere): after a run, positions within 1e-5 box
-units and velocities within 1e-5 v_max of the oracle, element by element.  The
-HIP path keeps positions and velocities in FP64, so the observed errors are
-~1e-12; contact sets, contact counts and the reproduced closed-form rebuild
-cadences are compared exactly.  The broad phase and the validity test run in
-FP32 with the eps margin, so the Verlet list and the rebuild schedule may differ
-from the oracle's only at near-ties of those FP32 tests; such differences are
-checked to be near-ties, and the results (which by the theorem of Sec. 4.2 do
-not depend on the list) are still compared element by element.
+Bar (stated once, used everywhere): after a run, positions within 1e-5 box units
+and velocities within 1e-5 v_max of the oracle, element by element.  The HIP path
+keeps positions and velocities in FP64 and evaluates the contact law and the
+integration in the oracle's order with every operation rounded (no contraction,
+the contact normal by division, correctly rounded square root and division), so
+positions and velocities come out bit for bit equal to the oracle's, which
+every comparison below also asserts; the kinetic energy differs only by its
+summation order (rtol 1e-9).  Contact sets, contact counts and the reproduced
+closed-form rebuild cadences are compared exactly.  The broad phase and the
+validity test run in FP32 with the eps margin, so the Verlet list and the
+rebuild schedule may differ from the oracle's only at near-ties of those FP32
+tests; such differences are checked to be near-ties, and the results (which by
+the theorem of Sec. 4.2 do not depend on the list) are still compared bit for
+bit.
 """
 import numpy as np
 import pytest
 
 import oracle
+import paper_2208_13770_amd as vb
 import synth
 from tests._gpu import GpuRun, gpu_trajectory, host_arrays, say
 
@@ -32,8 +38,11 @@ def oracle_run(systems_or_one, steps, **overrides):
 def assert_close(sys_, xg, vg, xo, vo, what):
     ex = np.abs(xg - xo).max() if len(xo) else 0.0
     ev = np.abs(vg - vo).max() / sys_.meta.get("v_max", 1.0) if len(vo) else 0.0
-    say(f"  {what}: max|dx| = {ex:.3e} box units, max|dv| = {ev:.3e} v_max")
+    nd = int((xg != xo).sum() + (vg != vo).sum())
+    say(f"  {what}: max|dx| = {ex:.3e} box units, max|dv| = {ev:.3e} v_max, "
+        f"{nd} of {xo.size + vo.size} values differ from the oracle's")
     assert ex <= TOL_X and ev <= TOL_V, (what, ex, ev)
+    assert nd == 0, (what, "not bit for bit", nd)
     return ex, ev
 
 
@@ -56,7 +65,11 @@ def test_m1_parity_with_oracle(seed):
     """The small workload (16,384 particles, 200 steps, K = 200): GPU vs oracle."""
     s = synth.config_systems("M1", seed=seed)[0]
     say(f"M1 seed {seed}: N={s.n}, 200 steps")
-    xg, vg, hg = gpu_trajectory([s], 200)
+    with GpuRun([s]) as g:
+        hg = g.run(200)
+        xg, vg, _ = g.state()
+        n_list = vb.vb_get_pairs(g.ctx, 0, 0)
+    assert hg[0]["list_pairs"][-1] == n_list  # the record counts the list in use
     xo, vo, ho, _ = oracle_run(s, 200)
     assert_close(s, xg, vg, xo, vo, "M1")
     assert np.array_equal(hg[0]["contacts"], ho["contacts"])
