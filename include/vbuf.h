@@ -122,17 +122,27 @@ typedef struct vb_step_record {
 
 typedef struct vb_ctx vb_ctx;
 
-/* Create a context for one system of n particles (n >= 0).  stream is a
- * hipStream_t (NULL for the default stream); *out receives the context.
- * Errors: VB_EINVAL for a bad parameter, VB_ENOMEM, VB_EDEVICE. */
+/* Create a context for one system of n particles (n >= 0): the inputs of the
+ * method as the paper states them, the skin factor K and time step dt (Sec. 4.1,
+ * Eq. skin_formulus1), the uniform cell size L_C of the linked-cell grid
+ * (Sec. 3.2, Alg. 1; Sec. 5.1, Eq. skin_formulus_mincell) and the contact model
+ * (Sec. 5.1).  stream is a hipStream_t (NULL for the default stream); *out
+ * receives the context, which owns every device buffer the method needs.
+ * Errors: VB_EINVAL for a bad parameter (checked before any device call),
+ * VB_ENOMEM, VB_EDEVICE. */
 vb_status vb_create(const vb_params *h_params, int64_t n, void *stream, vb_ctx **out);
 
 /* Create a context for n_sys independent systems solved together, one launch per
- * phase for the whole batch.  h_params[s] and h_n[s] describe system s. */
+ * phase for the whole batch (each system follows the method of Sec. 4 on its
+ * own: its own K, cells, skins and broad-phase decisions).  h_params[s] and
+ * h_n[s] describe system s.  Errors as vb_create, and VB_EINVAL for n_sys
+ * outside 1..1024. */
 vb_status vb_batch_create(const vb_params *h_params, const int64_t *h_n, int32_t n_sys,
                           void *stream, vb_ctx **out);
 
-/* Load the state, in original order, all systems concatenated:
+/* Load the state of the particles (Sec. 3.2: centre X_i and bounding radius R_C,i
+ * of every particle; Sec. 4.1: its velocity v_p), in original order, all systems
+ * concatenated:
  *   d_x    [N][3] FP64 positions x^n
  *   d_v    [N][3] FP64 velocities: the full-step velocity v^0 when v_is_half_step
  *                 is 0 (a fresh start: the first step applies half a kick), or the
@@ -146,26 +156,63 @@ vb_status vb_batch_create(const vb_params *h_params, const int64_t *h_n, int32_t
 vb_status vb_set_state(vb_ctx *ctx, const double *d_x, const double *d_v, const float *d_rc,
                        const float *d_invm, int32_t v_is_half_step);
 
-/* Advance every system n_steps time steps.  h_hist, if not NULL, receives
- * [n_sys][n_steps] records.  A Verlet-list row, a cell bin or a friction
- * history that overflows is grown and the call's steps are run again from the
- * call's starting state (results unchanged).  The overflow counters are read
- * back after every block of 64 steps, one block behind the device, and a call
- * stops launching steps once they show an overflow; a late overflow still
- * repeats the steps before it, so long simulations are best run as calls of a
- * few hundred steps.  Synchronises the stream at the end, and waits on each
- * block's counters one block behind.
+/* Advance every system n_steps time steps of the time loop with the Verlet check
+ * (flow chart of Sec. 4; Sec. 4.2, Eq. update, Def. autoverlet): at each step a
+ * system whose list failed the validity test after the previous step (and every
+ * system at its first step) runs the broad phase on extended spheres, then every
+ * system runs the narrow phase on its list (Eq. delta), the contact forces and
+ * velocity-Verlet integration (Sec. 3.1, Sec. 5.1), and the validity test for the
+ * next step.  h_hist, if not NULL, receives [n_sys][n_steps] records.
+ * A Verlet-list row, a cell bin or a friction history that overflows is grown,
+ * and the steps since the call's last snapshot run again: a call keeps its
+ * starting state and, every 4 blocks of 64 steps, the state once every step
+ * before it is known free of overflow.  A run from a snapshot rebuilds the rows
+ * from the stored x0 and R_NL, so results, records and the schedule of broad
+ * phases are those of a run that never overflowed.  The overflow counters are
+ * read back after every block of 64 steps, one block behind the device.
+ * Synchronises the stream at the end.
  * Errors: VB_ECAPACITY if a row needs more than 128 entries, a bin more than 256
  * or a friction history more than 64 contacts; VB_ENONFINITE if the state
  * becomes NaN or infinite (the context then needs vb_set_state again);
  * VB_ENOMEM, VB_EDEVICE. */
 vb_status vb_run(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 
-/* Copy the state out, original order: d_x [N][3] positions x^n and d_v [N][3]
+/* Copy the state out (the positions and velocities the integration of Sec. 3.1
+ * advances), original order: d_x [N][3] positions x^n and d_v [N][3]
  * velocities (v^{n-1/2} after at least one step, else the loaded velocities).
  * Either pointer may be NULL.  *h_v_is_half_step (if not NULL) tells which.
  * Synchronises the stream.  Errors: VB_EINVAL without a loaded state. */
 vb_status vb_get_state(vb_ctx *ctx, double *d_x, double *d_v, int32_t *h_v_is_half_step);
+
+/* The Verlet state (what the automatic update of Sec. 4.2 carries from one step
+ * to the next besides positions and velocities: Eq. update, Def. autoverlet),
+ * for a checkpoint that resumes with the same schedule of broad phases:
+ *   d_x0r     [N][4] FP32, original order: the reference position x0 of the last
+ *             broad phase (x, y, z; Eq. update) and the extended radius R_NL of
+ *             that broad phase (Eq. bounding_sphere, capped as in Eq.
+ *             skin_formulus_mincell);
+ *   h_pending [n_sys]: 1 if the system's list failed the validity test after the
+ *             last step (or a broad phase was requested), so that the next step
+ *             runs a broad phase;
+ *   *h_step   the step counter (may be NULL).
+ * Synchronises the stream.  Errors: VB_EINVAL without a loaded state or before
+ * the first step (no list yet). */
+vb_status vb_get_verlet_state(vb_ctx *ctx, float *d_x0r, int32_t *h_pending, int64_t *h_step);
+
+/* Load a Verlet state in the layout of vb_get_verlet_state, right after
+ * vb_set_state and before any vb_run.  The next step rebuilds each system's list
+ * from the given x0 and R_NL (the set of pairs within reach of those spheres,
+ * Alg. 1) without re-deriving skins, or runs a broad phase where h_pending says
+ * so, and the step counter continues from step.  With vb_set_state(...,
+ * v_is_half_step = 1) (and vb_set_history under friction) from one checkpoint,
+ * the resumed run repeats the uninterrupted one: positions, velocities, the
+ * broad-phase schedule and every record field (the kinetic energy up to its
+ * summation order).  Synchronises the stream.
+ * Errors: VB_EINVAL if a step ran since vb_set_state, for step outside
+ * 0..2^31-2, a pending flag other than 0 or 1, or an R_NL below its R_C or beyond
+ * the cap; VB_ENONFINITE for NaN or Inf. */
+vb_status vb_set_verlet_state(vb_ctx *ctx, const float *d_x0r, const int32_t *h_pending,
+                              int64_t step);
 
 /* The friction history, for a checkpoint that resumes exactly: the contacts of
  * the last step with their tangential springs (the state a frictional step
@@ -184,7 +231,8 @@ vb_status vb_get_state(vb_ctx *ctx, double *d_x, double *d_v, int32_t *h_v_is_ha
 vb_status vb_get_history(vb_ctx *ctx, int32_t *d_partner, double *d_spring, int32_t cap,
                          int32_t *h_needed);
 
-/* Load a friction history in the layout of vb_get_history, right after
+/* Load a friction history (the per-contact springs of the static friction named
+ * in Sec. 5.1) in the layout of vb_get_history, right after
  * vb_set_state and before any vb_run: with the state and the history of a
  * checkpoint (vb_get_state, vb_get_history; v_is_half_step = 1), the run goes on
  * bit for bit as the uninterrupted one.  Without it a resumed run starts every
@@ -232,15 +280,18 @@ vb_status vb_set_timing(vb_ctx *ctx, int32_t on);
 vb_status vb_phase_times(vb_ctx *ctx, double *h_ms_rebuild, double *h_ms_step,
                          int64_t *h_steps, int64_t *h_rebuild_steps);
 
-/* Sizes: total particles N, systems, current row width, current step counter.
+/* Sizes: total particles N, systems, current row width (the longest Verlet-list
+ * row it holds, Def. verletlist), current step counter (Sec. 3.1 time loop).
  * Any output pointer may be NULL.  Errors: VB_EINVAL for a NULL ctx. */
 vb_status vb_get_info(vb_ctx *ctx, int64_t *h_n_total, int32_t *h_n_sys,
                       int32_t *h_row_width, int64_t *h_step);
 
-/* Message of the last failed call on ctx (ctx may be NULL for a failed create). */
+/* Message of the last failed call on ctx (ctx may be NULL for a failed create).
+ * The pointer stays valid until the next call on ctx. */
 const char *vb_last_error(const vb_ctx *ctx);
 
-/* Release every resource of ctx (NULL is ignored).  Synchronises the stream. */
+/* Release every resource of ctx: the state, the Verlet lists and cell bins of
+ * Alg. 1 and the friction history (NULL is ignored).  Synchronises the stream. */
 void vb_destroy(vb_ctx *ctx);
 
 #ifdef __cplusplus

@@ -68,6 +68,9 @@ _SIGNATURES = {
     "vb_get_state": (ctypes.c_int32, [_P, _P, _P, ctypes.POINTER(ctypes.c_int32)]),
     "vb_get_pairs": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "vb_get_verlet_state": (ctypes.c_int32, [_P, _P, ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+    "vb_set_verlet_state": (ctypes.c_int32, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]),
     "vb_get_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "vb_set_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32]),
     "vb_force_rebuild": (ctypes.c_int32, [_P]),
@@ -260,6 +263,30 @@ def vb_get_history(ctx, partner=None, spring=None):
         return int(need.value)
     _check(code, ctx)
     return int(need.value)
+
+
+def vb_get_verlet_state(ctx, x0r):
+    """Fills x0r (float32 [N,4] device tensor: x0 and R_NL of the last broad
+    phase, original order); returns (pending flags per system, step counter)."""
+    import torch
+    (p,) = _device_ptrs(("x0r", x0r, torch.float32, lambda: (_n_total(ctx), 4)))
+    n_sys = vb_get_info(ctx)["n_sys"]
+    pend = (ctypes.c_int32 * n_sys)()
+    step = ctypes.c_int64(0)
+    _check(lib().vb_get_verlet_state(ctx, p, pend, ctypes.byref(step)), ctx)
+    return [int(t) for t in pend], int(step.value)
+
+
+def vb_set_verlet_state(ctx, x0r, pending, step):
+    """Loads a Verlet state (the values of vb_get_verlet_state) right after
+    vb_set_state."""
+    import torch
+    (p,) = _device_ptrs(("x0r", x0r, torch.float32, lambda: (_n_total(ctx), 4)))
+    n_sys = vb_get_info(ctx)["n_sys"]
+    if len(pending) != n_sys:
+        raise ValueError(f"pending must have one flag per system ({n_sys})")
+    pend = (ctypes.c_int32 * n_sys)(*[int(t) for t in pending])
+    _check(lib().vb_set_verlet_state(ctx, p, pend, int(step)), ctx)
 
 
 def _history_ptrs(ctx, partner, spring):

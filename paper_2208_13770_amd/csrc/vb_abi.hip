@@ -55,6 +55,10 @@ hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const
                         int64_t *total, int64_t cap, int32_t *pairs, double *delta,
                         hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_get_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
+                         const float4 *bp, float4 *x0r, hipStream_t st);
+hipError_t launch_set_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
+                         const float4 *x0r, float4 *bp, int32_t *err, hipStream_t st);
 hipError_t launch_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
                        const PX *px, uint64_t *posq, int64_t n, hipStream_t st);
 }  // namespace vb
@@ -85,14 +89,26 @@ struct vb_ctx {
   HistEntry *hist_snap = nullptr;
   int32_t *hcnt_snap = nullptr;
   int32_t hist_snap_cap = 0;   // entries per slot hist_snap holds
+  // snapshot of a step that a call can be run again from after an overflow
+  // (state, x0 and R_NL, pending flags, friction history; the rows are rebuilt
+  // from x0 and R_NL on restore), with the host's bookkeeping at that step
   PX *snap_px = nullptr;
   PV *snap_pv = nullptr;
+  float4 *snap_bp = nullptr;
+  int32_t *snap_flags = nullptr;
+  struct {
+    int32_t at = 0;            // index of the step within the call
+    int64_t step = 0, next_sort = 0;
+    int first = 0, force = 0;
+    int32_t hcap = 0;          // history columns the snapshot holds
+  } snap;
   // overflow counters read back after each block of steps (pinned, two slots),
   // so that a call stops launching once a row, a bin or a history overflowed
   int32_t *ovf_host = nullptr;
   hipEvent_t ovf_ev[2] = {nullptr, nullptr};
   int32_t ovf_n = 0;    // read-backs requested in the current pass of vb_run
   float4 *bp = nullptr;
+  float4 *bp_alt = nullptr;    // the storage sort moves bp here, then the two swap
   int32_t *cnt = nullptr, *nbr = nullptr;
   int32_t width = 0;
   int32_t *bin_count = nullptr;
@@ -124,6 +140,8 @@ struct vb_ctx {
   int64_t step = 0;
   int first = 1;
   int force_pending = 1;
+  int relist_pending = 0;      // the next step rebuilds rows from x0 and R_NL (no broad phase)
+  int have_list = 0;           // bp and the rows hold a list (a step ran, or a Verlet state was loaded)
   int64_t next_sort = 0;       // step at which the storage is re-sorted next (-1: never)
   int32_t sort_interval = 0;
   int loaded = 0;
@@ -174,7 +192,7 @@ static void free_all(vb_ctx *c) {
   void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->posq[0],
                   c->posq[1], c->rrange, c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
                   c->hcnt_snap, c->snap_px,
-                  c->snap_pv, c->bp, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
+                  c->snap_pv, c->snap_bp, c->snap_flags, c->bp, c->bp_alt, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
                   c->brick_sys, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
                   c->go, c->overflow, c->err, c->stats, c->rebuilt_ring, c->hist_d,
@@ -456,6 +474,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   }
   ALLOC(c->rrange, 2 * n_sys);
   ALLOC(c->bp, c->slots);
+  ALLOC(c->bp_alt, c->slots);
   ALLOC(c->cnt, c->slots);
   ALLOC(c->bin_count, c->n_cells);
   ALLOC(c->brick_sys, c->n_bricks);
@@ -557,13 +576,15 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
   c->step = 0;
   c->first = v_is_half_step ? 0 : 1;
   c->force_pending = 1;
+  c->relist_pending = 0;
+  c->have_list = 0;
   c->next_sort = 0;
   c->loaded = 1;
   c->fresh = 1;
   return VB_OK;
 }
 
-static BroadArgs broad_args(vb_ctx *c, int force) {
+static BroadArgs broad_args(vb_ctx *c, int force, int relist) {
   BroadArgs a;
   a.sys = c->sys_d;
   a.tile_sys = c->tile_sys;
@@ -591,11 +612,14 @@ static BroadArgs broad_args(vb_ctx *c, int force) {
   a.step = c->graph_mode ? c->graph_off : (int32_t)c->step;
   a.step_base = c->graph_mode ? c->step_base_d : nullptr;
   a.force = force;
+  a.relist = relist;
   return a;
 }
 
 // Work that precedes the step kernel of the current step: the storage re-sort
-// when it is due (then a forced broad phase), and the conditional broad phase.
+// when it is due (x0 and R_NL move with their particles; the rows, which hold
+// slots, are then rebuilt from them without a broad phase, so the schedule of
+// broad phases does not change), and the conditional broad phase.
 // t0/t1 (may be null) take the start and end of the broad-phase kernels.
 static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   if (c->next_sort >= 0 && c->step >= c->next_sort && c->n_tiles > 0) {
@@ -608,6 +632,8 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.pv_src = c->pv[c->cur];
     s.px_dst = c->px[c->cur ^ 1];
     s.pv_dst = c->pv[c->cur ^ 1];
+    s.bp_src = c->bp;
+    s.bp_dst = c->bp_alt;
     s.cell_count = c->cell_count;
     s.cell_start = c->cell_start;
     s.block_sum = c->block_sum;
@@ -622,13 +648,15 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.stride = c->slots;
     HIP_OK(c, launch_sort(s, c->stream));
     c->cur ^= 1;
+    std::swap(c->bp, c->bp_alt);
     HIP_OK(c, fill_posq(c, c->cur));
-    c->force_pending = 1;  // slots moved: every row must be rebuilt
+    c->relist_pending = 1;  // slots moved: every row must be rebuilt
     c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
   }
-  HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending), c->broad_grid, c->pairs_grid,
-                               c->stream, t0, t1));
+  HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending, c->relist_pending), c->broad_grid,
+                               c->pairs_grid, c->stream, t0, t1));
   c->force_pending = 0;
+  c->relist_pending = 0;
   return VB_OK;
 }
 
@@ -681,6 +709,7 @@ static vb_status ensure_events(vb_ctx *c, size_t n) {
 // What a captured block of steps bakes in: buffers, sizes, launch shapes.
 static uint64_t graph_key(const vb_ctx *c, int cur) {
   const uint64_t parts[] = {(uint64_t)(uintptr_t)c->px[cur], (uint64_t)(uintptr_t)c->nbr,
+                            (uint64_t)(uintptr_t)c->bp,
                             (uint64_t)(uintptr_t)c->bins_bp, (uint64_t)(uintptr_t)c->bins_so,
                             (uint64_t)(uintptr_t)c->hist[cur], (uint64_t)(uintptr_t)c->hist[cur ^ 1],
                             (uint64_t)(uintptr_t)c->stream, (uint64_t)c->width, (uint64_t)c->pmax,
@@ -710,7 +739,7 @@ static vb_status capture_block(vb_ctx *c, int cur) {
   } else {
     for (int32_t i = 0; i < STATS_RING && st == VB_OK; ++i) {
       c->graph_off = i;
-      BroadArgs b = broad_args(c, 0);
+      BroadArgs b = broad_args(c, 0, 0);
       if (launch_broad_phase(b, c->broad_grid, c->pairs_grid, c->stream, nullptr, nullptr) !=
           hipSuccess)
         st = fail(c, VB_EDEVICE, "capture of the broad phase failed");
@@ -762,19 +791,117 @@ static vb_status overflow_seen(vb_ctx *c, bool *seen) {
   return VB_OK;
 }
 
-// Queues n_steps steps; *done receives the steps queued, fewer than n_steps
-// when an overflow stopped the call early.  With timing on, four events per
-// step take the kernels' own start and end times: binning start and
-// pair-search end, step-kernel start and end.
-static vb_status run_steps(vb_ctx *c, int32_t n_steps, int32_t *done) {
+// Blocks of STATS_RING steps between two snapshots of a call.  A call keeps a
+// snapshot of its first step and of every SNAP_BLOCKS-th block boundary after
+// it, each taken once every step before it is known free of overflow; a row, a
+// bin or a history that outgrows its capacity runs the call again from the last
+// snapshot, so at most SNAP_BLOCKS + 1 blocks run twice.
+constexpr int SNAP_BLOCKS = 4;
+
+// Keeps the state at the current step (call step index `at`): positions and
+// velocities, x0 and R_NL, the pending validity flags, the friction history and
+// the host's step bookkeeping.  The rows are not kept: a restore rebuilds them
+// from x0 and R_NL.
+static vb_status take_snapshot(vb_ctx *c, int32_t at) {
+  if (!c->snap_px) {
+    HIP_OK(c, dalloc(&c->snap_px, c->slots));
+    HIP_OK(c, dalloc(&c->snap_pv, c->slots));
+    HIP_OK(c, dalloc(&c->snap_bp, c->slots));
+    HIP_OK(c, dalloc(&c->snap_flags, 2 * (int64_t)c->n_sys));
+  }
+  HIP_OK(c, hipMemcpyAsync(c->snap_px, c->px[c->cur], sizeof(PX) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->snap_pv, c->pv[c->cur], sizeof(PV) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->snap_bp, c->bp, sizeof(float4) * c->slots, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->snap_flags, c->flags, sizeof(int32_t) * 2 * c->n_sys,
+                           hipMemcpyDeviceToDevice, c->stream));
+  if (c->any_friction) {
+    if (c->hist_snap_cap < c->hcap) {
+      if (c->hist_snap) (void)hipFree(c->hist_snap);
+      c->hist_snap = nullptr;
+      HIP_OK(c, dalloc(&c->hist_snap, c->slots * (int64_t)c->hcap));
+      c->hist_snap_cap = c->hcap;
+    }
+    if (!c->hcnt_snap) HIP_OK(c, dalloc(&c->hcnt_snap, c->slots));
+    HIP_OK(c, hipMemcpyAsync(c->hist_snap, c->hist[c->cur], sizeof(HistEntry) * c->slots * c->hcap,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->hcnt_snap, c->hcnt[c->cur], sizeof(int32_t) * c->slots,
+                             hipMemcpyDeviceToDevice, c->stream));
+    c->snap.hcap = c->hcap;
+  }
+  c->snap.at = at;
+  c->snap.step = c->step;
+  c->snap.next_sort = c->next_sort;
+  c->snap.first = c->first;
+  c->snap.force = c->force_pending;
+  return VB_OK;
+}
+
+// Back to the snapshot.  The rows are rebuilt at its step from its x0 and R_NL
+// (a broad phase where one was pending there), so the run from it repeats the
+// same schedule of broad phases, whatever capacities grew meanwhile.
+static vb_status restore_snapshot(vb_ctx *c) {
+  HIP_OK(c, hipMemcpyAsync(c->px[0], c->snap_px, sizeof(PX) * c->slots, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->bp, c->snap_bp, sizeof(float4) * c->slots, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
+  HIP_OK(c, fill_posq(c, 0));
+  if (c->any_friction) {  // entries c < snap.hcap sit at the same place in a wider table
+    HIP_OK(c, hipMemcpyAsync(c->hist[0], c->hist_snap, sizeof(HistEntry) * c->slots * c->snap.hcap,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->hcnt[0], c->hcnt_snap, sizeof(int32_t) * c->slots,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
+  vb_status st = reset_control(c);
+  if (st != VB_OK) return st;
+  HIP_OK(c, hipMemcpyAsync(c->flags, c->snap_flags, sizeof(int32_t) * 2 * c->n_sys,
+                           hipMemcpyDeviceToDevice, c->stream));
+  c->cur = 0;
+  c->step = c->snap.step;
+  c->next_sort = c->snap.next_sort;
+  c->first = c->snap.first;
+  c->force_pending = c->snap.force;
+  c->relist_pending = 1;
+  return VB_OK;
+}
+
+// Waits for every queued step and reads the overflow counters.
+static vb_status overflow_now(vb_ctx *c, bool *seen) {
+  int32_t ovf[3] = {0, 0, 0};
+  HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  *seen = ovf[0] > c->width || ovf[1] > c->bin_cap || ovf[2] > c->hcap;
+  c->ovf_n = 0;  // nothing left to look at one block behind
+  return VB_OK;
+}
+
+// Queues the steps i0 .. n_steps-1 of the call (records go to hist_d[i * n_sys
+// + s]); *done receives the call index reached, and *seen is set when the
+// overflow counters showed a row, a bin or a history beyond its capacity (the
+// steps since the last snapshot are then to be run again).  With timing on,
+// four events per step take the kernels' own start and end times: binning
+// start and pair-search end, step-kernel start and end.
+static vb_status run_steps(vb_ctx *c, int32_t i0, int32_t n_steps, int32_t *done, bool *seen) {
   vb_status st;
-  bool seen = false;
+  *seen = false;
   c->ovf_n = 0;
-  *done = 0;
+  *done = i0;
   int32_t pending = 0;
-  for (int32_t i = 0; i < n_steps;) {
+  int blocks = 0;  // blocks queued since the last snapshot
+  for (int32_t i = i0; i < n_steps;) {
+    if (blocks >= SNAP_BLOCKS && pending == 0) {
+      if ((st = overflow_now(c, seen)) != VB_OK) return st;
+      if (*seen) return VB_OK;
+      if ((st = take_snapshot(c, i)) != VB_OK) return st;
+      blocks = 0;
+    }
     const bool block = c->use_graphs && !c->timing && !c->first && !c->force_pending &&
-                       n_steps - i >= STATS_RING && c->n_tiles > 0 &&
+                       !c->relist_pending && n_steps - i >= STATS_RING && c->n_tiles > 0 &&
                        (c->next_sort < 0 || c->next_sort >= c->step + STATS_RING);
     if (block && pending > 0) {  // close the records of the steps before the block
       HIP_OK(c, launch_stats_reduce(c->sys_d, c->stats, c->rebuilt_ring, c->n_tiles, c->n_sys,
@@ -794,8 +921,9 @@ static vb_status run_steps(vb_ctx *c, int32_t n_steps, int32_t *done) {
                                     c->hist_d + (int64_t)i * c->n_sys, c->stream));
       i += STATS_RING;
       *done = i;
-      if ((st = overflow_seen(c, &seen)) != VB_OK) return st;
-      if (seen) return VB_OK;
+      ++blocks;
+      if ((st = overflow_seen(c, seen)) != VB_OK) return st;
+      if (*seen) return VB_OK;
       continue;
     }
     hipEvent_t *e = c->timing ? &c->ev[4 * (size_t)i] : nullptr;
@@ -812,9 +940,10 @@ static vb_status run_steps(vb_ctx *c, int32_t n_steps, int32_t *done) {
                                     c->stream));
       pending = 0;
       *done = i + 1;
+      ++blocks;
       if (i + 1 < n_steps) {
-        if ((st = overflow_seen(c, &seen)) != VB_OK) return st;
-        if (seen) return VB_OK;
+        if ((st = overflow_seen(c, seen)) != VB_OK) return st;
+        if (*seen) return VB_OK;
       }
     }
     ++i;
@@ -850,35 +979,13 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
   vb_status st;
   if ((st = alloc_hist(c, n_steps)) != VB_OK) return st;
   if (c->timing && (st = ensure_events(c, 4 * (size_t)n_steps)) != VB_OK) return st;
-  if (!c->snap_px) {
-    HIP_OK(c, dalloc(&c->snap_px, c->slots));
-    HIP_OK(c, dalloc(&c->snap_pv, c->slots));
-  }
-  // starting state, to run the call again if a row or a bin overflows
-  HIP_OK(c, hipMemcpyAsync(c->snap_px, c->px[c->cur], sizeof(PX) * c->slots,
-                           hipMemcpyDeviceToDevice, c->stream));
-  HIP_OK(c, hipMemcpyAsync(c->snap_pv, c->pv[c->cur], sizeof(PV) * c->slots,
-                           hipMemcpyDeviceToDevice, c->stream));
-  int32_t snap_hcap = 0;
-  if (c->any_friction) {
-    if (c->hist_snap_cap < c->hcap) {
-      if (c->hist_snap) (void)hipFree(c->hist_snap);
-      c->hist_snap = nullptr;
-      HIP_OK(c, dalloc(&c->hist_snap, c->slots * (int64_t)c->hcap));
-      c->hist_snap_cap = c->hcap;
-    }
-    if (!c->hcnt_snap) HIP_OK(c, dalloc(&c->hcnt_snap, c->slots));
-    snap_hcap = c->hcap;
-    HIP_OK(c, hipMemcpyAsync(c->hist_snap, c->hist[c->cur], sizeof(HistEntry) * c->slots * c->hcap,
-                             hipMemcpyDeviceToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(c->hcnt_snap, c->hcnt[c->cur], sizeof(int32_t) * c->slots,
-                             hipMemcpyDeviceToDevice, c->stream));
-  }
-  const int64_t step0 = c->step, sort0 = c->next_sort;
-  const int first0 = c->first;
-  for (int attempt = 0;; ++attempt) {
+  const int64_t step0 = c->step;
+  if ((st = take_snapshot(c, 0)) != VB_OK) return st;
+  int32_t i0 = 0, retries = 0, last_restore = -1;
+  for (;;) {
     int32_t done = 0;
-    if ((st = run_steps(c, n_steps, &done)) != VB_OK) return st;
+    bool seen = false;
+    if ((st = run_steps(c, i0, n_steps, &done, &seen)) != VB_OK) return st;
     int32_t ovf[3] = {0, 0, 0};
     HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -890,7 +997,9 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
       std::vector<vb_step_record> rec((size_t)done * c->n_sys);
       if ((st = read_records(c, rec, done, step0)) != VB_OK) return st;
     }
-    if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || ovf[2] > MAX_HIST || attempt >= 4) {
+    retries = c->snap.at == last_restore ? retries + 1 : 0;
+    last_restore = c->snap.at;
+    if (ovf[0] > c->row_limit || ovf[1] > MAX_BIN || ovf[2] > MAX_HIST || retries >= 4) {
       c->loaded = 0;
       return fail(c, VB_ECAPACITY,
                   "a Verlet-list row needs " + std::to_string(ovf[0]) + " entries (limit " +
@@ -898,8 +1007,8 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
                       " particles (limit 256) or a friction history " + std::to_string(ovf[2]) +
                       " contacts (limit " + std::to_string(MAX_HIST) + ")");
     }
-    // grow and start again from the call's first step; the forced broad phase
-    // changes the schedule, not the results (theorem of Sec. 4.2)
+    // grow, then run again from the last snapshot, which by construction lies
+    // before the block that overflowed
     if (ovf[0] > c->width &&
         (st = alloc_rows(c, std::min<int32_t>(c->row_limit, (ovf[0] + ovf[0] / 4 + 7) / 8 * 8))) != VB_OK)
       return st;
@@ -909,25 +1018,10 @@ extern "C" vb_status vb_run(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) 
     if (ovf[2] > c->hcap &&
         (st = alloc_hist_tables(c, std::min<int32_t>(MAX_HIST, (ovf[2] + ovf[2] / 4 + 3) / 4 * 4))) != VB_OK)
       return st;
-    HIP_OK(c, hipMemcpyAsync(c->px[0], c->snap_px, sizeof(PX) * c->slots,
-                             hipMemcpyDeviceToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots,
-                             hipMemcpyDeviceToDevice, c->stream));
-    HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
-    HIP_OK(c, fill_posq(c, 0));
-    if (c->any_friction) {  // entries c < snap_hcap sit at the same place in a wider table
-      HIP_OK(c, hipMemcpyAsync(c->hist[0], c->hist_snap, sizeof(HistEntry) * c->slots * snap_hcap,
-                               hipMemcpyDeviceToDevice, c->stream));
-      HIP_OK(c, hipMemcpyAsync(c->hcnt[0], c->hcnt_snap, sizeof(int32_t) * c->slots,
-                               hipMemcpyDeviceToDevice, c->stream));
-    }
-    if ((st = reset_control(c)) != VB_OK) return st;
-    c->cur = 0;
-    c->step = step0;
-    c->first = first0;
-    c->next_sort = sort0;
-    c->force_pending = 1;
+    if ((st = restore_snapshot(c)) != VB_OK) return st;
+    i0 = c->snap.at;
   }
+  c->have_list = 1;
   std::vector<vb_step_record> rec((size_t)n_steps * c->n_sys);
   if ((st = read_records(c, rec, n_steps, step0)) != VB_OK) return st;
   if (h_hist)
@@ -958,6 +1052,56 @@ extern "C" vb_status vb_get_state(vb_ctx *c, double *d_x, double *d_v,
                              d_x, d_v, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (h_v_is_half_step) *h_v_is_half_step = c->first ? 0 : 1;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_verlet_state(vb_ctx *c, float *d_x0r, int32_t *h_pending,
+                                         int64_t *h_step) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded");
+  if (!c->have_list) return fail(c, VB_EINVAL, "no list yet: run a step first");
+  if (c->n_total > 0 && !d_x0r) return fail(c, VB_EINVAL, "d_x0r is NULL");
+  if (c->n_total > 0)
+    HIP_OK(c, launch_get_bp(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], c->bp,
+                            reinterpret_cast<float4 *>(d_x0r), c->stream));
+  std::vector<int32_t> fl((size_t)c->n_sys, 0);
+  HIP_OK(c, hipMemcpyAsync(fl.data(), c->flags + (c->step & 1) * c->n_sys, sizeof(int32_t) * c->n_sys,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (h_pending)
+    for (int s = 0; s < c->n_sys; ++s) h_pending[s] = (fl[s] != 0 || c->force_pending) ? 1 : 0;
+  if (h_step) *h_step = c->step;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_set_verlet_state(vb_ctx *c, const float *d_x0r, const int32_t *h_pending,
+                                         int64_t step) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded || !c->fresh)
+    return fail(c, VB_EINVAL, "a Verlet state is loaded right after vb_set_state, before any step");
+  if (!h_pending || (c->n_total > 0 && !d_x0r)) return fail(c, VB_EINVAL, "input pointer is NULL");
+  if (step < 0 || step >= (int64_t)INT32_MAX) return fail(c, VB_EINVAL, "step out of range");
+  std::vector<int32_t> fl((size_t)2 * c->n_sys, 0);
+  for (int s = 0; s < c->n_sys; ++s) {
+    if (h_pending[s] != 0 && h_pending[s] != 1) return fail(c, VB_EINVAL, "pending flags are 0 or 1");
+    fl[(size_t)(step & 1) * c->n_sys + s] = h_pending[s];
+  }
+  HIP_OK(c, launch_fill_i32(c->err, 1, 0, c->stream));
+  if (c->n_total > 0)
+    HIP_OK(c, launch_set_bp(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur],
+                            reinterpret_cast<const float4 *>(d_x0r), c->bp, c->err, c->stream));
+  int32_t err = 0;
+  HIP_OK(c, hipMemcpyAsync(&err, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (err & 1) return fail(c, VB_ENONFINITE, "x0 or R_NL holds NaN or Inf");
+  if (err & 2) return fail(c, VB_EINVAL, "an R_NL is below its R_C or beyond the cap");
+  HIP_OK(c, hipMemcpyAsync(c->flags, fl.data(), sizeof(int32_t) * fl.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->step = step;
+  c->force_pending = 0;
+  c->relist_pending = 1;
+  c->have_list = 1;
   return VB_OK;
 }
 

@@ -128,6 +128,8 @@ struct BroadArgs {
   int32_t step;         // the step, or its offset from *step_base when step_base is set
   const int32_t *step_base;  // device step counter of a replayed graph (else null)
   int32_t force;        // 1: broad phase for every system regardless of flags
+  int32_t relist;       // 1: every system without a broad phase at this step rebuilds its
+                        //    rows from the stored x0 and R_NL (bp), keeping both
 };
 
 // Arguments of the fused step kernel.
@@ -176,6 +178,8 @@ struct SortArgs {
   const PV *pv_src;
   PX *px_dst;
   PV *pv_dst;
+  const float4 *bp_src; // x0 and R_NL of the last broad phase move with their particle
+  float4 *bp_dst;
   int32_t *cell_count;  // [cells] zero on entry, zero on exit
   int32_t *cell_start;  // [cells + 1]
   int32_t *block_sum;   // [scan blocks]

@@ -530,11 +530,14 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
 // ------------------------------------------------------------------ broad phase
 
 // Extended spheres, reference positions and cell bins of every system that needs
-// a broad phase at this step.  Grid-stride over tiles.
+// a broad phase at this step; with relist set, the other systems bin their
+// stored x0 and R_NL unchanged (their rows are then rebuilt by the pair search
+// without a broad phase: after a storage sort, a resumed checkpoint or a retried
+// block).  Grid-stride over tiles.
 __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
   const int tid = threadIdx.x;
   const int step = a.step + (a.step_base ? *a.step_base : 0);
-  int any = a.force;
+  int any = a.force | a.relist;
   for (int s = tid; s < a.n_sys; s += TILE)
     any |= needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, step, a.force);
   if (!__syncthreads_or(any)) {  // the same decision in every workgroup
@@ -548,13 +551,14 @@ __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
   if (blockIdx.x == 0)
     for (int s = tid; s < a.n_sys; s += TILE) {
       const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, step, a.force);
-      a.go[s] = nd;
+      a.go[s] = nd | a.relist;
       a.rebuilt_ring[(step % STATS_RING) * a.n_sys + s] = nd;
     }
   for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
     const int s = a.tile_sys[t];
     const SysDev &S = a.sys[s];
-    if (!needs_broad_phase(S, a.flags, a.n_sys, s, step, a.force)) continue;
+    const int nd = needs_broad_phase(S, a.flags, a.n_sys, s, step, a.force);
+    if (!nd && !a.relist) continue;
     const int local = (int)(t - S.tile_off) * TILE + tid;
     int64_t key = -1;
     float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -562,18 +566,26 @@ __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
     if (local < S.n) {
       const int64_t k = S.p_off + local;
       const PX x = a.px[k];
-      const PV v = a.pv[k];
-      double skin;
-      if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
-      else if (S.skin_mode == 2) skin = 0.0;
-      else skin = S.skin_uniform;
-      const double r = (double)x.rc + skin;
-      const double rnl = r < S.cap ? r : S.cap;
-      b = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
-      a.bp[k] = b;
+      if (nd) {
+        const PV v = a.pv[k];
+        double skin;
+        if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
+        else if (S.skin_mode == 2) skin = 0.0;
+        else skin = S.skin_uniform;
+        const double r = (double)x.rc + skin;
+        const double rnl = r < S.cap ? r : S.cap;
+        b = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
+        a.bp[k] = b;
+        key = S.c_off + cell_of(S, x.x, x.y, x.z);
+      } else {
+        // the list of the last broad phase is the set of pairs within reach of
+        // the stored spheres; any binning that keeps pairs within reach in
+        // neighbouring cells finds it, so binning x0 reproduces it exactly
+        b = a.bp[k];
+        key = S.c_off + cell_of(S, (double)b.x, (double)b.y, (double)b.z);
+      }
       a.inv[S.p_off + x.orig] = local;
       orig = x.orig;
-      key = S.c_off + cell_of(S, x.x, x.y, x.z);
     }
     const int slot = wave_bin_slot(a.bin_count, key);
     if (key >= 0) {
@@ -976,6 +988,7 @@ __global__ __launch_bounds__(TILE) void k_sort_place(SortArgs a) {
   for (int64_t m = cs; m < ce; ++m) rank += a.px_src[S.p_off + a.perm0[m]].orig < me.orig;
   a.px_dst[cs + rank] = me;
   a.pv_dst[cs + rank] = a.pv_src[S.p_off + q];
+  a.bp_dst[cs + rank] = a.bp_src[S.p_off + q];
   if (a.hist_src) {  // the friction history moves with its particle
     const int hn = a.hcnt_src[S.p_off + q];
     a.hcnt_dst[cs + rank] = hn;
@@ -1185,6 +1198,36 @@ __global__ void k_set_history(const SysDev *sys, const int32_t *tile_sys, const 
     ++n;
   }
   hcnt[k] = n;
+}
+
+// The Verlet state in the caller's original order: x0 (FP32) and R_NL of the
+// last broad phase, one float4 per particle.
+__global__ void k_get_bp(const SysDev *sys, const int32_t *tile_sys, const PX *px, const float4 *bp,
+                         float4 *x0r) {
+  const int64_t t = blockIdx.x;
+  const SysDev &S = sys[tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  x0r[S.o_off + px[k].orig] = bp[k];
+}
+
+// Loads a Verlet state given in original order into the slots; flags bad values
+// in *err: bit 0 not finite, bit 1 R_NL below R_C or beyond the cap.
+__global__ void k_set_bp(const SysDev *sys, const int32_t *tile_sys, const PX *px, const float4 *x0r,
+                         float4 *bp, int32_t *err) {
+  const int64_t t = blockIdx.x;
+  const SysDev &S = sys[tile_sys[t]];
+  const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
+  if (local >= S.n) return;
+  const int64_t k = S.p_off + local;
+  const PX p = px[k];
+  const float4 b = x0r[S.o_off + p.orig];
+  int e = 0;
+  if (!isfinite(b.x) || !isfinite(b.y) || !isfinite(b.z) || !isfinite(b.w)) e |= 1;
+  else if (!(b.w >= p.rc) || !(b.w <= (float)S.cap)) e |= 2;
+  if (e) atomicOr(err, e);
+  bp[k] = b;
 }
 
 // Copy the state back to the caller's original order.
@@ -1404,6 +1447,21 @@ hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t 
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_get_state, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
                      pv, x, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
+                         const float4 *bp, float4 *x0r, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_get_bp, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px, bp, x0r);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
+                         const float4 *x0r, float4 *bp, int32_t *err, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_bp, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px, x0r, bp,
+                     err);
   return hipGetLastError();
 }
 

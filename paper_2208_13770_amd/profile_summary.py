@@ -28,13 +28,20 @@ import os
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SRC = os.path.join(HERE, "csrc", "vb_kernels.hip")
+# every source that shapes what the kernels do or how they are launched: the
+# kernels, their record layouts and constants, the host code that sizes the grids
+# and sequences the launches, and the build flags
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("vb_kernels.hip", "vb_device.h",
+                                                          "vb_abi.hip")] + [os.path.join(HERE, "build.py")]
 COPY_BYTES = 4 << 30  # bench.py's copy probe moves 4 GiB per launch each way
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def stats(args):
