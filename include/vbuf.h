@@ -254,6 +254,20 @@ vb_status vb_set_history(vb_ctx *ctx, const int32_t *d_partner, const double *d_
 vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs,
                        double *d_delta, int64_t cap, int64_t *h_n);
 
+/* vb_get_pairs for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid it):
+ * the same result, with the export's per-particle scratch taken from a fixed
+ * array in the library (12 bytes per particle of the largest system it takes,
+ * VB_NOALLOC_MAX_N, held on each device the library runs on until the process
+ * ends) instead of the context's buffers.  This call allocates nothing.  Calls
+ * on one device share that array: two calls that overlap on one device (from
+ * several host threads or streams) race.  Synchronises the stream.
+ * Errors: as vb_get_pairs, and VB_EINVAL for a system of more than
+ * VB_NOALLOC_MAX_N particles. */
+#define VB_NOALLOC_MAX_N 4194304
+vb_status vb_get_pairs_noalloc(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs,
+                               double *d_delta, int64_t cap, int64_t *h_n);
+
 /* Request a broad phase at the next step (all systems), as if a validity test
  * had failed (Def. autoverlet); by the theorem of Sec. 4.2 this changes no
  * result.  Errors: VB_EINVAL for a NULL ctx. */

@@ -71,6 +71,8 @@ _SIGNATURES = {
     "vb_get_verlet_state": (ctypes.c_int32, [_P, _P, ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_int64)]),
     "vb_set_verlet_state": (ctypes.c_int32, [_P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]),
+    "vb_get_pairs_noalloc": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                              ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "vb_get_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "vb_set_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32]),
     "vb_force_rebuild": (ctypes.c_int32, [_P]),
@@ -230,9 +232,14 @@ def vb_get_state(ctx, x=None, v=None):
     return bool(half.value)
 
 
-def vb_get_pairs(ctx, sys, which, pairs=None, delta=None):
+VB_NOALLOC_MAX_N = 4194304
+
+
+def vb_get_pairs(ctx, sys, which, pairs=None, delta=None, noalloc=False):
     """Fills pairs (int32 [cap,2]) and delta (float64 [cap]) device tensors; returns
-    the total count.  Call with pairs=None to get the count only."""
+    the total count.  Call with pairs=None to get the count only.  noalloc=True
+    calls vb_get_pairs_noalloc, which takes its scratch from the library's fixed
+    array instead of the context's buffers."""
     import torch
     n = ctypes.c_int64(0)
     cap = 0
@@ -248,7 +255,8 @@ def vb_get_pairs(ctx, sys, which, pairs=None, delta=None):
         pp, pd = ptrs[0], (ptrs[1] if delta is not None else None)
     elif delta is not None:
         raise ValueError("delta needs pairs")
-    _check(lib().vb_get_pairs(ctx, int(sys), int(which), pp, pd, cap, ctypes.byref(n)), ctx)
+    fn = lib().vb_get_pairs_noalloc if noalloc else lib().vb_get_pairs
+    _check(fn(ctx, int(sys), int(which), pp, pd, cap, ctypes.byref(n)), ctx)
     return int(n.value)
 
 

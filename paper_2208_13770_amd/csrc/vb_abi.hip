@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,31 @@ hipError_t launch_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t
 using namespace vb;
 
 static_assert(sizeof(vb_step_record) == sizeof(RecordDev), "record layouts match");
+
+// Scratch of the allocation-free pair export (vb_get_pairs_noalloc): the
+// per-particle counts (int32), their exclusive prefix (int64) and the total
+// (int64) for one system of at most VB_NOALLOC_MAX_N particles.  Every device
+// the library runs on holds its own copy, from the first use of the library on
+// that device until the process ends.  In host code `scratch` names no device
+// address: the address of each device's copy is taken once, at the first
+// context created on that device, and kept in g_scratch.
+constexpr int64_t SCRATCH_BYTES = 12 * (int64_t)VB_NOALLOC_MAX_N + 256;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static void *g_scratch[MAX_DEVICES] = {};
+static std::mutex g_scratch_mutex;
+
+// Address of this device's scratch (the device is current); null on failure.
+static void *device_scratch(int device) {
+  if (device < 0 || device >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch[device] = ptr;
+  }
+  return g_scratch[device];
+}
 
 struct vb_ctx {
   hipStream_t stream = nullptr;
@@ -358,6 +384,10 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   };
   if (hipGetDevice(&c->device) != hipSuccess) {
     c->msg = "hipGetDevice failed";
+    return bail(VB_EDEVICE);
+  }
+  if (!device_scratch(c->device)) {
+    c->msg = "hipGetSymbolAddress of the export scratch failed";
     return bail(VB_EDEVICE);
   }
   hipDeviceProp_t prop;
@@ -1185,6 +1215,45 @@ extern "C" vb_status vb_get_pairs(vb_ctx *c, int32_t sys, int32_t which, int32_t
   int64_t total = 0;
   HIP_OK(c, hipMemcpyAsync(&total, c->pair_total, sizeof(int64_t), hipMemcpyDeviceToHost,
                            c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (c->sys_h[sys].n == 0) total = 0;
+  if (h_n) *h_n = total;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_pairs_noalloc(vb_ctx *c, int32_t sys, int32_t which, int32_t *d_pairs,
+                                          double *d_delta, int64_t cap, int64_t *h_n) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded");
+  if (sys < 0 || sys >= c->n_sys) return fail(c, VB_EINVAL, "sys out of range");
+  if (which != 0 && which != 1) return fail(c, VB_EINVAL, "which must be 0 or 1");
+  if (cap < 0 || (cap > 0 && !d_pairs)) return fail(c, VB_EINVAL, "bad output buffer");
+  if (c->sys_h[sys].n > VB_NOALLOC_MAX_N)
+    return fail(c, VB_EINVAL, "system " + std::to_string(sys) + " has " +
+                                  std::to_string(c->sys_h[sys].n) + " particles; the allocation-free "
+                                  "export takes at most " + std::to_string(VB_NOALLOC_MAX_N));
+  unsigned char *base = static_cast<unsigned char *>(g_scratch[c->device]);
+  if (!base) return fail(c, VB_EDEVICE, "no export scratch on this device");
+  // counts [n] int32, offsets [n] int64 and the total, 8-byte aligned
+  int32_t *counts = reinterpret_cast<int32_t *>(base);
+  int64_t *offsets = reinterpret_cast<int64_t *>(base + 4 * (int64_t)VB_NOALLOC_MAX_N);
+  int64_t *total_d = reinterpret_cast<int64_t *>(base + 12 * (int64_t)VB_NOALLOC_MAX_N);
+  vb_status st;
+  if (which == 1) {  // as vb_get_pairs: the broad phase the next step would run, if any
+    if ((st = queue_broad_phase(c)) != VB_OK) return st;
+    HIP_OK(c, launch_fill_i32(c->bin_count, c->n_cells, 0, c->stream));
+    int32_t ovf[2] = {0, 0};
+    HIP_OK(c, hipMemcpyAsync(ovf, c->overflow, sizeof(ovf), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (ovf[0] > c->width || ovf[1] > c->bin_cap)
+      return fail(c, VB_ECAPACITY, "list row or cell bin overflow in the broad phase; run a "
+                                   "step first so that vb_run grows them");
+  }
+  HIP_OK(c, launch_pairs(c->sys_h[sys], c->px[c->cur], c->cnt, c->nbr, c->slots, which, counts,
+                         offsets, total_d, cap, cap > 0 ? d_pairs : nullptr,
+                         cap > 0 ? d_delta : nullptr, c->stream));
+  int64_t total = 0;
+  HIP_OK(c, hipMemcpyAsync(&total, total_d, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (c->sys_h[sys].n == 0) total = 0;
   if (h_n) *h_n = total;
