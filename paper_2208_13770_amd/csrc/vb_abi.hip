@@ -32,13 +32,13 @@ hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, 
 size_t pairs_lds_bytes(int width, int pmax);
 int pairs_blocks_per_cu(int width, int pmax);
 hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
-                              const PX *px, const HistEntry *hist, const int32_t *hcnt,
+                              const uint32_t *origs, const HistEntry *hist, const int32_t *hcnt,
                               int64_t stride, int32_t hcap, int32_t *partner, double *spring,
                               int32_t cap, int32_t *needed, hipStream_t st);
 hipError_t launch_check_history(const SysDev &S, const int32_t *partner, const double *spring,
                                 int32_t cap, int32_t *needed, int32_t *err, hipStream_t st);
 hipError_t launch_set_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
-                              const PX *px, const int32_t *partner, const double *spring,
+                              const uint32_t *origs, const int32_t *partner, const double *spring,
                               int32_t cap, HistEntry *hist, int32_t *hcnt, int64_t stride,
                               hipStream_t st);
 hipError_t launch_sort(const SortArgs &a, hipStream_t st);
@@ -46,22 +46,24 @@ int64_t scan_blocks(int64_t n_cells);
 hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const int32_t *ring,
                                int64_t n_tiles, int32_t n_sys, int32_t step0, int32_t nsteps,
                                RecordDev *out, hipStream_t st);
-hipError_t launch_set_state(const SysDev &S, PX *px, PV *pv, const double *x, const double *v,
-                            const float *rc, const float *invm, int32_t *err, int32_t *r_lo,
-                            int32_t *r_hi, hipStream_t st);
+hipError_t launch_set_state(const SysDev &S, X3 *xs, V3 *vs, float2 *ri, uint32_t *origs,
+                            const double *x, const double *v, const float *rc, const float *invm,
+                            int32_t *err, int32_t *r_lo, int32_t *r_hi, hipStream_t st);
 hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
-                            const PX *px, const PV *pv, double *x, double *v, hipStream_t st);
-hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const int32_t *nbr,
-                        int64_t stride, int32_t contacts_only, int32_t *counts, int64_t *offsets,
-                        int64_t *total, int64_t cap, int32_t *pairs, double *delta,
-                        hipStream_t st);
+                            const X3 *xs, const V3 *vs, const uint32_t *origs, double *x, double *v,
+                            hipStream_t st);
+hipError_t launch_pairs(const SysDev &S, const X3 *xs, const float2 *ri, const uint32_t *origs,
+                        const int32_t *cnt, const int32_t *nbr, int64_t stride,
+                        int32_t contacts_only, int32_t *counts, int64_t *offsets, int64_t *total,
+                        int64_t cap, int32_t *pairs, double *delta, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
-hipError_t launch_get_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
-                         const float4 *bp, float4 *x0r, hipStream_t st);
-hipError_t launch_set_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
-                         const float4 *x0r, float4 *bp, int32_t *err, hipStream_t st);
+hipError_t launch_get_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                         const uint32_t *origs, const float4 *bp, float4 *x0r, hipStream_t st);
+hipError_t launch_set_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                         const uint32_t *origs, const float2 *ri, const float4 *x0r, float4 *bp,
+                         int32_t *err, hipStream_t st);
 hipError_t launch_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
-                       const PX *px, uint64_t *posq, int64_t n, hipStream_t st);
+                       const X3 *xs, const float2 *ri, uint64_t *posq, int64_t n, hipStream_t st);
 }  // namespace vb
 
 using namespace vb;
@@ -103,9 +105,14 @@ struct vb_ctx {
   std::vector<SysDev> sys_h;
   SysDev *sys_d = nullptr;
   int32_t *tile_sys = nullptr;
-  PX *px[2] = {nullptr, nullptr};
-  PV *pv[2] = {nullptr, nullptr};
-  uint64_t *posq[2] = {nullptr, nullptr};  // coded positions of px[0], px[1]
+  // state, double-buffered every step (index cur)
+  X3 *xs[2] = {nullptr, nullptr};
+  V3 *vs[2] = {nullptr, nullptr};
+  uint64_t *posq[2] = {nullptr, nullptr};  // coded positions of xs[0], xs[1]
+  // (R_C, 1/m) and original index, double-buffered only by the storage sort (index scur)
+  float2 *ri[2] = {nullptr, nullptr};
+  uint32_t *orig[2] = {nullptr, nullptr};
+  int scur = 0;
   int32_t *rrange = nullptr;               // [2][n_sys] smallest and largest R_C (FP32 bits)
   // friction history (allocated only when some system has friction)
   int any_friction = 0;
@@ -118,8 +125,10 @@ struct vb_ctx {
   // snapshot of a step that a call can be run again from after an overflow
   // (state, x0 and R_NL, pending flags, friction history; the rows are rebuilt
   // from x0 and R_NL on restore), with the host's bookkeeping at that step
-  PX *snap_px = nullptr;
-  PV *snap_pv = nullptr;
+  X3 *snap_x = nullptr;
+  V3 *snap_v = nullptr;
+  float2 *snap_ri = nullptr;
+  uint32_t *snap_orig = nullptr;
   float4 *snap_bp = nullptr;
   int32_t *snap_flags = nullptr;
   struct {
@@ -215,10 +224,10 @@ static hipError_t dalloc(T **p, int64_t count) {
 }
 
 static void free_all(vb_ctx *c) {
-  void *ptrs[] = {c->sys_d, c->tile_sys, c->px[0], c->px[1], c->pv[0], c->pv[1], c->posq[0],
+  void *ptrs[] = {c->sys_d, c->tile_sys, c->xs[0], c->xs[1], c->vs[0], c->vs[1], c->ri[0], c->ri[1],
+                  c->orig[0], c->orig[1], c->posq[0],
                   c->posq[1], c->rrange, c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
-                  c->hcnt_snap, c->snap_px,
-                  c->snap_pv, c->snap_bp, c->snap_flags, c->bp, c->bp_alt, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
+                  c->hcnt_snap, c->snap_x, c->snap_v, c->snap_ri, c->snap_orig, c->snap_bp, c->snap_flags, c->bp, c->bp_alt, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
                   c->brick_sys, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
                   c->go, c->overflow, c->err, c->stats, c->rebuilt_ring, c->hist_d,
@@ -498,8 +507,10 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->sys_d, n_sys);
   ALLOC(c->tile_sys, c->n_tiles);
   for (int b = 0; b < 2; ++b) {
-    ALLOC(c->px[b], c->slots);
-    ALLOC(c->pv[b], c->slots);
+    ALLOC(c->xs[b], c->slots);
+    ALLOC(c->vs[b], c->slots);
+    ALLOC(c->ri[b], c->slots);
+    ALLOC(c->orig[b], c->slots);
     ALLOC(c->posq[b], c->slots);
   }
   ALLOC(c->rrange, 2 * n_sys);
@@ -562,9 +573,9 @@ extern "C" vb_status vb_create(const vb_params *h_params, int64_t n, void *strea
   return vb_batch_create(h_params, &n, 1, stream, out);
 }
 
-// Coded positions of px[b] for the step kernel's pre-test.
+// Coded positions of xs[b] for the step kernel's pre-test.
 static hipError_t fill_posq(vb_ctx *c, int b) {
-  return launch_posq(c->sys_d, c->tile_sys, c->rrange, c->n_sys, c->px[b], c->posq[b], c->slots,
+  return launch_posq(c->sys_d, c->tile_sys, c->rrange, c->n_sys, c->xs[b], c->ri[c->scur], c->posq[b], c->slots,
                      c->stream);
 }
 
@@ -588,8 +599,10 @@ extern "C" vb_status vb_set_state(vb_ctx *c, const double *d_x, const double *d_
   HIP_OK(c, launch_fill_i32(c->rrange, c->n_sys, 0x7F800000, c->stream));  // +inf
   HIP_OK(c, launch_fill_i32(c->rrange + c->n_sys, c->n_sys, 0, c->stream));
   for (int s = 0; s < c->n_sys; ++s)
-    HIP_OK(c, launch_set_state(c->sys_h[s], c->px[0], c->pv[0], d_x, d_v, d_rc, d_invm, c->err,
+    HIP_OK(c, launch_set_state(c->sys_h[s], c->xs[0], c->vs[0], c->ri[0], c->orig[0], d_x, d_v,
+                               d_rc, d_invm, c->err,
                                c->rrange + s, c->rrange + c->n_sys + s, c->stream));
+  c->scur = 0;
   HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
   HIP_OK(c, fill_posq(c, 0));
   if (c->any_friction) HIP_OK(c, launch_fill_i32(c->hcnt[0], c->slots, 0, c->stream));
@@ -620,8 +633,10 @@ static BroadArgs broad_args(vb_ctx *c, int force, int relist) {
   a.tile_sys = c->tile_sys;
   a.n_sys = c->n_sys;
   a.n_tiles = c->n_tiles;
-  a.px = c->px[c->cur];
-  a.pv = c->pv[c->cur];
+  a.x = c->xs[c->cur];
+  a.v = c->vs[c->cur];
+  a.ri = c->ri[c->scur];
+  a.orig = c->orig[c->scur];
   a.bp = c->bp;
   a.cnt = c->cnt;
   a.nbr = c->nbr;
@@ -658,10 +673,14 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.tile_sys = c->tile_sys;
     s.n_tiles = c->n_tiles;
     s.n_cells = c->n_cells;
-    s.px_src = c->px[c->cur];
-    s.pv_src = c->pv[c->cur];
-    s.px_dst = c->px[c->cur ^ 1];
-    s.pv_dst = c->pv[c->cur ^ 1];
+    s.x_src = c->xs[c->cur];
+    s.v_src = c->vs[c->cur];
+    s.ri_src = c->ri[c->scur];
+    s.orig_src = c->orig[c->scur];
+    s.x_dst = c->xs[c->cur ^ 1];
+    s.v_dst = c->vs[c->cur ^ 1];
+    s.ri_dst = c->ri[c->scur ^ 1];
+    s.orig_dst = c->orig[c->scur ^ 1];
     s.bp_src = c->bp;
     s.bp_dst = c->bp_alt;
     s.cell_count = c->cell_count;
@@ -678,6 +697,7 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     s.stride = c->slots;
     HIP_OK(c, launch_sort(s, c->stream));
     c->cur ^= 1;
+    c->scur ^= 1;
     std::swap(c->bp, c->bp_alt);
     HIP_OK(c, fill_posq(c, c->cur));
     c->relist_pending = 1;  // slots moved: every row must be rebuilt
@@ -694,10 +714,12 @@ static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = 
   StepArgs a;
   a.sys = c->sys_d;
   a.tile_sys = c->tile_sys;
-  a.px_cur = c->px[c->cur];
-  a.pv_cur = c->pv[c->cur];
-  a.px_dst = c->px[c->cur ^ 1];
-  a.pv_dst = c->pv[c->cur ^ 1];
+  a.x_cur = c->xs[c->cur];
+  a.v_cur = c->vs[c->cur];
+  a.x_dst = c->xs[c->cur ^ 1];
+  a.v_dst = c->vs[c->cur ^ 1];
+  a.ri = c->ri[c->scur];
+  a.orig = c->orig[c->scur];
   a.posq_cur = c->posq[c->cur];
   a.posq_dst = c->posq[c->cur ^ 1];
   a.rrange = c->rrange;
@@ -738,7 +760,8 @@ static vb_status ensure_events(vb_ctx *c, size_t n) {
 // Queues n_steps steps; records go to hist_d[r * n_sys + s].
 // What a captured block of steps bakes in: buffers, sizes, launch shapes.
 static uint64_t graph_key(const vb_ctx *c, int cur) {
-  const uint64_t parts[] = {(uint64_t)(uintptr_t)c->px[cur], (uint64_t)(uintptr_t)c->nbr,
+  const uint64_t parts[] = {(uint64_t)(uintptr_t)c->xs[cur], (uint64_t)(uintptr_t)c->nbr,
+                            (uint64_t)(uintptr_t)c->ri[c->scur], (uint64_t)(uintptr_t)c->orig[c->scur],
                             (uint64_t)(uintptr_t)c->bp,
                             (uint64_t)(uintptr_t)c->bins_bp, (uint64_t)(uintptr_t)c->bins_so,
                             (uint64_t)(uintptr_t)c->hist[cur], (uint64_t)(uintptr_t)c->hist[cur ^ 1],
@@ -833,15 +856,21 @@ constexpr int SNAP_BLOCKS = 4;
 // the host's step bookkeeping.  The rows are not kept: a restore rebuilds them
 // from x0 and R_NL.
 static vb_status take_snapshot(vb_ctx *c, int32_t at) {
-  if (!c->snap_px) {
-    HIP_OK(c, dalloc(&c->snap_px, c->slots));
-    HIP_OK(c, dalloc(&c->snap_pv, c->slots));
+  if (!c->snap_x) {
+    HIP_OK(c, dalloc(&c->snap_x, c->slots));
+    HIP_OK(c, dalloc(&c->snap_v, c->slots));
+    HIP_OK(c, dalloc(&c->snap_ri, c->slots));
+    HIP_OK(c, dalloc(&c->snap_orig, c->slots));
     HIP_OK(c, dalloc(&c->snap_bp, c->slots));
     HIP_OK(c, dalloc(&c->snap_flags, 2 * (int64_t)c->n_sys));
   }
-  HIP_OK(c, hipMemcpyAsync(c->snap_px, c->px[c->cur], sizeof(PX) * c->slots,
+  HIP_OK(c, hipMemcpyAsync(c->snap_x, c->xs[c->cur], sizeof(X3) * c->slots,
                            hipMemcpyDeviceToDevice, c->stream));
-  HIP_OK(c, hipMemcpyAsync(c->snap_pv, c->pv[c->cur], sizeof(PV) * c->slots,
+  HIP_OK(c, hipMemcpyAsync(c->snap_v, c->vs[c->cur], sizeof(V3) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->snap_ri, c->ri[c->scur], sizeof(float2) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->snap_orig, c->orig[c->scur], sizeof(uint32_t) * c->slots,
                            hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->snap_bp, c->bp, sizeof(float4) * c->slots, hipMemcpyDeviceToDevice,
                            c->stream));
@@ -873,10 +902,15 @@ static vb_status take_snapshot(vb_ctx *c, int32_t at) {
 // (a broad phase where one was pending there), so the run from it repeats the
 // same schedule of broad phases, whatever capacities grew meanwhile.
 static vb_status restore_snapshot(vb_ctx *c) {
-  HIP_OK(c, hipMemcpyAsync(c->px[0], c->snap_px, sizeof(PX) * c->slots, hipMemcpyDeviceToDevice,
+  HIP_OK(c, hipMemcpyAsync(c->xs[0], c->snap_x, sizeof(X3) * c->slots, hipMemcpyDeviceToDevice,
                            c->stream));
-  HIP_OK(c, hipMemcpyAsync(c->pv[0], c->snap_pv, sizeof(PV) * c->slots, hipMemcpyDeviceToDevice,
+  HIP_OK(c, hipMemcpyAsync(c->vs[0], c->snap_v, sizeof(V3) * c->slots, hipMemcpyDeviceToDevice,
                            c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->ri[0], c->snap_ri, sizeof(float2) * c->slots, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->orig[0], c->snap_orig, sizeof(uint32_t) * c->slots,
+                           hipMemcpyDeviceToDevice, c->stream));
+  c->scur = 0;
   HIP_OK(c, hipMemcpyAsync(c->bp, c->snap_bp, sizeof(float4) * c->slots, hipMemcpyDeviceToDevice,
                            c->stream));
   HIP_OK(c, launch_fill_i32(c->cnt, c->slots, 0, c->stream));
@@ -1078,7 +1112,8 @@ extern "C" vb_status vb_get_state(vb_ctx *c, double *d_x, double *d_v,
                                   int32_t *h_v_is_half_step) {
   if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
   if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded");
-  HIP_OK(c, launch_get_state(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], c->pv[c->cur],
+  HIP_OK(c, launch_get_state(c->sys_d, c->tile_sys, c->n_tiles, c->xs[c->cur], c->vs[c->cur],
+                             c->orig[c->scur],
                              d_x, d_v, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (h_v_is_half_step) *h_v_is_half_step = c->first ? 0 : 1;
@@ -1092,7 +1127,7 @@ extern "C" vb_status vb_get_verlet_state(vb_ctx *c, float *d_x0r, int32_t *h_pen
   if (!c->have_list) return fail(c, VB_EINVAL, "no list yet: run a step first");
   if (c->n_total > 0 && !d_x0r) return fail(c, VB_EINVAL, "d_x0r is NULL");
   if (c->n_total > 0)
-    HIP_OK(c, launch_get_bp(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], c->bp,
+    HIP_OK(c, launch_get_bp(c->sys_d, c->tile_sys, c->n_tiles, c->orig[c->scur], c->bp,
                             reinterpret_cast<float4 *>(d_x0r), c->stream));
   std::vector<int32_t> fl((size_t)c->n_sys, 0);
   HIP_OK(c, hipMemcpyAsync(fl.data(), c->flags + (c->step & 1) * c->n_sys, sizeof(int32_t) * c->n_sys,
@@ -1118,7 +1153,7 @@ extern "C" vb_status vb_set_verlet_state(vb_ctx *c, const float *d_x0r, const in
   }
   HIP_OK(c, launch_fill_i32(c->err, 1, 0, c->stream));
   if (c->n_total > 0)
-    HIP_OK(c, launch_set_bp(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur],
+    HIP_OK(c, launch_set_bp(c->sys_d, c->tile_sys, c->n_tiles, c->orig[c->scur], c->ri[c->scur],
                             reinterpret_cast<const float4 *>(d_x0r), c->bp, c->err, c->stream));
   int32_t err = 0;
   HIP_OK(c, hipMemcpyAsync(&err, c->err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
@@ -1143,7 +1178,7 @@ extern "C" vb_status vb_get_history(vb_ctx *c, int32_t *d_partner, double *d_spr
   if (cap < 0 || (cap > 0 && (!d_partner || !d_spring)))
     return fail(c, VB_EINVAL, "bad output buffers");
   HIP_OK(c, launch_fill_i32(c->err, 1, 0, c->stream));
-  HIP_OK(c, launch_get_history(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], c->hist[c->cur],
+  HIP_OK(c, launch_get_history(c->sys_d, c->tile_sys, c->n_tiles, c->orig[c->scur], c->hist[c->cur],
                                c->hcnt[c->cur], c->slots, c->hcap, d_partner, d_spring, cap,
                                c->err, c->stream));
   int32_t needed = 0;
@@ -1183,7 +1218,7 @@ extern "C" vb_status vb_set_history(vb_ctx *c, const int32_t *d_partner, const d
   vb_status st;
   if (chk[0] > c->hcap && (st = alloc_hist_tables(c, std::min(MAX_HIST, (chk[0] + 3) / 4 * 4))) != VB_OK)
     return st;
-  HIP_OK(c, launch_set_history(c->sys_d, c->tile_sys, c->n_tiles, c->px[c->cur], d_partner,
+  HIP_OK(c, launch_set_history(c->sys_d, c->tile_sys, c->n_tiles, c->orig[c->scur], d_partner,
                                d_spring, cap, c->hist[c->cur], c->hcnt[c->cur], c->slots, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   return VB_OK;
@@ -1209,7 +1244,8 @@ extern "C" vb_status vb_get_pairs(vb_ctx *c, int32_t sys, int32_t which, int32_t
       return fail(c, VB_ECAPACITY, "list row or cell bin overflow in the broad phase; run a "
                                    "step first so that vb_run grows them");
   }
-  HIP_OK(c, launch_pairs(c->sys_h[sys], c->px[c->cur], c->cnt, c->nbr, c->slots, which,
+  HIP_OK(c, launch_pairs(c->sys_h[sys], c->xs[c->cur], c->ri[c->scur], c->orig[c->scur], c->cnt,
+                         c->nbr, c->slots, which,
                          c->pair_counts, c->pair_offsets, c->pair_total, cap,
                          cap > 0 ? d_pairs : nullptr, cap > 0 ? d_delta : nullptr, c->stream));
   int64_t total = 0;
@@ -1249,7 +1285,8 @@ extern "C" vb_status vb_get_pairs_noalloc(vb_ctx *c, int32_t sys, int32_t which,
       return fail(c, VB_ECAPACITY, "list row or cell bin overflow in the broad phase; run a "
                                    "step first so that vb_run grows them");
   }
-  HIP_OK(c, launch_pairs(c->sys_h[sys], c->px[c->cur], c->cnt, c->nbr, c->slots, which, counts,
+  HIP_OK(c, launch_pairs(c->sys_h[sys], c->xs[c->cur], c->ri[c->scur], c->orig[c->scur], c->cnt,
+                         c->nbr, c->slots, which, counts,
                          offsets, total_d, cap, cap > 0 ? d_pairs : nullptr,
                          cap > 0 ? d_delta : nullptr, c->stream));
   int64_t total = 0;

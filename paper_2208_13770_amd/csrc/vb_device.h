@@ -2,9 +2,11 @@
 //
 // Particles live in "slots".  Each system of a batch owns a contiguous range of
 // slots padded to a multiple of TILE, so a tile (one workgroup) never straddles
-// two systems.  The original index travels inside the position record; the slot
-// order is re-sorted by cell from time to time for locality (not at every broad
-// phase), so rows of the Verlet list hold slots and are ordered by original index.
+// two systems.  What a step changes (position, velocity) is kept apart from what
+// only a storage sort moves (R_C, 1/m, original index), so that a step writes
+// the 48 bytes of state it changes and nothing else.  The slot order is
+// re-sorted by cell from time to time for locality (not at every broad phase),
+// so rows of the Verlet list hold slots and are ordered by original index.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,20 +29,19 @@ constexpr int CONTACT_UNROLL = 2; // candidates whose records are requested toge
 constexpr int PAIRS_T = 384;      // threads of a pair-search workgroup (one brick): a brick of
                                   // 64 cells at about 5 particles per cell in one pass
 
-// Position record, 32 B: FP64 centre, FP32 cut-off radius R_C, original index.
-struct alignas(16) PX {
+// Position of a slot, 24 B: FP64 centre.  Double-buffered (a step reads one
+// buffer and writes the other).
+struct X3 {
   double x, y, z;
-  float rc;
-  uint32_t orig;
 };
-// Velocity record, 32 B: FP64 velocity (the half-step velocity once running),
-// FP32 inverse mass.
-struct alignas(16) PV {
+// Velocity of a slot, 24 B: FP64 velocity (the half-step velocity once running).
+// Double-buffered like the position.
+struct V3 {
   double vx, vy, vz;
-  float invm;
-  uint32_t pad;
 };
-static_assert(sizeof(PX) == 32 && sizeof(PV) == 32, "records are 32 bytes");
+static_assert(sizeof(X3) == 24 && sizeof(V3) == 24, "state records are 24 bytes");
+// Per slot and constant between storage sorts: float2 (R_C, 1/m) and the
+// original index (uint32), each in an array of its own.
 
 // One system of the batch, as the kernels see it.
 struct SysDev {
@@ -106,8 +107,10 @@ struct BroadArgs {
   const int32_t *tile_sys;
   int32_t n_sys;
   int64_t n_tiles;
-  const PX *px;
-  const PV *pv;
+  const X3 *x;
+  const V3 *v;
+  const float2 *ri;     // [slots] (R_C, 1/m)
+  const uint32_t *orig; // [slots] original index
   float4 *bp;           // [slots] x0 (FP32) and R_NL of the broad phase
   int32_t *cnt;         // [slots] row lengths
   int32_t *nbr;         // rows, column-major: entry q of slot k at nbr[q * stride + k]
@@ -136,12 +139,14 @@ struct BroadArgs {
 struct StepArgs {
   const SysDev *sys;
   const int32_t *tile_sys;
-  const PX *px_cur;
-  const PV *pv_cur;
-  PX *px_dst;
-  PV *pv_dst;
-  const uint64_t *posq_cur;  // coded positions and radius bounds of px_cur
-  uint64_t *posq_dst;        // written with px_dst
+  const X3 *x_cur;
+  const V3 *v_cur;
+  X3 *x_dst;
+  V3 *v_dst;
+  const float2 *ri;          // [slots] (R_C, 1/m)
+  const uint32_t *orig;      // [slots] original index
+  const uint64_t *posq_cur;  // coded positions and radius bounds of x_cur
+  uint64_t *posq_dst;        // written with x_dst
   const int32_t *rrange;     // [2][n_sys] FP32 bits of each system's smallest and largest R_C
   const float4 *bp;
   const int32_t *cnt;
@@ -174,10 +179,14 @@ struct SortArgs {
   const int32_t *tile_sys;
   int64_t n_tiles;
   int64_t n_cells;
-  const PX *px_src;
-  const PV *pv_src;
-  PX *px_dst;
-  PV *pv_dst;
+  const X3 *x_src;
+  const V3 *v_src;
+  const float2 *ri_src;
+  const uint32_t *orig_src;
+  X3 *x_dst;
+  V3 *v_dst;
+  float2 *ri_dst;
+  uint32_t *orig_dst;
   const float4 *bp_src; // x0 and R_NL of the last broad phase move with their particle
   float4 *bp_dst;
   int32_t *cell_count;  // [cells] zero on entry, zero on exit

@@ -84,13 +84,14 @@ __device__ __forceinline__ int64_t block_sum_i64(int64_t v) {
 // Returns true iff delta > 0 (contact, Sec. 3.2), with the separation vector
 // and distance for the force.  The cheap test on the squared distance only
 // skips pairs whose overlap is certainly negative.
-__device__ __forceinline__ bool overlap_positive(const PX &a, const PX &b, double &dx, double &dy,
-                                                 double &dz, double &d, double &delta) {
+__device__ __forceinline__ bool overlap_positive(const X3 &a, float arc, const X3 &b, float brc,
+                                                 double &dx, double &dy, double &dz, double &d,
+                                                 double &delta) {
   dx = a.x - b.x;
   dy = a.y - b.y;
   dz = a.z - b.z;
   const double d2 = dx * dx + dy * dy + dz * dz;
-  const double rs = (double)a.rc + (double)b.rc;
+  const double rs = (double)arc + (double)brc;
   if (!(d2 < rs * rs * (1.0 + 1e-12))) return false;
   d = sqrt(d2);
   delta = rs - d;
@@ -246,13 +247,11 @@ __device__ __forceinline__ void nt_store(float4 *p, const float4 &v) {
   const vf4_t w = {v.x, v.y, v.z, v.w};
   __builtin_nontemporal_store(w, reinterpret_cast<vf4_t *>(p));
 }
-template <typename T>
-__device__ __forceinline__ void nt_store32(T *dst, const T &val) {
-  static_assert(sizeof(T) == 32, "32-byte records");
-  const vd2_t *s = reinterpret_cast<const vd2_t *>(&val);
-  vd2_t *d = reinterpret_cast<vd2_t *>(dst);
-  __builtin_nontemporal_store(s[0], d);
-  __builtin_nontemporal_store(s[1], d + 1);
+// A 24-byte state record (three doubles, 8-byte aligned), non-temporal.
+__device__ __forceinline__ void nt_store24(double *dst, double a, double b, double c) {
+  __builtin_nontemporal_store(a, dst);
+  __builtin_nontemporal_store(b, dst + 1);
+  __builtin_nontemporal_store(c, dst + 2);
 }
 
 // ------------------------------------------------------------------ k_step
@@ -266,8 +265,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   const int local = lt * TILE + (int)threadIdx.x;
   const bool active = local < S.n;
   const int64_t k = S.p_off + local;
-  const PX *__restrict__ px = a.px_cur;
-  const PV *__restrict__ pv = a.pv_cur;
+  const X3 *__restrict__ xs = a.x_cur;
+  const V3 *__restrict__ vs = a.v_cur;
+  const float *__restrict__ rcs = reinterpret_cast<const float *>(a.ri);  // R_C at 2k, 1/m at 2k+1
   const int step = a.step + (a.step_base ? *a.step_base : 0);
   __shared__ int32_t s_cand[MAX_CAND * TILE];  // per-thread lists of contact candidates
 
@@ -293,10 +293,12 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     int32_t j[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? nt_load(&row[(int64_t)u * st]) : 0;
-    const PX me = px[k];
-    const PV mv = pv[k];
+    const X3 me = xs[k];  // plain loads: the flushes of the neighbours gather them too
+    const V3 mv = vs[k];
+    const float2 mri = a.ri[k];
+    const float mrc = mri.x;
     const float rlo = __int_as_float(a.rrange[s]), rhi = __int_as_float(a.rrange[a.n_sys + s]);
-    const QSelf mq = posq_self(posq_encode(S, rlo, rhi, me.x, me.y, me.z, me.rc), me.rc, S.qinv32);
+    const QSelf mq = posq_self(posq_encode(S, rlo, rhi, me.x, me.y, me.z, mrc), mrc, S.qinv32);
     const float rlo_q = rlo * S.qinv32, step_q = radius_step(rlo, rhi) * S.qinv32;
     const float4 b = nt_load(&a.bp[k]);
     rowlen = nt_load(&a.cnt[k]);
@@ -310,9 +312,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     HistEntry hold;
     hold.orig = 0xFFFFFFFFu;
     if (hn > 0) hold = a.hist_cur[k];
-    auto contact = [&](const PX &o, const PV &ov) {
+    auto contact = [&](const X3 &o, float orc, const V3 &ov, uint32_t oorig) {
       double dx, dy, dz, d, delta;
-      if (overlap_positive(me, o, dx, dy, dz, d, delta)) {
+      if (overlap_positive(me, mrc, o, orc, dx, dy, dz, d, delta)) {
         const double nx = dx / d, ny = dy / d, nz = dz / d;
         const double vn = (mv.vx - ov.vx) * nx + (mv.vy - ov.vy) * ny + (mv.vz - ov.vz) * nz;
         const double fm = S.kn * delta - S.gamma_n * vn;
@@ -326,12 +328,12 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
             // of the previous step, turned into the tangent plane, grows by
             // v_t dt; a force beyond mu F_n is cut back to the cone and the
             // spring set to the one that gives it
-            while (hp < hn && hold.orig < o.orig) {
+            while (hp < hn && hold.orig < oorig) {
               ++hp;
               if (hp < hn) hold = a.hist_cur[(int64_t)hp * st + k];
             }
             double sx = 0.0, sy = 0.0, sz = 0.0;
-            if (hp < hn && hold.orig == o.orig) {
+            if (hp < hn && hold.orig == oorig) {
               sx = hold.sx;
               sy = hold.sy;
               sz = hold.sz;
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
               e.sx = sx;
               e.sy = sy;
               e.sz = sz;
-              e.orig = o.orig;
+              e.orig = oorig;
               e.pad = 0;
               a.hist_dst[(int64_t)hc * st + k] = e;
             }
@@ -404,20 +406,25 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       }
       for (int i0 = 0; i0 < nc; i0 += CONTACT_UNROLL) {
         int32_t jj[CONTACT_UNROLL];
-        PX o[CONTACT_UNROLL];
-        PV ov[CONTACT_UNROLL];
+        X3 o[CONTACT_UNROLL];
+        V3 ov[CONTACT_UNROLL];
+        float orc[CONTACT_UNROLL];
+        uint32_t oo[CONTACT_UNROLL];
 #pragma unroll
         for (int u = 0; u < CONTACT_UNROLL; ++u)
           jj[u] = i0 + u < nc ? s_cand[(i0 + u) * TILE + threadIdx.x] : 0;
 #pragma unroll
         for (int u = 0; u < CONTACT_UNROLL; ++u)
           if (i0 + u < nc) {
-            o[u] = px[S.p_off + jj[u]];
-            ov[u] = pv[S.p_off + jj[u]];
+            const int64_t q = S.p_off + jj[u];
+            o[u] = xs[q];
+            orc[u] = rcs[2 * q];
+            ov[u] = vs[q];
+            oo[u] = FRIC ? a.orig[q] : 0u;
           }
 #pragma unroll
         for (int u = 0; u < CONTACT_UNROLL; ++u)
-          if (i0 + u < nc) contact(o[u], ov[u]);
+          if (i0 + u < nc) contact(o[u], orc[u], ov[u], oo[u]);
       }
     }
     if constexpr (FRIC) {
@@ -433,9 +440,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     double f[3] = {fx, fy, fz};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double dlo = (double)me.rc - (pos[ax] - S.lo[ax]);
+      const double dlo = (double)mrc - (pos[ax] - S.lo[ax]);
       if (dlo > 0.0) f[ax] += S.kn * dlo - S.gamma_n * vel[ax];
-      const double dhi = (double)me.rc - (S.hi[ax] - pos[ax]);
+      const double dhi = (double)mrc - (S.hi[ax] - pos[ax]);
       if (dhi > 0.0) f[ax] -= S.kn * dhi - S.gamma_n * (-vel[ax]);
     }
     // planar walls, in index order: the same law against the half-space n.x < d,
@@ -444,7 +451,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       const double *pl = S.planes[w];
       if (!(pos[2] > pl[4])) continue;
       const double sd = pl[0] * pos[0] + pl[1] * pos[1] + pl[2] * pos[2] - pl[3];
-      const double dw = (double)me.rc - sd;
+      const double dw = (double)mrc - sd;
       if (dw > 0.0) {
         const double vn = vel[0] * pl[0] + vel[1] * pl[1] + vel[2] * pl[2];
         const double fm = S.kn * dw - S.gamma_n * vn;
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     }
     // velocity Verlet: v^n = v^{n-1/2} + dt/2 a^n, v^{n+1/2} = v^n + dt/2 a^n,
     // x^{n+1} = x^n + dt v^{n+1/2}
-    const double hdt = 0.5 * S.dt, im = (double)mv.invm;
+    const double hdt = 0.5 * S.dt, im = (double)mri.y;
     double vf[3], vn[3], xn[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -464,21 +471,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       vn[ax] = vf[ax] + hdt * acc;
       xn[ax] = pos[ax] + S.dt * vn[ax];
     }
-    PX outx;
-    outx.x = xn[0];
-    outx.y = xn[1];
-    outx.z = xn[2];
-    outx.rc = me.rc;
-    outx.orig = me.orig;
-    PV outv;
-    outv.vx = vn[0];
-    outv.vy = vn[1];
-    outv.vz = vn[2];
-    outv.invm = mv.invm;
-    outv.pad = 0;
-    nt_store32(&a.px_dst[k], outx);
-    nt_store32(&a.pv_dst[k], outv);
-    __builtin_nontemporal_store(posq_encode(S, rlo, rhi, xn[0], xn[1], xn[2], me.rc), &a.posq_dst[k]);
+    nt_store24(&a.x_dst[k].x, xn[0], xn[1], xn[2]);
+    nt_store24(&a.v_dst[k].vx, vn[0], vn[1], vn[2]);
+    __builtin_nontemporal_store(posq_encode(S, rlo, rhi, xn[0], xn[1], xn[2], mrc), &a.posq_dst[k]);
     ke = 0.5 * (vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2]) / im;
     // Eq. update for the next step: straight-line displacement since the last
     // broad phase against the skin left after the cap (R_NL - R_C)
@@ -486,7 +481,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const float ddy = (float)(xn[1] - (double)b.y);
     const float ddz = (float)(xn[2] - (double)b.z);
     const float disp = sqrtf(__fmaf_rn(ddx, ddx, __fmaf_rn(ddy, ddy, ddz * ddz)));
-    const float skin_eff = b.w - me.rc;
+    const float skin_eff = b.w - mrc;
     viol = disp > skin_eff ? 1 : 0;
     excess = disp - skin_eff;
   }
@@ -565,14 +560,14 @@ __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
     uint32_t orig = 0;
     if (local < S.n) {
       const int64_t k = S.p_off + local;
-      const PX x = a.px[k];
+      const X3 x = a.x[k];
       if (nd) {
-        const PV v = a.pv[k];
+        const V3 v = a.v[k];
         double skin;
         if (S.skin_mode == 0) skin = S.K * sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz) * S.dt;
         else if (S.skin_mode == 2) skin = 0.0;
         else skin = S.skin_uniform;
-        const double r = (double)x.rc + skin;
+        const double r = (double)a.ri[k].x + skin;
         const double rnl = r < S.cap ? r : S.cap;
         b = make_float4((float)x.x, (float)x.y, (float)x.z, (float)rnl);
         a.bp[k] = b;
@@ -584,8 +579,8 @@ __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
         b = a.bp[k];
         key = S.c_off + cell_of(S, (double)b.x, (double)b.y, (double)b.z);
       }
-      a.inv[S.p_off + x.orig] = local;
-      orig = x.orig;
+      orig = a.orig[k];
+      a.inv[S.p_off + orig] = local;
     }
     const int slot = wave_bin_slot(a.bin_count, key);
     if (key >= 0) {
@@ -898,7 +893,7 @@ __global__ __launch_bounds__(TILE) void k_sort_count(SortArgs a) {
   const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  const PX p = a.px_src[k];
+  const X3 p = a.x_src[k];
   const int c = cell_of(S, p.x, p.y, p.z);
   a.cellid[k] = c;
   a.inslot[k] = atomicAdd(&a.cell_count[S.c_off + c], 1);
@@ -983,11 +978,13 @@ __global__ __launch_bounds__(TILE) void k_sort_place(SortArgs a) {
   const int32_t base = a.cell_start[S.c_off];
   const int64_t cs = S.p_off + (a.cell_start[S.c_off + c] - base);
   const int64_t ce = S.p_off + (a.cell_start[S.c_off + c + 1] - base);
-  const PX me = a.px_src[S.p_off + q];
+  const uint32_t me = a.orig_src[S.p_off + q];
   int rank = 0;
-  for (int64_t m = cs; m < ce; ++m) rank += a.px_src[S.p_off + a.perm0[m]].orig < me.orig;
-  a.px_dst[cs + rank] = me;
-  a.pv_dst[cs + rank] = a.pv_src[S.p_off + q];
+  for (int64_t m = cs; m < ce; ++m) rank += a.orig_src[S.p_off + a.perm0[m]] < me;
+  a.x_dst[cs + rank] = a.x_src[S.p_off + q];
+  a.v_dst[cs + rank] = a.v_src[S.p_off + q];
+  a.ri_dst[cs + rank] = a.ri_src[S.p_off + q];
+  a.orig_dst[cs + rank] = me;
   a.bp_dst[cs + rank] = a.bp_src[S.p_off + q];
   if (a.hist_src) {  // the friction history moves with its particle
     const int hn = a.hcnt_src[S.p_off + q];
@@ -1057,60 +1054,55 @@ __global__ __launch_bounds__(TILE) void k_stats_reduce(const SysDev *sys, const 
 
 // Coded positions of every slot, for the step kernel's pre-test.
 __global__ void k_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
-                       const PX *px, uint64_t *posq, int64_t n) {
+                       const X3 *xs, const float2 *ri, uint64_t *posq, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int s = tile_sys[i / TILE];
-  const PX p = px[i];
+  const X3 p = xs[i];
   posq[i] = posq_encode(sys[s], __int_as_float(rrange[s]), __int_as_float(rrange[n_sys + s]), p.x,
-                        p.y, p.z, p.rc);
+                        p.y, p.z, ri[i].x);
 }
 
 // Load one system from the caller's original order; flags bad values in *err:
 // bit 0 non-finite, bit 1 radius out of range, bit 2 non-positive inverse mass.
 // The smallest and largest valid R_C go to *r_lo and *r_hi (FP32 bits; positive
 // floats order like their bits).
-__global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const double *v,
-                            const float *rc, const float *invm, int32_t *err, int32_t *r_lo,
-                            int32_t *r_hi) {
+__global__ void k_set_state(SysDev S, X3 *xs, V3 *vs, float2 *ri, uint32_t *origs, const double *x,
+                            const double *v, const float *rc, const float *invm, int32_t *err,
+                            int32_t *r_lo, int32_t *r_hi) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t padded = (int64_t)S.n_tiles * TILE;
   if (i >= padded) return;  // padded is a multiple of the block size: whole waves
-  PX p;
-  PV q;
+  X3 p = {0.0, 0.0, 0.0};
+  V3 q = {0.0, 0.0, 0.0};
+  float2 r = make_float2(0.0f, 0.0f);
+  uint32_t o = 0xFFFFFFFFu;
   float rmin = INFINITY, rmax = 0.0f;
   if (i < S.n) {
     const int64_t g = S.o_off + i;
     p.x = x[3 * g];
     p.y = x[3 * g + 1];
     p.z = x[3 * g + 2];
-    p.rc = rc[g];
-    p.orig = (uint32_t)i;
     q.vx = v[3 * g];
     q.vy = v[3 * g + 1];
     q.vz = v[3 * g + 2];
-    q.invm = invm[g];
-    q.pad = 0;
+    r = make_float2(rc[g], invm[g]);
+    o = (uint32_t)i;
     int e = 0;
     if (!isfinite(p.x) || !isfinite(p.y) || !isfinite(p.z) || !isfinite(q.vx) ||
-        !isfinite(q.vy) || !isfinite(q.vz) || !isfinite(p.rc) || !isfinite(q.invm))
+        !isfinite(q.vy) || !isfinite(q.vz) || !isfinite(r.x) || !isfinite(r.y))
       e |= 1;
     else {
-      if (!(p.rc > 0.0f) || (double)p.rc > S.cap) e |= 2;
-      if (!(q.invm > 0.0f)) e |= 4;
+      if (!(r.x > 0.0f) || (double)r.x > S.cap) e |= 2;
+      if (!(r.y > 0.0f)) e |= 4;
     }
     if (e) atomicOr(err, e);
-    else rmin = rmax = p.rc;
-  } else {
-    p.x = p.y = p.z = 0.0;
-    p.rc = 0.0f;
-    p.orig = 0xFFFFFFFFu;
-    q.vx = q.vy = q.vz = 0.0;
-    q.invm = 0.0f;
-    q.pad = 0;
+    else rmin = rmax = r.x;
   }
-  px[S.p_off + i] = p;
-  pv[S.p_off + i] = q;
+  xs[S.p_off + i] = p;
+  vs[S.p_off + i] = q;
+  ri[S.p_off + i] = r;
+  origs[S.p_off + i] = o;
   rmin = -wave_max(-rmin);
   rmax = wave_max(rmax);
   if ((threadIdx.x & (WAVE - 1)) == 0 && rmax > 0.0f) {
@@ -1122,7 +1114,7 @@ __global__ void k_set_state(SysDev S, PX *px, PV *pv, const double *x, const dou
 // Friction history to the caller's original order: particle g's contacts of
 // the last step (partner ascending) in partner[g][0..cap), -1 after the last,
 // with their springs; *needed receives the largest count of any particle.
-__global__ void k_get_history(const SysDev *sys, const int32_t *tile_sys, const PX *px,
+__global__ void k_get_history(const SysDev *sys, const int32_t *tile_sys, const uint32_t *origs,
                               const HistEntry *hist, const int32_t *hcnt, int64_t stride,
                               int32_t hcap, int32_t *partner, double *spring, int32_t cap,
                               int32_t *needed) {
@@ -1131,7 +1123,7 @@ __global__ void k_get_history(const SysDev *sys, const int32_t *tile_sys, const 
   const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  const int64_t g = S.o_off + px[k].orig;
+  const int64_t g = S.o_off + origs[k];
   const int n = S.friction ? min(hcnt[k], hcap) : 0;
   if (n > 0) atomicMax(needed, n);
   for (int c = 0; c < cap; ++c) {
@@ -1175,7 +1167,7 @@ __global__ void k_check_history(SysDev S, const int32_t *partner, const double *
 
 // Loads a checked history into the tables: each slot takes the contacts of
 // the particle it holds (whatever the storage order).
-__global__ void k_set_history(const SysDev *sys, const int32_t *tile_sys, const PX *px,
+__global__ void k_set_history(const SysDev *sys, const int32_t *tile_sys, const uint32_t *origs,
                               const int32_t *partner, const double *spring, int32_t cap,
                               HistEntry *hist, int32_t *hcnt, int64_t stride) {
   const int64_t t = blockIdx.x;
@@ -1183,7 +1175,7 @@ __global__ void k_set_history(const SysDev *sys, const int32_t *tile_sys, const 
   const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
   if (local >= S.n || !S.friction) return;
   const int64_t k = S.p_off + local;
-  const int64_t g = S.o_off + px[k].orig;
+  const int64_t g = S.o_off + origs[k];
   int n = 0;
   for (int c = 0; c < cap; ++c) {
     const int32_t who = partner[g * cap + c];
@@ -1202,51 +1194,50 @@ __global__ void k_set_history(const SysDev *sys, const int32_t *tile_sys, const 
 
 // The Verlet state in the caller's original order: x0 (FP32) and R_NL of the
 // last broad phase, one float4 per particle.
-__global__ void k_get_bp(const SysDev *sys, const int32_t *tile_sys, const PX *px, const float4 *bp,
-                         float4 *x0r) {
+__global__ void k_get_bp(const SysDev *sys, const int32_t *tile_sys, const uint32_t *origs,
+                         const float4 *bp, float4 *x0r) {
   const int64_t t = blockIdx.x;
   const SysDev &S = sys[tile_sys[t]];
   const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  x0r[S.o_off + px[k].orig] = bp[k];
+  x0r[S.o_off + origs[k]] = bp[k];
 }
 
 // Loads a Verlet state given in original order into the slots; flags bad values
 // in *err: bit 0 not finite, bit 1 R_NL below R_C or beyond the cap.
-__global__ void k_set_bp(const SysDev *sys, const int32_t *tile_sys, const PX *px, const float4 *x0r,
-                         float4 *bp, int32_t *err) {
+__global__ void k_set_bp(const SysDev *sys, const int32_t *tile_sys, const uint32_t *origs,
+                         const float2 *ri, const float4 *x0r, float4 *bp, int32_t *err) {
   const int64_t t = blockIdx.x;
   const SysDev &S = sys[tile_sys[t]];
   const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  const PX p = px[k];
-  const float4 b = x0r[S.o_off + p.orig];
+  const float4 b = x0r[S.o_off + origs[k]];
   int e = 0;
   if (!isfinite(b.x) || !isfinite(b.y) || !isfinite(b.z) || !isfinite(b.w)) e |= 1;
-  else if (!(b.w >= p.rc) || !(b.w <= (float)S.cap)) e |= 2;
+  else if (!(b.w >= ri[k].x) || !(b.w <= (float)S.cap)) e |= 2;
   if (e) atomicOr(err, e);
   bp[k] = b;
 }
 
 // Copy the state back to the caller's original order.
-__global__ void k_get_state(const SysDev *sys, const int32_t *tile_sys, const PX *px, const PV *pv,
-                            double *x, double *v) {
+__global__ void k_get_state(const SysDev *sys, const int32_t *tile_sys, const X3 *xs, const V3 *vs,
+                            const uint32_t *origs, double *x, double *v) {
   const int64_t t = blockIdx.x;
   const SysDev &S = sys[tile_sys[t]];
   const int local = (int)(t - S.tile_off) * TILE + (int)threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  const PX p = px[k];
-  const int64_t g = S.o_off + p.orig;
+  const int64_t g = S.o_off + origs[k];
   if (x) {
+    const X3 p = xs[k];
     x[3 * g] = p.x;
     x[3 * g + 1] = p.y;
     x[3 * g + 2] = p.z;
   }
   if (v) {
-    const PV q = pv[k];
+    const V3 q = vs[k];
     v[3 * g] = q.vx;
     v[3 * g + 1] = q.vy;
     v[3 * g + 2] = q.vz;
@@ -1257,50 +1248,59 @@ __global__ void k_get_state(const SysDev *sys, const int32_t *tile_sys, const PX
 
 // Per original index i of system S: how many row entries j have orig(j) > i
 // (and positive overlap when contacts_only).
-__global__ void k_pairs_count(SysDev S, const PX *px, const int32_t *cnt, const int32_t *nbr,
-                              int64_t stride, int32_t contacts_only, int32_t *counts) {
+__global__ void k_pairs_count(SysDev S, const X3 *xs, const float2 *ri, const uint32_t *origs,
+                              const int32_t *cnt, const int32_t *nbr, int64_t stride,
+                              int32_t contacts_only, int32_t *counts) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  const PX me = px[k];
+  const X3 me = xs[k];
+  const float mrc = ri[k].x;
+  const uint32_t mo = origs[k];
   int c = 0;
   const int len = cnt[k];
   for (int q = 0; q < len; ++q) {
-    const PX o = px[S.p_off + nbr[(int64_t)q * stride + k]];
-    if (o.orig <= me.orig) continue;
+    const int64_t j = S.p_off + nbr[(int64_t)q * stride + k];
+    if (origs[j] <= mo) continue;
     if (contacts_only) {
       double dx, dy, dz, d, delta;
-      if (!overlap_positive(me, o, dx, dy, dz, d, delta)) continue;
+      if (!overlap_positive(me, mrc, xs[j], ri[j].x, dx, dy, dz, d, delta)) continue;
     }
     ++c;
   }
-  counts[me.orig] = c;
+  counts[mo] = c;
 }
 
-__global__ void k_pairs_write(SysDev S, const PX *px, const int32_t *cnt, const int32_t *nbr,
-                              int64_t stride, int32_t contacts_only, const int64_t *offsets,
-                              int64_t cap, int32_t *pairs, double *delta_out) {
+__global__ void k_pairs_write(SysDev S, const X3 *xs, const float2 *ri, const uint32_t *origs,
+                              const int32_t *cnt, const int32_t *nbr, int64_t stride,
+                              int32_t contacts_only, const int64_t *offsets, int64_t cap,
+                              int32_t *pairs, double *delta_out) {
   const int local = blockIdx.x * blockDim.x + threadIdx.x;
   if (local >= S.n) return;
   const int64_t k = S.p_off + local;
-  const PX me = px[k];
-  int64_t off = offsets[me.orig];
+  const X3 me = xs[k];
+  const float mrc = ri[k].x;
+  const uint32_t mo = origs[k];
+  int64_t off = offsets[mo];
   const int len = cnt[k];
   for (int q = 0; q < len; ++q) {
-    const PX o = px[S.p_off + nbr[(int64_t)q * stride + k]];
-    if (o.orig <= me.orig) continue;
+    const int64_t j = S.p_off + nbr[(int64_t)q * stride + k];
+    const uint32_t oo = origs[j];
+    if (oo <= mo) continue;
+    const X3 o = xs[j];
+    const float orc = ri[j].x;
     double dx, dy, dz, d = 0.0, delta = 0.0;
-    const bool touch = overlap_positive(me, o, dx, dy, dz, d, delta);
+    const bool touch = overlap_positive(me, mrc, o, orc, dx, dy, dz, d, delta);
     if (contacts_only && !touch) continue;
     if (!touch) {
       dx = me.x - o.x;
       dy = me.y - o.y;
       dz = me.z - o.z;
-      delta = ((double)me.rc + (double)o.rc) - sqrt(dx * dx + dy * dy + dz * dz);
+      delta = ((double)mrc + (double)orc) - sqrt(dx * dx + dy * dy + dz * dz);
     }
     if (off < cap) {
-      pairs[2 * off] = (int32_t)me.orig;
-      pairs[2 * off + 1] = (int32_t)o.orig;
+      pairs[2 * off] = (int32_t)mo;
+      pairs[2 * off + 1] = (int32_t)oo;
       if (delta_out) delta_out[off] = delta;
     }
     ++off;
@@ -1432,45 +1432,48 @@ hipError_t launch_stats_reduce(const SysDev *sys, const TileStats *stats, const 
   return hipGetLastError();
 }
 
-hipError_t launch_set_state(const SysDev &S, PX *px, PV *pv, const double *x, const double *v,
-                            const float *rc, const float *invm, int32_t *err, int32_t *r_lo,
-                            int32_t *r_hi, hipStream_t st) {
+hipError_t launch_set_state(const SysDev &S, X3 *xs, V3 *vs, float2 *ri, uint32_t *origs,
+                            const double *x, const double *v, const float *rc, const float *invm,
+                            int32_t *err, int32_t *r_lo, int32_t *r_hi, hipStream_t st) {
   const int64_t padded = (int64_t)S.n_tiles * TILE;
   if (padded == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_state, dim3((unsigned)(padded / 256)), dim3(256), 0, st, S, px, pv, x, v,
-                     rc, invm, err, r_lo, r_hi);
+  hipLaunchKernelGGL(k_set_state, dim3((unsigned)(padded / 256)), dim3(256), 0, st, S, xs, vs, ri,
+                     origs, x, v, rc, invm, err, r_lo, r_hi);
   return hipGetLastError();
 }
 
 hipError_t launch_get_state(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
-                            const PX *px, const PV *pv, double *x, double *v, hipStream_t st) {
+                            const X3 *xs, const V3 *vs, const uint32_t *origs, double *x, double *v,
+                            hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_get_state, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
-                     pv, x, v);
+  hipLaunchKernelGGL(k_get_state, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, xs,
+                     vs, origs, x, v);
   return hipGetLastError();
 }
 
-hipError_t launch_get_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
-                         const float4 *bp, float4 *x0r, hipStream_t st) {
+hipError_t launch_get_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                         const uint32_t *origs, const float4 *bp, float4 *x0r, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_get_bp, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px, bp, x0r);
+  hipLaunchKernelGGL(k_get_bp, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, origs, bp,
+                     x0r);
   return hipGetLastError();
 }
 
-hipError_t launch_set_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles, const PX *px,
-                         const float4 *x0r, float4 *bp, int32_t *err, hipStream_t st) {
+hipError_t launch_set_bp(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
+                         const uint32_t *origs, const float2 *ri, const float4 *x0r, float4 *bp,
+                         int32_t *err, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_bp, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px, x0r, bp,
-                     err);
+  hipLaunchKernelGGL(k_set_bp, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, origs, ri,
+                     x0r, bp, err);
   return hipGetLastError();
 }
 
 hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
-                              const PX *px, const HistEntry *hist, const int32_t *hcnt,
+                              const uint32_t *origs, const HistEntry *hist, const int32_t *hcnt,
                               int64_t stride, int32_t hcap, int32_t *partner, double *spring,
                               int32_t cap, int32_t *needed, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_get_history, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
+  hipLaunchKernelGGL(k_get_history, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, origs,
                      hist, hcnt, stride, hcap, partner, spring, cap, needed);
   return hipGetLastError();
 }
@@ -1484,36 +1487,36 @@ hipError_t launch_check_history(const SysDev &S, const int32_t *partner, const d
 }
 
 hipError_t launch_set_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
-                              const PX *px, const int32_t *partner, const double *spring,
+                              const uint32_t *origs, const int32_t *partner, const double *spring,
                               int32_t cap, HistEntry *hist, int32_t *hcnt, int64_t stride,
                               hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_set_history, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, px,
+  hipLaunchKernelGGL(k_set_history, dim3((unsigned)n_tiles), dim3(TILE), 0, st, sys, tile_sys, origs,
                      partner, spring, cap, hist, hcnt, stride);
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(const SysDev &S, const PX *px, const int32_t *cnt, const int32_t *nbr,
-                        int64_t stride, int32_t contacts_only, int32_t *counts, int64_t *offsets,
-                        int64_t *total, int64_t cap, int32_t *pairs, double *delta,
-                        hipStream_t st) {
+hipError_t launch_pairs(const SysDev &S, const X3 *xs, const float2 *ri, const uint32_t *origs,
+                        const int32_t *cnt, const int32_t *nbr, int64_t stride,
+                        int32_t contacts_only, int32_t *counts, int64_t *offsets, int64_t *total,
+                        int64_t cap, int32_t *pairs, double *delta, hipStream_t st) {
   if (S.n <= 0) return hipSuccess;
   const unsigned g = (unsigned)((S.n + 255) / 256);
-  hipLaunchKernelGGL(k_pairs_count, dim3(g), dim3(256), 0, st, S, px, cnt, nbr, stride,
+  hipLaunchKernelGGL(k_pairs_count, dim3(g), dim3(256), 0, st, S, xs, ri, origs, cnt, nbr, stride,
                      contacts_only, counts);
   hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(TILE), 0, st, counts, (int64_t)S.n, offsets,
                      total);
   if (pairs)
-    hipLaunchKernelGGL(k_pairs_write, dim3(g), dim3(256), 0, st, S, px, cnt, nbr, stride,
+    hipLaunchKernelGGL(k_pairs_write, dim3(g), dim3(256), 0, st, S, xs, ri, origs, cnt, nbr, stride,
                        contacts_only, offsets, cap, pairs, delta);
   return hipGetLastError();
 }
 
 hipError_t launch_posq(const SysDev *sys, const int32_t *tile_sys, const int32_t *rrange, int n_sys,
-                       const PX *px, uint64_t *posq, int64_t n, hipStream_t st) {
+                       const X3 *xs, const float2 *ri, uint64_t *posq, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_posq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sys, tile_sys,
-                     rrange, n_sys, px, posq, n);
+                     rrange, n_sys, xs, ri, posq, n);
   return hipGetLastError();
 }
 
