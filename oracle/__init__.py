@@ -27,7 +27,7 @@ class Params(ctypes.Structure):
         ("check_superset", ctypes.c_int32),
         ("validity_uses_uncapped_skin", ctypes.c_int32),
         ("v_in_is_half_step", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("state_fp32", ctypes.c_int32),
         ("K", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("cell_size", ctypes.c_double),
@@ -104,6 +104,7 @@ def make_params(p: dict) -> Params:
     q.check_superset = int(p.get("check_superset", 0))
     q.validity_uses_uncapped_skin = int(p.get("validity_uses_uncapped_skin", 0))
     q.v_in_is_half_step = int(p.get("v_in_is_half_step", 0))
+    q.state_fp32 = int(p.get("state_fp32", 0))
     for k in ("K", "dt", "cell_size", "skin_uniform", "eps", "kn", "gamma_n", "kt", "gamma_t", "mu"):
         setattr(q, k, float(p.get(k, 0.0)))
     for k in ("lo", "hi", "g"):

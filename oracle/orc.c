@@ -525,6 +525,11 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
         x[3 * i + a] = x[3 * i + a] + p->dt * vh[3 * i + a];
       }
       ke += 0.5 * (vfull[0] * vfull[0] + vfull[1] * vfull[1] + vfull[2] * vfull[2]) / invm[i];
+      if (p->state_fp32)
+        for (int a = 0; a < 3; a++) {
+          x[3 * i + a] = (double)(float)x[3 * i + a];
+          vh[3 * i + a] = (double)(float)vh[3 * i + a];
+        }
     }
     /* 6. displacement test for the next step */
     int64_t viol = 0;

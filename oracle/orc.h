@@ -45,7 +45,8 @@ typedef struct {
   int32_t validity_uses_uncapped_skin; /* planted mistake for a negative test; 0 normally    */
   int32_t v_in_is_half_step; /* 1: v_in is a half-step velocity v^{n-1/2} (a resumed run): */
                              /*    the first step applies both half kicks                  */
-  int32_t pad_;
+  int32_t state_fp32;      /* 1: positions and velocities are rounded to FP32 after every     */
+                           /*    step (a variant for the precision test; 0 normally)         */
   double K, dt, cell_size, skin_uniform, eps;
   double lo[3], hi[3];     /* box; a planar wall on each of the six faces                     */
   double kn, gamma_n;      /* normal linear spring-dashpot                                    */

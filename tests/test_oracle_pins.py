@@ -324,6 +324,33 @@ def test_list_pairs_record_is_the_list_in_use(orc):
     assert h["rebuilt"][changed].all()
 
 
+# ---------------------------------------------------------------- precision of the state
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fp32_state_misses_the_parity_bar(orc, seed):
+    """Why positions and velocities are kept in FP64: the paper fixes no
+    precision, and the parity bar of this build is 1e-5 box units in position and
+    1e-5 v_max in velocity after the run.  Storing the state in FP32 between
+    steps (the FP32 record layout of a 16-byte position and a 16-byte velocity),
+    even with every step computed in FP64, puts M1's velocities some 4e-3 v_max
+    away from the FP64 run after its 200 steps, 400 times the bar: a contact
+    overlap is a few 1e-5 box units, so an FP32 position (one ulp is 6e-8 near
+    0.5) moves each contact force by about a thousandth.  The positions drift by
+    some 5e-8 per step (the rounding of x + dt v) and leave the bar soon after
+    step 200; the contact counts part by then too."""
+    s = synth.config_systems("M1", seed=seed)[0]
+    x, v, rc, invm = arrays(s)
+    a = orc.run(s.params, x, v, rc, invm, 200)
+    b = orc.run(dict(s.params, state_fp32=1), x, v, rc, invm, 200)
+    ev = np.abs(a[1] - b[1]).max() / s.meta["v_max"]
+    ex = np.abs(a[0] - b[0]).max()
+    assert ev > 100 * 1e-5, ev
+    assert 1e-6 < ex < 1e-5, ex
+    a = orc.run(s.params, x, v, rc, invm, 300)
+    b = orc.run(dict(s.params, state_fp32=1), x, v, rc, invm, 300)
+    assert np.abs(a[0] - b[0]).max() > 1e-5
+    assert not np.array_equal(a[2]["contacts"], b[2]["contacts"])
+
+
 # ---------------------------------------------------------------- fixed interval, capped skin (R4)
 def _two_body(v_b, gap, p_extra):
     """Particle A at rest, particle B approaching it along x."""
