@@ -51,11 +51,10 @@ HBM_PEAK_GBS = 8000.0
 #  - FP64: the same with the FP64 state this library keeps (parity needs it):
 #    read x and v (48 B), R_C and 1/m (8), x0 and R_NL (16), row length (4);
 #    write x and v (48).
-#  - KERNEL: what the step kernel's records move: read the position record
-#    (32 B: x, R_C, original index), the velocity record (32: v, 1/m), x0 and
-#    R_NL (16) and the row length (4); write both records (64) and the coded
-#    position the next step's pre-test gathers (8).
-STEP_BYTES = {"alg": 84, "fp64": 124, "kernel": 156}
+#  - KERNEL: what the step kernel's own accesses move: read x and v (48 B),
+#    (R_C, 1/m) (8), x0 and R_NL (16) and the row length (4); write x and v (48)
+#    and the coded position the next step's pre-test gathers (8).
+STEP_BYTES = {"alg": 84, "fp64": 124, "kernel": 132}
 STEP_BYTES_PER_ENTRY = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_M2_traffic.json")
 
