@@ -191,12 +191,19 @@ CONFIGS = {
 }
 
 
-def _gravity_scale(a: float, dt: float) -> float:
-    """Gravity for the gravity-driven stand-ins: 4e-6 a/dt^2.  Under it a
-    particle's weight compresses one contact by about 0.002 a (kn = 1e5, m = 1),
-    so a column of 50 particles stays within 0.1 a; and a particle falling for
-    500 steps reaches v_max."""
-    return 4e-6 * a / (dt * dt)
+STATIC_OVERLAP = 0.01  # largest static overlap under gravity, in units of the smallest R_C
+
+
+def _gravity_for_depth(kn: float, depth: int, r_min: float, m_max: float = 1.0) -> float:
+    """Gravity of the gravity-driven stand-ins: the largest under which a column of
+    `depth` particles compresses its lowest contact by at most STATIC_OVERLAP
+    times the smallest radius.  That contact carries at most the column's weight
+    depth m_max g, which compresses a linear spring of stiffness kn by
+    depth m_max g / kn (walls carrying part of the weight only lower it).  With
+    dt = t_c / 50 fixed by the contact, this is the one free ratio of the
+    contact law to gravity: a stiffer spring at the same dt is the same run in
+    other units."""
+    return STATIC_OVERLAP * r_min * kn / (depth * m_max)
 
 
 def hopper_system(n_target: int, seed: int, alpha_deg: float = 30.0, outlet: int = 8,
@@ -247,7 +254,8 @@ def hopper_system(n_target: int, seed: int, alpha_deg: float = 30.0, outlet: int
     phys = physics_constants(a)
     v_max = phys["v_max"]
     vel = rng.normal(0.0, sigma * v_max, size=(n, 3))
-    g0 = _gravity_scale(a, phys["dt"])
+    # the tallest column: the box height in lattice sites (bin, fill, headroom)
+    g0 = _gravity_for_depth(phys["kn"], nz, rad.min(), mass.max())
     ca, sa = np.cos(np.radians(alpha_deg)), np.sin(np.radians(alpha_deg))
     planes = [  # (n, d, z_min): left wall (normal to +x and up), right wall
         (_f32(ca), 0.0, _f32(sa), float(np.float32((xc - 0.5 * outlet * a) * ca + z_o * sa)), _f32(z_o)),
@@ -258,7 +266,8 @@ def hopper_system(n_target: int, seed: int, alpha_deg: float = 30.0, outlet: int
     return _system(pos, rad, mass, vel, a, phys, (nx + 1) * a, (ny + 1) * a, (nz + 1) * a,
                    (0.0, 0.0, -g0), planes, K, cell_factor, eps,
                    {"kind": "hopper", "alpha_deg": alpha_deg, "outlet_sites": outlet,
-                    "layers": k, "seed": seed, "v_max": v_max, "a": a})
+                    "layers": k, "depth": nz, "seed": seed, "v_max": v_max, "a": a,
+                    "static_overlap_bound": STATIC_OVERLAP * float(rad.min())})
 
 
 def incline_system(n_target: int, seed: int, theta_deg: float = 25.0,
@@ -285,12 +294,13 @@ def incline_system(n_target: int, seed: int, theta_deg: float = 25.0,
     phys = physics_constants(a)
     v_max = phys["v_max"]
     vel = rng.normal(0.0, sigma * v_max, size=(n, 3))
-    g0 = _gravity_scale(a, phys["dt"])
     th = np.radians(theta_deg)
+    # the slab's weight along the floor normal, g cos(theta), bounded as for a column
+    g0 = _gravity_for_depth(phys["kn"], nz, rad.min(), mass.max()) / np.cos(th)
     return _system(pos, rad, mass, vel, a, phys, (lx + 1) * a, (ny + 1) * a, (3 * nz + 1) * a,
                    (g0 * np.sin(th), 0.0, -g0 * np.cos(th)), [], K, cell_factor, eps,
                    {"kind": "incline", "theta_deg": theta_deg, "seed": seed, "v_max": v_max,
-                    "a": a})
+                    "a": a, "depth": nz, "static_overlap_bound": STATIC_OVERLAP * float(rad.min())})
 
 
 def _system(pos, rad, mass, vel, a, phys, hx, hy, hz, gravity, planes, K, cell_factor, eps, meta):

@@ -324,6 +324,74 @@ def test_list_pairs_record_is_the_list_in_use(orc):
     assert h["rebuilt"][changed].all()
 
 
+# ---------------------------------------------------------------- gravity stand-ins (Sec. 5.2)
+def test_gravity_stand_in_static_overlap_is_one_percent():
+    """The gravity of the hopper and incline stand-ins comes from their column
+    depth: a column of `depth` particles of the heaviest mass resting on one
+    contact of stiffness kn compresses it by depth m g / kn (the closed form of
+    a linear spring under a static load, Sec. 5.1's linear spring-dashpot), and
+    that is at most 1 % of the smallest R_C."""
+    for s in (synth.hopper_system(2000, 5), synth.config_systems("H125")[0],
+              synth.config_systems("H500")[0], synth.config_systems("INCLINE")[0]):
+        g = np.linalg.norm(s.params["g"])
+        if s.meta["kind"] == "incline":
+            g *= np.cos(np.radians(s.meta["theta_deg"]))  # the load along the floor normal
+        m_max = 1.0 / s.vel_m[:, 3].min()
+        overlap = s.meta["depth"] * m_max * g / s.params["kn"]
+        assert overlap <= 0.01 * s.pos_r[:, 3].min() * (1 + 1e-6), (s.meta["kind"], s.n)
+
+
+def test_stack_at_the_stand_in_gravity_rests_at_its_static_overlaps(orc):
+    """A vertical stack of `depth` particles of the reduced hopper's smallest
+    radius and heaviest mass, placed at the static overlaps of a linear spring
+    under gravity (the contact below particle k carries the weight of the
+    particles from k up), stays at rest over 2,000 steps, and its lowest contact
+    (against the floor) is compressed by at most 1 % of R_C."""
+    h = synth.hopper_system(2000, 5)
+    D, R, m = h.meta["depth"], float(h.pos_r[:, 3].min()), float(1.0 / h.vel_m[:, 3].min())
+    g, kn = -h.params["g"][2], h.params["kn"]
+    z = np.empty(D)
+    z[0] = R - D * m * g / kn
+    for k in range(1, D):
+        z[k] = z[k - 1] + 2 * R - (D - k) * m * g / kn
+    x = np.stack([np.full(D, 0.5), np.full(D, 0.5), z], axis=1)
+    p = dict(h.params, planes=[])
+    p["hi"] = (1.0, 1.0, float(z[-1] + 2.0))
+    xo, vo, hist, _ = orc.run(p, x, np.zeros((D, 3)), np.full(D, R), np.full(D, 1.0 / m), 2000)
+    assert np.abs(xo - x).max() < 1e-12 and np.abs(vo).max() < 1e-9
+    assert (hist["contacts"] == D - 1).all()
+    assert R - xo[0, 2] <= 0.01 * R * (1 + 1e-6)
+
+
+def test_hopper_stand_in_over_the_paper_run_length(orc):
+    """The reduced hopper over 5,000 steps, the paper's shortest run (Sec. 5.1):
+    no collapse under gravity.  Sampled every 250 steps, every overlap (pairs,
+    box faces and hopper walls) stays below 8 % of the smallest R_C (impacts at
+    the speeds gravity reaches; the static load alone gives 1 %), no cell of
+    edge L_C holds more than 16 particles, and particles leave through the
+    outlet into the collection bin."""
+    s = synth.hopper_system(2000, 5)
+    x, v, rc, invm = arrays(s)
+    lo, hi, L = np.array(s.params["lo"]), np.array(s.params["hi"]), s.params["cell_size"]
+    z_outlet = s.params["planes"][0][4]
+    worst, fullest = 0.0, 0
+    for c in range(20):
+        x, v, h, _ = orc.run(dict(s.params, v_in_is_half_step=int(c > 0)), x, v, rc, invm, 250)
+        pr = orc.contacts_brute(x, rc)
+        if len(pr):
+            worst = max(worst, (rc[pr[:, 0]] + rc[pr[:, 1]]
+                                - np.linalg.norm(x[pr[:, 0]] - x[pr[:, 1]], axis=1)).max())
+        worst = max(worst, np.maximum(rc[:, None] - (x - lo), rc[:, None] - (hi - x)).max())
+        for pl in s.params["planes"]:
+            above = x[:, 2] > pl[4]
+            worst = max(worst, (rc[above] - (x[above] @ np.array(pl[:3]) - pl[3])).max())
+        fullest = max(fullest, np.unique(np.floor((x - lo) / L).astype(int), axis=0,
+                                         return_counts=True)[1].max())
+    assert worst < 0.08 * rc.min(), worst / rc.min()
+    assert fullest <= 16
+    assert (x[:, 2] < z_outlet).sum() > 10
+
+
 # ---------------------------------------------------------------- precision of the state
 @pytest.mark.parametrize("seed", [0, 1])
 def test_fp32_state_misses_the_parity_bar(orc, seed):
