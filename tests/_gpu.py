@@ -69,3 +69,18 @@ def gpu_trajectory(systems, steps, **overrides):
         hist = g.run(steps)
         x, v, half = g.state()
     return x, v, hist
+
+
+def oracle_digest(args, steps):
+    """The oracle on one lattice system, built from its generator arguments in the
+    calling process (a worker of a process pool): SHA-256 of its final FP64
+    positions and velocities, and its contact and broad-phase records."""
+    import hashlib
+
+    import oracle
+    import synth
+    s = synth.lattice_system(*args)
+    x, v, rc, invm = host_arrays([s])
+    xo, vo, ho, _ = oracle.run(s.params, x, v, rc, invm, steps)
+    return (hashlib.sha256(xo.tobytes()).hexdigest(), hashlib.sha256(vo.tobytes()).hexdigest(),
+            ho["contacts"].copy(), ho["rebuilt"].copy())

@@ -54,6 +54,26 @@ def test_m2_full_size_parity_with_oracle(m2):
     assert np.allclose(hg[0]["kinetic_energy"], ho["kinetic_energy"], rtol=1e-9, atol=0)
 
 
+def test_m2_full_size_friction_parity_with_oracle(m2):
+    """M2 with the tangential friction bench.py --friction 0.4 times (kt = kn/2,
+    gamma_t = gamma_n/2, mu = 0.4), 100 steps, every particle against the
+    oracle, bit for bit, with its contact count at every step."""
+    s = m2
+    fr = {"kt": 0.5 * s.params["kn"], "gamma_t": 0.5 * s.params["gamma_n"], "mu": 0.4}
+    say(f"M2 with friction: N={s.n}, {STEPS} steps, GPU then oracle")
+    xg, vg, hg = gpu_trajectory([s], STEPS, **fr)
+    x, v, rc, invm = host_arrays([s])
+    xo, vo, ho, _ = oracle.run(dict(s.params, **fr), x, v, rc, invm, STEPS)
+    ex = np.abs(xg - xo).max()
+    ev = np.abs(vg - vo).max() / s.meta["v_max"]
+    say(f"  max|dx| = {ex:.3e}, max|dv| = {ev:.3e} v_max, contacts at the last step "
+        f"{int(ho['contacts'][-1])}")
+    assert ex <= TOL_X and ev <= TOL_V
+    assert np.array_equal(xg, xo) and np.array_equal(vg, vo)
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert ho["contacts"][-1] > 10000
+
+
 def test_m2_full_size_k_invariance_bitwise(m2):
     """K = 200 against the broad phase at every step: identical bits (Sec. 4.2)."""
     s = m2
@@ -96,24 +116,37 @@ def test_m3_batch_parity_with_oracle():
     assert hg["contacts"][:, -1].sum() > 0
 
 
-def test_m5_sampled_parity_with_oracle():
+def test_m5_every_system_bitwise_with_oracle():
     """The largest workload, 16 systems of 512x512x64 (268M particles) in one
-    batch: the first and the last system (16.8M particles each) are compared with
-    the oracle, every particle of them."""
+    batch, in the launch configuration bench.py times: every system against the
+    oracle, which runs them in parallel processes on the host.  Each compares the
+    SHA-256 of the FP64 positions and velocities (bit-for-bit equality of all
+    268M particles) and the contact count of every step."""
+    import hashlib
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    from synth.systems import _lattice_args
+    from tests._gpu import oracle_digest
+    args = _lattice_args("M5", 0, 1.0)
     systems = synth.config_systems("M5", seed=0, workers=16)
     steps = 10
-    say(f"M5: {len(systems)} systems, N={sum(s.n for s in systems)}, {steps} steps")
+    say(f"M5: {len(systems)} systems, N={sum(s.n for s in systems)}, {steps} steps on the GPU")
     xg, vg, hg = gpu_trajectory(systems, steps)
     sl = _slices(systems)
-    for i in (0, len(systems) - 1):
-        s = systems[i]
-        xo, vo, ho, _ = _oracle_system(s, steps)
-        ex = np.abs(xg[sl[i]] - xo).max()
-        ev = np.abs(vg[sl[i]] - vo).max() / s.meta["v_max"]
-        say(f"  system {i}: max|dx| = {ex:.3e}, max|dv| = {ev:.3e} v_max")
-        assert ex <= TOL_X and ev <= TOL_V
-        assert np.array_equal(xg[sl[i]], xo) and np.array_equal(vg[sl[i]], vo)
-        assert np.array_equal(hg[i]["contacts"], ho["contacts"])
+    gpu = [(hashlib.sha256(np.ascontiguousarray(xg[sl[i]]).tobytes()).hexdigest(),
+            hashlib.sha256(np.ascontiguousarray(vg[sl[i]]).tobytes()).hexdigest())
+           for i in range(len(systems))]
+    del xg, vg, systems
+    say("  oracle on every system, 16 processes")
+    # spawned workers: this process has initialised the GPU, the workers use none
+    with ProcessPoolExecutor(max_workers=16, mp_context=multiprocessing.get_context("spawn")) as ex:
+        ref = list(ex.map(oracle_digest, args, [steps] * len(args)))
+    for i, (hx, hv, con, reb) in enumerate(ref):
+        say(f"  system {i}: positions {'equal' if hx == gpu[i][0] else 'DIFFER'}, velocities "
+            f"{'equal' if hv == gpu[i][1] else 'DIFFER'}, contacts at the end {int(con[-1])}")
+        assert (hx, hv) == gpu[i], i
+        assert np.array_equal(hg[i]["contacts"], con), i
     assert hg["rebuilt"][:, 0].all()
 
 
