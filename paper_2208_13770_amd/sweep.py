@@ -15,7 +15,10 @@ tuner choose K while the simulation runs (autotune.py).  Every row also says whe
 final state is bit-identical to the run without buffer (Sec. 4.2).  The last
 part is one line in the layout of Tab. summary: the time without buffer, the
 optimum K, its time and improvement, the time and improvement at K = 200, and
-the overhead of K = 200 over the optimum.
+the overhead of K = 200 over the optimum.  Every row also gives its own overhead
+over the optimum (the quantity of Fig. overhead), and with --repeats R the wall
+time is the mean of R runs from the same state, with its standard deviation, so
+that the optimum can be told from the noise.
 """
 import argparse
 import json
@@ -41,25 +44,33 @@ def summary_row(name, t_without, times_by_k):
             "overhead": report.overhead_to_optimum(t_def, t_opt)}
 
 
-def run_case(vb, torch, systems, x, v, rc, invm, steps, overrides):
-    """The same steps twice from the same state: once without instrumentation
-    (the wall time) and once with HIP events on every kernel (the split between
-    broad phase and step kernel)."""
+def run_case(vb, torch, systems, x, v, rc, invm, steps, overrides, repeats=1, call_steps=500):
+    """The same steps from the same state: `repeats` times without
+    instrumentation (the wall times), then once with HIP events on every kernel
+    (the split between broad phase and step kernel).  Steps go to vb_run in calls
+    of at most call_steps."""
     params = [dict(s.params, **overrides) for s in systems]
     ctx = vb.vb_batch_create(params, [s.n for s in systems])
+    walls = []
     try:
-        vb.vb_set_state(ctx, x, v, rc, invm)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hist = vb.vb_run(ctx, steps)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        for r in range(max(1, repeats)):
+            vb.vb_set_state(ctx, x, v, rc, invm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            parts = [vb.vb_run(ctx, min(call_steps, steps - k), want_history=(r == 0))
+                     for k in range(0, steps, call_steps)]
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            if r == 0:
+                hist = np.concatenate(parts, axis=1)
+        wall = walls
         xo = torch.empty_like(x)
         vo = torch.empty_like(v)
         vb.vb_get_state(ctx, xo, vo)
         vb.vb_set_state(ctx, x, v, rc, invm)
         vb.vb_set_timing(ctx, 1)
-        vb.vb_run(ctx, steps, want_history=False)
+        for k in range(0, steps, call_steps):
+            vb.vb_run(ctx, min(call_steps, steps - k), want_history=False)
         pt = vb.vb_phase_times(ctx)
     finally:
         vb.vb_destroy(ctx)
@@ -72,6 +83,9 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--fixed-interval", type=int, default=50)
+    ap.add_argument("--repeats", type=int, default=1,
+                    help="timed runs of every case from the same state (mean and spread)")
+    ap.add_argument("--no-tuner", action="store_true", help="skip the tuned-K row")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -92,12 +106,16 @@ def main(argv=None):
                {"skin_mode": vb.VB_FIXED_INTERVAL, "fixed_interval": args.fixed_interval})]
     rows, ref = [], None
     for name, ov in cases:
-        wall, hist, pt, xo, vo = run_case(vb, torch, systems, x, v, rc, invm, args.steps, ov)
+        walls, hist, pt, xo, vo = run_case(vb, torch, systems, x, v, rc, invm, args.steps, ov,
+                                           repeats=args.repeats)
+        wall = float(np.mean(walls))
         if ref is None:
             ref = (wall, xo, vo, hist)
         exact = bool(torch.equal(xo, ref[1]) and torch.equal(vo, ref[2]))
         n_bp = int(hist["rebuilt"].sum())
         row = {"case": name, "K": ov.get("K"), "time_ms": wall * 1e3,
+               "time_ms_std": float(np.std(walls, ddof=1)) * 1e3 if len(walls) > 1 else 0.0,
+               "runs": len(walls),
                "broad_phase_ms": pt["ms_rebuild"], "step_kernel_ms": pt["ms_step"],
                "broad_phases": n_bp,
                "executed_pct": report.executed_fraction(n_bp, args.steps * len(systems)),
@@ -106,7 +124,24 @@ def main(argv=None):
                "contacts_equal": bool(np.array_equal(hist["contacts"], ref[3]["contacts"]))}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
-    # K chosen at run time, windows of about 1/20 of the run (no instrumentation)
+    times = {r["K"]: r["time_ms"] / 1e3 for r in rows if r["K"] is not None}
+    t_opt = min(times.values())
+    for r in rows:  # Fig. overhead: each case's extra time over the optimum K, in % of its own
+        r["overhead_to_opt_pct"] = report.overhead_to_optimum(r["time_ms"] / 1e3, t_opt)
+    if not args.no_tuner:
+        rows.append(tuned_row(vb, torch, systems, x, v, rc, invm, args.steps, ref))
+    out = {"workload": args.workload, "particles": n, "systems": len(systems),
+           "steps": args.steps, "repeats": args.repeats, "rows": rows,
+           "summary": summary_row(args.workload, ref[0], times)}
+    text = json.dumps(out, indent=1)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+
+
+def tuned_row(vb, torch, systems, x, v, rc, invm, steps, ref):
+    """K chosen at run time, windows of about 1/20 of the run (no instrumentation)."""
     params = [dict(s.params) for s in systems]
     ctx = vb.vb_batch_create(params, [s.n for s in systems])
     rebuilds = []
@@ -117,9 +152,9 @@ def main(argv=None):
             vb, ctx, on_records=lambda h: rebuilds.append(int(h["rebuilt"].any(axis=0).sum())))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        windows, k_auto = autotune.tune(run_window, args.steps, K0=K_DEFAULT,
-                                        window=max(10, args.steps // 20),
-                                        exploit=max(40, args.steps // 4))
+        windows, k_auto = autotune.tune(run_window, steps, K0=K_DEFAULT,
+                                        window=max(10, steps // 20),
+                                        exploit=max(40, steps // 4))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         xo = torch.empty_like(x)
@@ -130,21 +165,12 @@ def main(argv=None):
     row = {"case": "auto (tuned K)", "K": None, "K_final": k_auto, "time_ms": wall * 1e3,
            "broad_phase_ms": None, "step_kernel_ms": None,
            "broad_phases": sum(rebuilds),
-           "executed_pct": report.executed_fraction(sum(rebuilds), args.steps),
+           "executed_pct": report.executed_fraction(sum(rebuilds), steps),
            "impr_pct": report.improvement(ref[0], wall),
            "identical_to_no_buffer": bool(torch.equal(xo, ref[1]) and torch.equal(vo, ref[2])),
            "contacts_equal": None, "windows": [[k, s_, t] for k, s_, t in windows]}
-    rows.append(row)
     print(json.dumps({k: v_ for k, v_ in row.items() if k != "windows"}), file=sys.stderr, flush=True)
-    times = {r["K"]: r["time_ms"] / 1e3 for r in rows if r["K"] is not None}
-    out = {"workload": args.workload, "particles": n, "systems": len(systems),
-           "steps": args.steps, "rows": rows,
-           "summary": summary_row(args.workload, ref[0], times)}
-    text = json.dumps(out, indent=1)
-    if args.out:
-        with open(args.out, "w") as f:
-            f.write(text + "\n")
-    print(text, flush=True)
+    return row
 
 
 if __name__ == "__main__":
