@@ -26,8 +26,9 @@ Prints ONE JSON line:
               the 8 TB/s HBM peak;
   plain       the same steps with the broad phase at every step ("without Verlet
               buffer"), and Eq. impr between the two;
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload, one core,
-              with the host's CPU model and core count.
+  cpu_baseline the FP64 oracle on a bounded sample of the same workload on the host's
+              cores (and, beside it, on one thread), with the host's CPU model and
+              core count.
 """
 import argparse
 import json
@@ -137,13 +138,16 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(system, steps):
-    """The FP64 oracle on the first `steps` steps of the workload, one thread."""
+def cpu_baseline(system, steps, threads=1):
+    """The FP64 oracle on the first `steps` steps of the workload, on `threads`
+    host threads (its results do not depend on the count)."""
     import oracle
     pos, vel = system.pos_r.astype(np.float64), system.vel_m.astype(np.float64)
+    oracle.set_threads(threads)
     t0 = time.perf_counter()
     oracle.run(system.params, pos[:, :3], vel[:, :3], pos[:, 3], vel[:, 3], steps)
     dt = time.perf_counter() - t0
+    oracle.set_threads(1)
     return system.n * steps / dt / 1e6, dt
 
 
@@ -173,7 +177,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="M2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=120,
-                    help="steps of the oracle on the same workload (CPU baseline, M2 only)")
+                    help="steps of the single-thread oracle on the same workload (M2 only)")
+    ap.add_argument("--cpu-steps-all", type=int, default=200,
+                    help="steps of the oracle on every host core (the CPU baseline, M2 only)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--sequential", action="store_true",
@@ -276,12 +282,19 @@ def main():
 
     cpu = None
     if args.workload == "M2" and args.friction == 0 and not args.no_cpu and args.cpu_steps > 0:
-        v_cpu, dt_cpu = cpu_baseline(systems[0], args.cpu_steps)
-        cpu = {"value": v_cpu, "unit": "Mparticle*step/s", "cores": 1, "kind": "oracle",
-               "sample": f"M2 workload ({n} particles), first {args.cpu_steps} steps, K=200, "
-                         f"FP64 oracle, single thread, {dt_cpu:.1f} s",
+        # on the host's cores (os.cpu_count() is this host's share, capped at 16), and
+        # on one thread; the same FP64 oracle as the tests use, untuned
+        threads = min(16, os.cpu_count() or 1)
+        v_all, dt_all = cpu_baseline(systems[0], args.cpu_steps_all, threads)
+        v_one, dt_one = cpu_baseline(systems[0], args.cpu_steps, 1)
+        cpu = {"value": v_all, "unit": "Mparticle*step/s", "cores": threads, "kind": "oracle",
+               "sample": f"M2 workload ({n} particles), first {args.cpu_steps_all} steps, K=200, "
+                         f"FP64 oracle on {threads} threads, {dt_all:.1f} s",
+               "single_thread": {"value": v_one, "cores": 1,
+                                 "sample": f"first {args.cpu_steps} steps, {dt_one:.1f} s"},
                "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
-        log(f"cpu oracle: {v_cpu:.3f} Mparticle*step/s ({dt_cpu:.1f} s)")
+        log(f"cpu oracle: {v_all:.3f} Mparticle*step/s on {threads} threads ({dt_all:.1f} s), "
+            f"{v_one:.3f} on one ({dt_one:.1f} s)")
 
     traffic = (measured_traffic()
                if args.workload == "M2" and args.scale == 1.0 and args.friction == 0 else None)

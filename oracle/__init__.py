@@ -75,11 +75,24 @@ def lib():
         L.orc_rebuild_radii.argtypes = [ctypes.POINTER(Params), i64, dp, dp, dp, dp]
         L.orc_forces.restype = ctypes.c_int
         L.orc_forces.argtypes = [ctypes.POINTER(Params), i64, dp, dp, dp, i64, ip, dp]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
+        L.orc_get_threads.argtypes = []
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.POINTER(Params), i64, dp, dp, dp, dp, i32, dp, dp, dp,
                               ip, i64, ctypes.POINTER(ctypes.c_int64)]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads the oracle's loops over particles use (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def _d(a, shape=None):

@@ -16,7 +16,7 @@ MUT = [
  ("validity >=", "if (disp > skin_test[i]) viol++;", "if (disp >= skin_test[i]) viol++;"),
  ("skip same cell", "if (cb == ca && pb >= pa) continue;", "if (cb == ca) continue;"),
  ("hi wall sign", "if (dhi > 0.0) f[ax] -= p->kn * dhi - p->gamma_n * (-vi[ax]);", "if (dhi > 0.0) f[ax] += p->kn * dhi - p->gamma_n * (-vi[ax]);"),
- ("contact >=", "if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(&C, i, j);", "if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) >= 0.0) pv_push(&C, i, j);"),
+ ("contact >=", "if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(Ct, i, j);", "if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) >= 0.0) pv_push(Ct, i, j);"),
  ("drift with vfull", "x[3 * i + a] = x[3 * i + a] + p->dt * vh[3 * i + a];", "x[3 * i + a] = x[3 * i + a] + p->dt * vfull[a];"),
  ("x0 not refreshed", "memcpy(x0, x, n3 * sizeof(double));", ";"),
  ("damping uses vi only", "double vn = (vi[0] - vj[0]) * nrm[0] + (vi[1] - vj[1]) * nrm[1] + (vi[2] - vj[2]) * nrm[2];", "double vn = (vi[0]) * nrm[0] + (vi[1]) * nrm[1] + (vi[2]) * nrm[2];"),
@@ -34,8 +34,8 @@ MUT = [
  ("friction history dropped", "          for (int c = 0; c < 3; c++) s[c] = old->xi[3 * h + c];", "          ;"),
  ("friction tangent not projected", "          s[c] = (s[c] - sn * nrm[c]) + vt[c] * p->dt;", "          s[c] = s[c] + vt[c] * p->dt;"),
  ("plane damping sign", "double fm = p->kn * delta - p->gamma_n * vn;\n        f[0] += fm * pl[0];", "double fm = p->kn * delta + p->gamma_n * vn;\n        f[0] += fm * pl[0];"),
- ("kinetic energy of the half-step velocity", "ke += 0.5 * (vfull[0] * vfull[0] + vfull[1] * vfull[1] + vfull[2] * vfull[2]) / invm[i];", "ke += 0.5 * (vh[3 * i] * vh[3 * i] + vh[3 * i + 1] * vh[3 * i + 1] + vh[3 * i + 2] * vh[3 * i + 2]) / invm[i];"),
- ("kinetic energy without 1/2", "ke += 0.5 * (vfull[0] * vfull[0]", "ke += (vfull[0] * vfull[0]"),
+ ("kinetic energy of the half-step velocity", "kin[i] = 0.5 * (vfull[0] * vfull[0] + vfull[1] * vfull[1] + vfull[2] * vfull[2]) / invm[i];", "kin[i] = 0.5 * (vh[3 * i] * vh[3 * i] + vh[3 * i + 1] * vh[3 * i + 1] + vh[3 * i + 2] * vh[3 * i + 2]) / invm[i];"),
+ ("kinetic energy without 1/2", "kin[i] = 0.5 * (vfull[0] * vfull[0]", "kin[i] = (vfull[0] * vfull[0]"),
  ("max_excess without the skin", "double excess = disp - skin_test[i];", "double excess = disp;"),
  ("list_pairs as contact count", "r->list_pairs = p->skin_mode == ORC_NAIVE ? 0 : list_pairs;", "r->list_pairs = p->skin_mode == ORC_NAIVE ? 0 : C.n;"),
  ("violators off by one", "if (disp > skin_test[i]) viol++;", "if (disp > skin_test[i]) viol += 2;"),

@@ -39,6 +39,21 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads.  Loops over particles whose iterations are independent may run on
+ * several threads; every result is the same as on one thread, bit for bit:
+ * each iteration writes only its own particle, a list is built as pieces of
+ * consecutive iterations joined in iteration order (or sorted afterwards),
+ * maxima and counts are order-free, and the one sum (the kinetic energy) is
+ * taken in particle order on one thread. */
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+
+int orc_get_threads(void) { return g_threads; }
 
 /* ------------------------------------------------------------------ helpers */
 
@@ -78,6 +93,15 @@ static void pv_push(pairvec *v, int32_t i, int32_t j) {
   v->p[2 * v->n] = i;
   v->p[2 * v->n + 1] = j;
   v->n++;
+}
+
+/* Appends the pieces a[0..np) to v in order and frees them. */
+static void pv_join(pairvec *v, pairvec *a, int np) {
+  for (int t = 0; t < np; t++) {
+    if (a[t].oom) v->oom = 1;
+    for (int64_t k = 0; k < a[t].n; k++) pv_push(v, a[t].p[2 * k], a[t].p[2 * k + 1]);
+    free(a[t].p);
+  }
 }
 
 static int64_t pv_export(const pairvec *v, int32_t *out, int64_t cap) {
@@ -149,9 +173,21 @@ static int broad_linked_cell(int64_t n, const double *x, const double *r, double
   /* members of each cell in ascending particle index */
   for (int64_t i = 0; i < n; i++) member[start[cell[i]] + fill[cell[i]]++] = i;
 
+  /* every thread collects the pairs of its own cells; the list is sorted below */
+  pairvec *part = (pairvec *)calloc((size_t)g_threads, sizeof(pairvec));
+  if (!part) {
+    free(cell), free(start), free(fill), free(member);
+    return -2;
+  }
+#pragma omp parallel for collapse(2) schedule(dynamic) num_threads(g_threads)
   for (int64_t cz = 0; cz < nc[2]; cz++)
     for (int64_t cy = 0; cy < nc[1]; cy++)
       for (int64_t cx = 0; cx < nc[0]; cx++) {
+#ifdef _OPENMP
+        pairvec *mine = &part[omp_get_thread_num()];
+#else
+        pairvec *mine = &part[0];
+#endif
         int64_t ca = (cz * nc[1] + cy) * nc[0] + cx;
         for (int64_t dz = -ring; dz <= ring; dz++)
           for (int64_t dy = -ring; dy <= ring; dy++)
@@ -168,12 +204,14 @@ static int broad_linked_cell(int64_t n, const double *x, const double *r, double
                   if (cb == ca && pb >= pa) continue; /* same cell: P_b < P_a */
                   if (dist3(x + 3 * pa, x + 3 * pb) <= r[pa] + r[pb] + eps) {
                     int64_t i = pa < pb ? pa : pb, j = pa < pb ? pb : pa;
-                    pv_push(out, (int32_t)i, (int32_t)j);
+                    pv_push(mine, (int32_t)i, (int32_t)j);
                   }
                 }
               }
             }
       }
+  pv_join(out, part, g_threads);
+  free(part);
   free(cell), free(start), free(fill), free(member);
   if (out->oom) return -2;
   qsort(out->p, (size_t)out->n, 2 * sizeof(int32_t), cmp_pair);
@@ -200,9 +238,20 @@ static double overlap(const double *xi, const double *xj, double ri, double rj) 
 /* The contact set by definition: every pair whose overlap exceeds zero (Eq. delta,
  * Sec. 3.2: such a pair collides, one with zero or negative overlap does not). */
 static void contacts_brute(int64_t n, const double *x, const double *rc, pairvec *out) {
-  for (int64_t i = 0; i < n; i++)
-    for (int64_t j = i + 1; j < n; j++)
-      if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(out, (int32_t)i, (int32_t)j);
+  int np = g_threads;
+  pairvec *part = (pairvec *)calloc((size_t)np, sizeof(pairvec));
+  if (!part) {
+    out->oom = 1;
+    return;
+  }
+  /* piece t holds the pairs of the particles i in [t n / np, (t+1) n / np) */
+#pragma omp parallel for schedule(static, 1) num_threads(np)
+  for (int t = 0; t < np; t++)
+    for (int64_t i = t * n / np; i < (t + 1) * n / np; i++)
+      for (int64_t j = i + 1; j < n; j++)
+        if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(&part[t], (int32_t)i, (int32_t)j);
+  pv_join(out, part, np);
+  free(part);
 }
 
 int64_t orc_contacts_brute(int64_t n, const double *x, const double *rc, int32_t *pairs,
@@ -226,6 +275,8 @@ static double cap_of(const orc_params *p) {
 int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const double *rc,
                       double *rnl, double *skin_eff) {
   double cap = cap_of(p);
+  int bad = 0;
+#pragma omp parallel for reduction(|| : bad) num_threads(g_threads)
   for (int64_t i = 0; i < n; i++) {
     double skin;
     switch (p->skin_mode) {
@@ -234,12 +285,12 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
       case ORC_FIXED_INTERVAL: skin = p->skin_uniform; break;
       default: skin = 0.0; break; /* no buffer: R_NL = R_C */
     }
-    if (rc[i] > cap) return -1;
+    if (rc[i] > cap) bad = 1;
     double r = rc[i] + skin;
     rnl[i] = r < cap ? r : cap;
     skin_eff[i] = rnl[i] - rc[i];
   }
-  return 0;
+  return bad ? -1 : 0;
 }
 
 /* --------------------------------------------------------------------- forces */
@@ -286,6 +337,7 @@ static int forces_core(const orc_params *p, int64_t n, const double *x, const do
     adj[deg[i] + fill[i]++] = j;
     adj[deg[j] + fill[j]++] = i;
   }
+#pragma omp parallel for num_threads(g_threads)
   for (int64_t i = 0; i < n; i++) { /* ascending partner order (insertion sort) */
     for (int64_t a = deg[i] + 1; a < deg[i + 1]; a++) {
       int32_t key = adj[a];
@@ -311,6 +363,7 @@ static int forces_core(const orc_params *p, int64_t n, const double *x, const do
     }
     memcpy(neu->off, deg, (size_t)(n + 1) * sizeof(int64_t));
   }
+#pragma omp parallel for num_threads(g_threads)
   for (int64_t i = 0; i < n; i++) {
     const double *xi = x + 3 * i, *vi = v + 3 * i;
     double f[3] = {0.0, 0.0, 0.0};
@@ -440,6 +493,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
   double *rnl = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   double *skin_eff = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   double *skin_test = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  double *kin = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   pairvec L = {0}, C = {0}, B = {0};
   history H[2] = {{0}, {0}};
   const int fric = friction_on(p);
@@ -452,7 +506,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
       goto done;
     }
   }
-  if (!x || !vh || !x0 || !F || !rnl || !skin_eff || !skin_test) {
+  if (!x || !vh || !x0 || !F || !rnl || !skin_eff || !skin_test || !kin) {
     ret = -2;
     goto done;
   }
@@ -490,10 +544,23 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
     if (p->skin_mode == ORC_NAIVE) {
       contacts_brute(n, x, rc, &C);
     } else {
-      for (int64_t k = 0; k < L.n; k++) {
-        int32_t i = L.p[2 * k], j = L.p[2 * k + 1];
-        if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(&C, i, j);
+      /* piece t filters the list entries [t L.n / np, (t+1) L.n / np), joined in order */
+      int np = g_threads;
+      pairvec *part = (pairvec *)calloc((size_t)np, sizeof(pairvec));
+      if (!part) {
+        ret = -2;
+        goto done;
       }
+#pragma omp parallel for schedule(static, 1) num_threads(np)
+      for (int t = 0; t < np; t++) {
+        pairvec *Ct = &part[t];
+        for (int64_t k = t * L.n / np; k < (t + 1) * L.n / np; k++) {
+          int32_t i = L.p[2 * k], j = L.p[2 * k + 1];
+          if (overlap(x + 3 * i, x + 3 * j, rc[i], rc[j]) > 0.0) pv_push(Ct, i, j);
+        }
+      }
+      pv_join(&C, part, np);
+      free(part);
     }
     int64_t missed = 0;
     if (p->check_superset && p->skin_mode != ORC_NAIVE) {
@@ -514,8 +581,8 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
     }
     cur_h ^= 1;
     /* 5. integration */
-    double ke = 0.0;
     double hdt = 0.5 * p->dt;
+#pragma omp parallel for num_threads(g_threads)
     for (int64_t i = 0; i < n; i++) {
       double vfull[3];
       for (int a = 0; a < 3; a++) {
@@ -524,17 +591,20 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
         vh[3 * i + a] = vfull[a] + hdt * acc;
         x[3 * i + a] = x[3 * i + a] + p->dt * vh[3 * i + a];
       }
-      ke += 0.5 * (vfull[0] * vfull[0] + vfull[1] * vfull[1] + vfull[2] * vfull[2]) / invm[i];
+      kin[i] = 0.5 * (vfull[0] * vfull[0] + vfull[1] * vfull[1] + vfull[2] * vfull[2]) / invm[i];
       if (p->state_fp32)
         for (int a = 0; a < 3; a++) {
           x[3 * i + a] = (double)(float)x[3 * i + a];
           vh[3 * i + a] = (double)(float)vh[3 * i + a];
         }
     }
+    double ke = 0.0;
+    for (int64_t i = 0; i < n; i++) ke += kin[i]; /* in particle order */
     /* 6. displacement test for the next step */
     int64_t viol = 0;
     double max_excess = -INFINITY;
     if (p->skin_mode != ORC_NAIVE) {
+#pragma omp parallel for reduction(max : max_excess) reduction(+ : viol) num_threads(g_threads)
       for (int64_t i = 0; i < n; i++) {
         double disp = dist3(x + 3 * i, x0 + 3 * i);
         double excess = disp - skin_test[i];
@@ -566,7 +636,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
     }
   }
 done:
-  free(x), free(vh), free(x0), free(F), free(rnl), free(skin_eff), free(skin_test);
+  free(x), free(vh), free(x0), free(F), free(rnl), free(skin_eff), free(skin_test), free(kin);
   free(L.p), free(C.p), free(B.p);
   for (int b = 0; b < 2; b++) free(H[b].off), free(H[b].j), free(H[b].xi);
   return ret;

@@ -71,6 +71,11 @@ typedef struct {
   double kinetic_energy;   /* sum_p m_p |v^n_p|^2 / 2                                        */
 } orc_record;
 
+/* Threads for the loops over particles (default 1).  Every result is bit-identical
+ * whatever the count. */
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
 /* Broad phase by brute force: every pair i<j with |x_i - x_j| <= r_i + r_j + eps.
  * Writes up to cap pairs (int32 i, j) in lexicographic order; returns the count. */
 int64_t orc_broadphase_brute(int64_t n, const double *x, const double *r, double eps,

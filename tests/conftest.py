@@ -11,6 +11,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD Instinct MI355X")
     config.addinivalue_line("markers", "slow: long CPU test")
+    # the oracle's results do not depend on its thread count: use the host's cores
+    import oracle
+    oracle.set_threads(min(16, os.cpu_count() or 1))
 
 
 @pytest.fixture(scope="session")

@@ -787,3 +787,38 @@ def test_friction_conserves_momentum_and_the_method_stays_exact(orc):
     xm, vm, hm, _ = orc.run(p, x, v, rc, invm, 300)
     assert np.array_equal(xn, xm) and np.array_equal(vn, vm)
     assert np.array_equal(hn["contacts"], hm["contacts"]) and hm["rebuilt"].sum() < 300
+
+
+# ---------------------------------------------------------------- threads
+@pytest.mark.parametrize("case", ["method", "friction", "naive", "hopper"])
+def test_oracle_threads_give_identical_bits(orc, case):
+    """The oracle's loops over particles may run on several threads (for the CPU
+    baseline on all host cores); positions, velocities, every record field and
+    the final list are the same bits on 1, 3 and 8 threads."""
+    if case == "hopper":
+        s = synth.hopper_system(2000, 5)
+        p = dict(s.params)
+    else:
+        s = colliding(11, poly=True)
+        p = dict(s.params, check_superset=1)
+        if case == "friction":
+            p.update(kt=0.5 * p["kn"], gamma_t=0.5 * p["gamma_n"], mu=0.4)
+        if case == "naive":
+            p.update(skin_mode=orc.NAIVE, check_superset=0)
+    x, v, rc, invm = arrays(s)
+    ref = None
+    before = orc.get_threads()
+    try:
+        for t in (1, 3, 8):
+            orc.set_threads(t)
+            out = orc.run(p, x, v, rc, invm, 300, want_list=case != "naive")
+            if ref is None:
+                ref = out
+                assert out[2]["contacts"].sum() > 0
+                continue
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), t
+            assert np.array_equal(out[2], ref[2]), t
+            if case != "naive":
+                assert np.array_equal(out[3], ref[3]), t
+    finally:
+        orc.set_threads(before)
