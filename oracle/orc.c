@@ -50,6 +50,8 @@
  * maxima and counts are order-free, and the one sum (the kinetic energy) is
  * taken in particle order on one thread. */
 static int g_threads = 1;
+/* smallest loop that runs on several threads: below it one thread is faster */
+#define ORC_PAR_MIN 16384
 
 void orc_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
 
@@ -179,7 +181,7 @@ static int broad_linked_cell(int64_t n, const double *x, const double *r, double
     free(cell), free(start), free(fill), free(member);
     return -2;
   }
-#pragma omp parallel for collapse(2) schedule(dynamic) num_threads(g_threads)
+#pragma omp parallel for collapse(2) schedule(dynamic) num_threads(g_threads) if (n >= ORC_PAR_MIN)
   for (int64_t cz = 0; cz < nc[2]; cz++)
     for (int64_t cy = 0; cy < nc[1]; cy++)
       for (int64_t cx = 0; cx < nc[0]; cx++) {
@@ -245,7 +247,7 @@ static void contacts_brute(int64_t n, const double *x, const double *rc, pairvec
     return;
   }
   /* piece t holds the pairs of the particles i in [t n / np, (t+1) n / np) */
-#pragma omp parallel for schedule(static, 1) num_threads(np)
+#pragma omp parallel for schedule(static, 1) num_threads(np) if (n >= 512)
   for (int t = 0; t < np; t++)
     for (int64_t i = t * n / np; i < (t + 1) * n / np; i++)
       for (int64_t j = i + 1; j < n; j++)
@@ -276,7 +278,7 @@ int orc_rebuild_radii(const orc_params *p, int64_t n, const double *v, const dou
                       double *rnl, double *skin_eff) {
   double cap = cap_of(p);
   int bad = 0;
-#pragma omp parallel for reduction(|| : bad) num_threads(g_threads)
+#pragma omp parallel for reduction(|| : bad) num_threads(g_threads) if (n >= ORC_PAR_MIN)
   for (int64_t i = 0; i < n; i++) {
     double skin;
     switch (p->skin_mode) {
@@ -337,7 +339,7 @@ static int forces_core(const orc_params *p, int64_t n, const double *x, const do
     adj[deg[i] + fill[i]++] = j;
     adj[deg[j] + fill[j]++] = i;
   }
-#pragma omp parallel for num_threads(g_threads)
+#pragma omp parallel for num_threads(g_threads) if (n >= ORC_PAR_MIN)
   for (int64_t i = 0; i < n; i++) { /* ascending partner order (insertion sort) */
     for (int64_t a = deg[i] + 1; a < deg[i + 1]; a++) {
       int32_t key = adj[a];
@@ -363,7 +365,7 @@ static int forces_core(const orc_params *p, int64_t n, const double *x, const do
     }
     memcpy(neu->off, deg, (size_t)(n + 1) * sizeof(int64_t));
   }
-#pragma omp parallel for num_threads(g_threads)
+#pragma omp parallel for num_threads(g_threads) if (n >= ORC_PAR_MIN)
   for (int64_t i = 0; i < n; i++) {
     const double *xi = x + 3 * i, *vi = v + 3 * i;
     double f[3] = {0.0, 0.0, 0.0};
@@ -551,7 +553,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
         ret = -2;
         goto done;
       }
-#pragma omp parallel for schedule(static, 1) num_threads(np)
+#pragma omp parallel for schedule(static, 1) num_threads(np) if (L.n >= ORC_PAR_MIN)
       for (int t = 0; t < np; t++) {
         pairvec *Ct = &part[t];
         for (int64_t k = t * L.n / np; k < (t + 1) * L.n / np; k++) {
@@ -582,7 +584,7 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
     cur_h ^= 1;
     /* 5. integration */
     double hdt = 0.5 * p->dt;
-#pragma omp parallel for num_threads(g_threads)
+#pragma omp parallel for num_threads(g_threads) if (n >= ORC_PAR_MIN)
     for (int64_t i = 0; i < n; i++) {
       double vfull[3];
       for (int a = 0; a < 3; a++) {
@@ -604,7 +606,8 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
     int64_t viol = 0;
     double max_excess = -INFINITY;
     if (p->skin_mode != ORC_NAIVE) {
-#pragma omp parallel for reduction(max : max_excess) reduction(+ : viol) num_threads(g_threads)
+#pragma omp parallel for reduction(max : max_excess) reduction(+ : viol) num_threads(g_threads) \
+    if (n >= ORC_PAR_MIN)
       for (int64_t i = 0; i < n; i++) {
         double disp = dist3(x + 3 * i, x0 + 3 * i);
         double excess = disp - skin_test[i];

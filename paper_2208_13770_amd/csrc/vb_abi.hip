@@ -409,6 +409,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   c->lds_cu = std::max(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
   c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144 - pairs_lds_bytes(0, 0)) /
                                                          (PAIRS_T * sizeof(uint16_t)));
+  c->row_limit -= c->row_limit % ROW_GROUP;  // rows are stored in whole groups
   c->n_sys = n_sys;
   c->sys_h.resize(n_sys);
   c->sort_interval = h_params[0].reorder_interval;
@@ -474,6 +475,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     bcap = std::max(bcap, p.bin_capacity > 0 ? p.bin_capacity : 16);
     c->max_n = std::max(c->max_n, S.n);
   }
+  width = (width + ROW_GROUP - 1) / ROW_GROUP * ROW_GROUP;
   if (width > c->row_limit) {
     c->msg = "max_neighbors exceeds " + std::to_string(c->row_limit) + " on this device";
     return bail(VB_EINVAL);

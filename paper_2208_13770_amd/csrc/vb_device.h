@@ -28,6 +28,15 @@ constexpr int MAX_CAND = 32;      // row entries per segment of the step kernel'
 constexpr int CONTACT_UNROLL = 2; // candidates whose records are requested together (4 waves/SIMD)
 constexpr int PAIRS_T = 384;      // threads of a pair-search workgroup (one brick): a brick of
                                   // 64 cells at about 5 particles per cell in one pass
+// Rows of the Verlet list are stored in groups of ROW_GROUP entries: group g of
+// slot k is the int4 at nbr[(g * stride + k) * ROW_GROUP], entry q is component
+// q % ROW_GROUP of group q / ROW_GROUP.  One 16-byte load fetches four entries of
+// a row, and a wave's lanes read one group as 1 KB of consecutive memory.  Row
+// widths are multiples of ROW_GROUP.
+constexpr int ROW_GROUP = 4;
+__host__ __device__ __forceinline__ int64_t row_index(int64_t stride, int64_t k, int q) {
+  return ((int64_t)(q / ROW_GROUP) * stride + k) * ROW_GROUP + (q % ROW_GROUP);
+}
 
 // Position of a slot, 24 B: FP64 centre.  Double-buffered (a step reads one
 // buffer and writes the other).
@@ -113,7 +122,7 @@ struct BroadArgs {
   const uint32_t *orig; // [slots] original index
   float4 *bp;           // [slots] x0 (FP32) and R_NL of the broad phase
   int32_t *cnt;         // [slots] row lengths
-  int32_t *nbr;         // rows, column-major: entry q of slot k at nbr[q * stride + k]
+  int32_t *nbr;         // rows in groups of four entries: entry q of slot k at row_index(stride, k, q)
   int64_t stride;
   int32_t width;        // row capacity W
   int32_t *bin_count;   // [cells] particles binned per cell (zeroed by the step kernel)

@@ -243,6 +243,15 @@ __device__ __forceinline__ float4 nt_load(const float4 *p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ int32_t nt_load(const int32_t *p) { return __builtin_nontemporal_load(p); }
+typedef int vi4_t __attribute__((ext_vector_type(4)));
+// One group of four row entries (16 bytes), non-temporal.
+__device__ __forceinline__ void nt_load_group(const int32_t *p, int32_t *out) {
+  const vi4_t v = __builtin_nontemporal_load(reinterpret_cast<const vi4_t *>(p));
+  out[0] = v.x;
+  out[1] = v.y;
+  out[2] = v.z;
+  out[3] = v.w;
+}
 __device__ __forceinline__ void nt_store(float4 *p, const float4 &v) {
   const vf4_t w = {v.x, v.y, v.z, v.w};
   __builtin_nontemporal_store(w, reinterpret_cast<vf4_t *>(p));
@@ -286,13 +295,25 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   if (active) {
     // the particle's records and the first UNROLL row entries are requested
     // together: entries below the row width are always allocated, and an entry
-    // is used only if it lies below the row length
-    const int32_t *row = a.nbr + k;
+    // is used only if it lies below the row length.  With UNROLL a multiple of
+    // ROW_GROUP the row is read a group (four entries) per load.
     const int64_t st = a.stride;
     const int spec = min(UNROLL, a.width);
     int32_t j[UNROLL];
+    // entries q .. q+UNROLL-1 (q a multiple of UNROLL) that lie below limit
+    auto load_entries = [&](int q, int limit, int32_t *dst) {
+      if constexpr (UNROLL % ROW_GROUP == 0) {
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) j[u] = u < spec ? nt_load(&row[(int64_t)u * st]) : 0;
+        for (int g = 0; g < UNROLL / ROW_GROUP; ++g)
+          if (q + g * ROW_GROUP < limit)
+            nt_load_group(&a.nbr[row_index(st, k, q + g * ROW_GROUP)], dst + g * ROW_GROUP);
+      } else {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+          dst[u] = q + u < limit ? nt_load(&a.nbr[row_index(st, k, q + u)]) : 0;
+      }
+    };
+    load_entries(0, spec, j);
     const X3 me = xs[k];  // plain loads: the flushes of the neighbours gather them too
     const V3 mv = vs[k];
     const float2 mri = a.ri[k];
@@ -392,9 +413,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         for (int u = 0; u < UNROLL; ++u)
           if (q + u < q1) o[u] = a.posq_cur[S.p_off + j[u]];
         int32_t jn[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-          jn[u] = q + UNROLL + u < rowlen ? nt_load(&row[(int64_t)(q + UNROLL + u) * st]) : 0;
+        load_entries(q + UNROLL, rowlen, jn);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
           if (q + u < q1 && posq_candidate(mq, o[u], rlo_q, step_q)) {
@@ -636,22 +655,27 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&key)[N]) {
 template <int N>
 __device__ __forceinline__ void row_write_sorted(const uint16_t *s_row, const int32_t *s_key,
                                                  const int32_t *__restrict__ inv, int n,
-                                                 int32_t *out, int64_t stride) {
+                                                 int32_t *nbr, int64_t stride, int64_t k) {
+  static_assert(N % ROW_GROUP == 0, "whole groups");
   int32_t key[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) key[q] = q < n ? s_key[s_row[q * PAIRS_T + threadIdx.x]] : INT32_MAX;
   bitonic_sort<N>(key);
 #pragma unroll
   for (int q = 0; q < N; ++q) key[q] = q < n ? inv[key[q]] : 0;
+  // whole groups: a group that holds an entry below n lies below the row width
+  // (n <= W and W is a multiple of ROW_GROUP)
 #pragma unroll
-  for (int q = 0; q < N; ++q)
-    if (q < n) out[(int64_t)q * stride] = key[q];
+  for (int g = 0; g < N / ROW_GROUP; ++g)
+    if (g * ROW_GROUP < n)
+      *reinterpret_cast<int4 *>(&nbr[row_index(stride, k, g * ROW_GROUP)]) =
+          make_int4(key[4 * g], key[4 * g + 1], key[4 * g + 2], key[4 * g + 3]);
 }
 
 // The same for a row of any length up to W: insertion sort in LDS.
 __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int32_t *s_key,
-                                                     const int32_t *s_slot, int n, int32_t *out,
-                                                     int64_t stride) {
+                                                     const int32_t *s_slot, int n, int32_t *nbr,
+                                                     int64_t stride, int64_t k) {
   for (int i = 1; i < n; ++i) {
     const int e = s_row[i * PAIRS_T + threadIdx.x];
     const int32_t key = s_key[e];
@@ -664,7 +688,7 @@ __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int3
     }
     s_row[j * PAIRS_T + threadIdx.x] = (uint16_t)e;
   }
-  for (int q = 0; q < n; ++q) out[(int64_t)q * stride] = s_slot[s_row[q * PAIRS_T + threadIdx.x]];
+  for (int q = 0; q < n; ++q) nbr[row_index(stride, k, q)] = s_slot[s_row[q * PAIRS_T + threadIdx.x]];
 }
 
 // The FP32 inclusion test of Alg. 1 on the extended spheres, |x_i - x_j| <=
@@ -842,17 +866,16 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
             }
           count = (int)(wofs / PAIRS_T);
           const int kept = count < W ? count : W;
-          int32_t *out = a.nbr + k;
           // one sort for the whole wave, sized by its longest row (no divergence)
           const int32_t *inv = a.inv + S.p_off;
           if (!__any(kept > 8))
-            row_write_sorted<8>(s_row16, s_key, inv, kept, out, a.stride);
+            row_write_sorted<8>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else if (!__any(kept > 16))
-            row_write_sorted<16>(s_row16, s_key, inv, kept, out, a.stride);
+            row_write_sorted<16>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else if (!__any(kept > 32))
-            row_write_sorted<32>(s_row16, s_key, inv, kept, out, a.stride);
+            row_write_sorted<32>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else
-            row_write_sorted_lds(s_row16, s_key, s_slot, kept, out, a.stride);
+            row_write_sorted_lds(s_row16, s_key, s_slot, kept, a.nbr, a.stride, k);
         } else {
           const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
           const float4 me = a.bins_bp[mybase + i];
@@ -874,7 +897,7 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
               }
           const int kept = count < W ? count : W;
           for (int q = 0; q < kept; ++q)
-            a.nbr[(int64_t)q * a.stride + k] = a.inv[S.p_off + s_row32[q * HALF + tid]];
+            a.nbr[row_index(a.stride, k, q)] = a.inv[S.p_off + s_row32[q * HALF + tid]];
         }
         a.cnt[k] = count < W ? count : W;
         if (count > W) atomicMax(&a.overflow[0], count);
@@ -1260,7 +1283,7 @@ __global__ void k_pairs_count(SysDev S, const X3 *xs, const float2 *ri, const ui
   int c = 0;
   const int len = cnt[k];
   for (int q = 0; q < len; ++q) {
-    const int64_t j = S.p_off + nbr[(int64_t)q * stride + k];
+    const int64_t j = S.p_off + nbr[row_index(stride, k, q)];
     if (origs[j] <= mo) continue;
     if (contacts_only) {
       double dx, dy, dz, d, delta;
@@ -1284,7 +1307,7 @@ __global__ void k_pairs_write(SysDev S, const X3 *xs, const float2 *ri, const ui
   int64_t off = offsets[mo];
   const int len = cnt[k];
   for (int q = 0; q < len; ++q) {
-    const int64_t j = S.p_off + nbr[(int64_t)q * stride + k];
+    const int64_t j = S.p_off + nbr[row_index(stride, k, q)];
     const uint32_t oo = origs[j];
     if (oo <= mo) continue;
     const X3 o = xs[j];

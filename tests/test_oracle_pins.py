@@ -793,25 +793,28 @@ def test_friction_conserves_momentum_and_the_method_stays_exact(orc):
 @pytest.mark.parametrize("case", ["method", "friction", "naive", "hopper"])
 def test_oracle_threads_give_identical_bits(orc, case):
     """The oracle's loops over particles may run on several threads (for the CPU
-    baseline on all host cores); positions, velocities, every record field and
-    the final list are the same bits on 1, 3 and 8 threads."""
+    baseline on all host cores; loops of 16,384 particles or list entries and
+    more, and brute force over 512 particles or more); positions, velocities,
+    every record field and the final list are the same bits on 1, 3 and 8
+    threads."""
     if case == "hopper":
-        s = synth.hopper_system(2000, 5)
+        s = synth.hopper_system(20000, 5)
         p = dict(s.params)
+    elif case == "naive":
+        s = synth.lattice_system(8, 8, 8, 3, 2, 0.3, 11, polydisperse=True)
+        p = dict(s.params, skin_mode=orc.NAIVE)
     else:
-        s = colliding(11, poly=True)
-        p = dict(s.params, check_superset=1)
+        s = synth.config_systems("M1", seed=11)[0]
+        p = dict(s.params)
         if case == "friction":
             p.update(kt=0.5 * p["kn"], gamma_t=0.5 * p["gamma_n"], mu=0.4)
-        if case == "naive":
-            p.update(skin_mode=orc.NAIVE, check_superset=0)
     x, v, rc, invm = arrays(s)
     ref = None
     before = orc.get_threads()
     try:
         for t in (1, 3, 8):
             orc.set_threads(t)
-            out = orc.run(p, x, v, rc, invm, 300, want_list=case != "naive")
+            out = orc.run(p, x, v, rc, invm, 200, want_list=case != "naive")
             if ref is None:
                 ref = out
                 assert out[2]["contacts"].sum() > 0
