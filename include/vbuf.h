@@ -42,9 +42,11 @@
  *     replaying blocks of 64 steps as one captured HIP graph; VBUF_STEP_UNROLL
  *     = 1, 2, 4 or 8 (default 8) sets the partner gathers each thread of the
  *     step kernel keeps in flight; VBUF_XCD_REMAP=1 gives each of the 8 XCDs a
- *     contiguous range of the step kernel's tiles.  Results are bit-identical
- *     for every setting: the FP64 contact law and integration round every
- *     operation (no contraction), in one fixed order.
+ *     contiguous range of the step kernel's tiles.  Either of the two fixes the
+ *     launch shape of the context (vb_set_launch), which vb_tune then does not
+ *     take from its cache.  Results are bit-identical for every setting: the
+ *     FP64 contact law and integration round every operation (no contraction),
+ *     in one fixed order.
  */
 #ifndef VBUF_H
 #define VBUF_H
@@ -267,6 +269,30 @@ vb_status vb_get_pairs(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs
 #define VB_NOALLOC_MAX_N 4194304
 vb_status vb_get_pairs_noalloc(vb_ctx *ctx, int32_t sys, int32_t which, int32_t *d_pairs,
                                double *d_delta, int64_t cap, int64_t *h_n);
+
+/* Launch shape of a context: the partner gathers each thread of the step kernel
+ * keeps in flight (unroll 1, 2, 4 or 8), the step kernel's tile order (xcd_order
+ * 0: launch order, 1: each of the 8 XCDs a contiguous range of tiles) and the
+ * threads of a pair-search workgroup (256, 384 or 512).  Results, records and
+ * the schedule of broad phases do not depend on it (the steps are those of the
+ * time loop of Sec. 3.1 whatever the shape), so it may change between any two
+ * calls.  Errors: VB_EINVAL for a value outside those sets. */
+vb_status vb_set_launch(vb_ctx *ctx, int32_t unroll, int32_t xcd_order, int32_t pairs_threads);
+vb_status vb_get_launch(vb_ctx *ctx, int32_t *h_unroll, int32_t *h_xcd_order,
+                        int32_t *h_pairs_threads);
+
+/* Advance n_steps steps as vb_run does (the same positions and velocities)
+ * while choosing the launch shape by measurement: every gather count and tile
+ * order of the step kernel for n_steps/16 steps each (at least 2), then every
+ * pair-search workgroup size on two forced broad phases each (which change no
+ * result, theorem of Sec. 4.2, but show in the records' rebuilt flags), each
+ * timed by HIP events on the kernels themselves; the rest of the steps run with
+ * the fastest shape.  The chosen shape stays with the context and, for the life
+ * of the process, with its kind (log2 of its particle count, particles per cell,
+ * friction on or off): a context of that kind created later starts from it.
+ * h_hist as for vb_run.  Errors: VB_EINVAL for fewer than 18 steps; those of
+ * vb_run. */
+vb_status vb_tune(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 
 /* Request a broad phase at the next step (all systems), as if a validity test
  * had failed (Def. autoverlet); by the theorem of Sec. 4.2 this changes no

@@ -75,6 +75,11 @@ _SIGNATURES = {
                                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "vb_get_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "vb_set_history": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32]),
+    "vb_set_launch": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "vb_get_launch": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "vb_tune": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     "vb_force_rebuild": (ctypes.c_int32, [_P]),
     "vb_set_K": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_double]),
     "vb_set_timing": (ctypes.c_int32, [_P, ctypes.c_int32]),
@@ -319,6 +324,27 @@ def vb_set_history(ctx, partner, spring):
     vb_set_state."""
     cap, pp, ps = _history_ptrs(ctx, partner, spring)
     _check(lib().vb_set_history(ctx, pp, ps, cap), ctx)
+
+
+def vb_set_launch(ctx, unroll=8, xcd_order=0, pairs_threads=384):
+    """Launch shape of the context (results do not depend on it)."""
+    _check(lib().vb_set_launch(ctx, int(unroll), int(xcd_order), int(pairs_threads)), ctx)
+
+
+def vb_get_launch(ctx):
+    u, x, p = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().vb_get_launch(ctx, ctypes.byref(u), ctypes.byref(x), ctypes.byref(p)), ctx)
+    return {"unroll": u.value, "xcd_order": x.value, "pairs_threads": p.value}
+
+
+def vb_tune(ctx, n_steps, want_history=True):
+    """vb_run that chooses the launch shape by measurement while it runs; returns
+    the [n_sys, n_steps] step records (or None)."""
+    n_sys = vb_get_info(ctx)["n_sys"] if want_history else 0
+    hist = np.zeros((n_sys, max(n_steps, 0)), dtype=STEP_RECORD_DTYPE) if want_history else None
+    ptr = hist.ctypes.data_as(ctypes.c_void_p) if want_history and n_steps > 0 else None
+    _check(lib().vb_tune(ctx, int(n_steps), ptr), ctx)
+    return hist
 
 
 def vb_force_rebuild(ctx):

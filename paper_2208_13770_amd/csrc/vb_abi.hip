@@ -17,8 +17,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/vbuf.h"
@@ -27,10 +29,11 @@
 namespace vb {
 hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, hipStream_t st,
                        hipEvent_t t0, hipEvent_t t1);
-hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st,
+hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, int nt, hipStream_t st,
                               hipEvent_t t0, hipEvent_t t1);
-size_t pairs_lds_bytes(int width, int pmax);
-int pairs_blocks_per_cu(int width, int pmax);
+size_t pairs_lds_bytes(int width, int pmax, int nt);
+int pairs_blocks_per_cu(int width, int pmax, int nt);
+bool pairs_threads_supported(int nt);
 hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
                               const uint32_t *origs, const HistEntry *hist, const int32_t *hcnt,
                               int64_t stride, int32_t hcap, int32_t *partner, double *spring,
@@ -181,8 +184,11 @@ struct vb_ctx {
   int32_t sort_interval = 0;
   int loaded = 0;
   int fresh = 0;               // a state was loaded and no step has run since
+  // launch shape (results do not depend on it): see Shape below
   int xcd_remap = 0;
   int step_unroll = 8;
+  int pairs_t = PAIRS_T;
+  int shape_fixed = 0;  // the shape was set by the environment: the tuned cache does not apply
   // replay of STATS_RING steps as one HIP graph (launch-bound small systems);
   // one cached graph per ping-pong parity, keyed by what the graph bakes in
   int use_graphs = 1;
@@ -309,24 +315,73 @@ static int64_t make_grid(const vb_params &p, SysDev &S) {
   return nkeys;
 }
 
+// LDS and grid of the pair search for the current row width and threads per
+// workgroup.  LDS: rows plus staged candidates of 24 bytes; half the CU's LDS per
+// workgroup (two resident per CU), less 5 KB for the kernel's static arrays,
+// unless wide rows need more; never beyond the device limit.  Grid: the pair
+// search walks the bricks grid-stride with exactly the workgroups that are
+// resident at once, so that at any time they work on one window of consecutive
+// bricks, whose staged neighbourhoods overlap in L2.
+static void size_pair_search(vb_ctx *c) {
+  const int64_t rows = (int64_t)pairs_lds_bytes(c->width, 0, c->pairs_t);
+  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - 6144,
+                                           std::max<int64_t>((int64_t)c->lds_cu / 2 - 5120, rows + 1024 * 24));
+  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
+  c->pairs_grid = (int)std::max<int64_t>(
+      1, std::min<int64_t>(c->n_bricks,
+                           (int64_t)pairs_blocks_per_cu(c->width, c->pmax, c->pairs_t) * c->n_cu));
+}
+
 static vb_status alloc_rows(vb_ctx *c, int32_t width) {
   if (c->nbr) (void)hipFree(c->nbr);
   c->nbr = nullptr;
   HIP_OK(c, dalloc(&c->nbr, c->slots * (int64_t)width));
   c->width = width;
-  // LDS of k_pairs: rows plus staged candidates of 24 bytes.  Half the CU's
-  // LDS per workgroup (two resident per CU), less 5 KB for the kernel's static
-  // arrays, unless wide rows need more; never beyond the device limit.
-  const int64_t rows = (int64_t)pairs_lds_bytes(width, 0);
-  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - 6144,
-                                           std::max<int64_t>((int64_t)c->lds_cu / 2 - 5120, rows + 1024 * 24));
-  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
-  // the pair search walks the bricks grid-stride with exactly the workgroups
-  // that are resident at once, so that at any time they work on one window of
-  // consecutive bricks, whose staged neighbourhoods overlap in L2
-  c->pairs_grid = (int)std::max<int64_t>(
-      1, std::min<int64_t>(c->n_bricks, (int64_t)pairs_blocks_per_cu(width, c->pmax) * c->n_cu));
+  size_pair_search(c);
   return VB_OK;
+}
+
+// ------------------------------------------------------------------ launch shapes
+// The launch shape of a context: the partner gathers each step-kernel thread
+// keeps in flight (1, 2, 4 or 8), the step kernel's tile order (0: launch
+// order, 1: each XCD a contiguous range) and the pair search's threads per
+// workgroup (256, 384 or 512).  Results do not depend on it (the FP64 contact
+// law and integration are rounded after every operation and summed in one
+// order), so it may change between any two steps.
+struct Shape {
+  int unroll, xcd, pairs_t;
+};
+
+static bool shape_ok(const Shape &sh) {
+  return (sh.unroll == 1 || sh.unroll == 2 || sh.unroll == 4 || sh.unroll == 8) &&
+         (sh.xcd == 0 || sh.xcd == 1) && pairs_threads_supported(sh.pairs_t);
+}
+
+static Shape current_shape(const vb_ctx *c) { return Shape{c->step_unroll, c->xcd_remap, c->pairs_t}; }
+
+static void apply_shape(vb_ctx *c, const Shape &sh) {
+  c->step_unroll = sh.unroll;
+  c->xcd_remap = sh.xcd;
+  if (sh.pairs_t != c->pairs_t) {
+    c->pairs_t = sh.pairs_t;
+    size_pair_search(c);
+  }
+}
+
+// Shapes chosen by vb_tune, kept for the life of the process and keyed by the
+// batch's size (log2 of its particle count), its density (particles per cell, in
+// quarters) and whether friction is on; vb_batch_create starts from the entry
+// of its key.
+using ShapeKey = std::tuple<int, int, int>;
+static std::map<ShapeKey, Shape> g_shapes;
+static std::mutex g_shapes_mutex;
+
+static ShapeKey shape_key(const vb_ctx *c) {
+  int64_t cells = 0;
+  for (const SysDev &S : c->sys_h) cells += (int64_t)S.nc[0] * S.nc[1] * S.nc[2];
+  const int lg = c->n_total > 0 ? (int)std::floor(std::log2((double)c->n_total)) : 0;
+  const int dens = (int)std::lround(4.0 * (double)c->n_total / (double)std::max<int64_t>(cells, 1));
+  return ShapeKey(lg, dens, c->any_friction);
 }
 
 // Friction history: cap entries per slot, double-buffered, plus the snapshot
@@ -381,8 +436,8 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   if (!c) return fail(nullptr, VB_ENOMEM, "host allocation failed");
   c->stream = reinterpret_cast<hipStream_t>(stream);
   const char *env = std::getenv("VBUF_XCD_REMAP");
-  if (env) c->xcd_remap = std::atoi(env) != 0;
-  if ((env = std::getenv("VBUF_STEP_UNROLL"))) c->step_unroll = std::atoi(env);
+  if (env) c->xcd_remap = std::atoi(env) != 0, c->shape_fixed = 1;
+  if ((env = std::getenv("VBUF_STEP_UNROLL"))) c->step_unroll = std::atoi(env), c->shape_fixed = 1;
   if ((env = std::getenv("VBUF_GRAPHS"))) c->use_graphs = std::atoi(env) != 0;
   vb_status st = VB_OK;
   auto bail = [&](vb_status code) {
@@ -407,8 +462,10 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   c->n_cu = prop.multiProcessorCount;
   c->lds_limit = prop.sharedMemPerBlock;
   c->lds_cu = std::max(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
-  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144 - pairs_lds_bytes(0, 0)) /
-                                                         (PAIRS_T * sizeof(uint16_t)));
+  // rows are sorted in LDS: the widest row any pair-search shape (up to 512
+  // threads per workgroup) can hold
+  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144 - pairs_lds_bytes(0, 0, 512)) /
+                                                         (512 * sizeof(uint16_t)));
   c->row_limit -= c->row_limit % ROW_GROUP;  // rows are stored in whole groups
   c->n_sys = n_sys;
   c->sys_h.resize(n_sys);
@@ -566,6 +623,11 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     c->msg = "device initialisation failed";
     return bail(VB_EDEVICE);
   }
+  if (!c->shape_fixed) {  // a shape tuned earlier in this process for batches like this one
+    std::lock_guard<std::mutex> lock(g_shapes_mutex);
+    auto it = g_shapes.find(shape_key(c));
+    if (it != g_shapes.end()) apply_shape(c, it->second);
+  }
   *out = c;
   return VB_OK;
 }
@@ -706,7 +768,7 @@ static vb_status queue_broad_phase(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_
     c->next_sort = c->sort_interval > 0 ? c->step + c->sort_interval : -1;
   }
   HIP_OK(c, launch_broad_phase(broad_args(c, c->force_pending, c->relist_pending), c->broad_grid,
-                               c->pairs_grid, c->stream, t0, t1));
+                               c->pairs_grid, c->pairs_t, c->stream, t0, t1));
   c->force_pending = 0;
   c->relist_pending = 0;
   return VB_OK;
@@ -769,6 +831,7 @@ static uint64_t graph_key(const vb_ctx *c, int cur) {
                             (uint64_t)(uintptr_t)c->hist[cur], (uint64_t)(uintptr_t)c->hist[cur ^ 1],
                             (uint64_t)(uintptr_t)c->stream, (uint64_t)c->width, (uint64_t)c->pmax,
                             (uint64_t)c->bin_cap, (uint64_t)c->hcap, (uint64_t)c->step_unroll,
+                            (uint64_t)c->xcd_remap, (uint64_t)c->pairs_t, (uint64_t)c->pairs_grid,
                             (uint64_t)cur};
   uint64_t h = 1469598103934665603ull;  // FNV-1a over the words
   for (uint64_t w : parts)
@@ -795,7 +858,7 @@ static vb_status capture_block(vb_ctx *c, int cur) {
     for (int32_t i = 0; i < STATS_RING && st == VB_OK; ++i) {
       c->graph_off = i;
       BroadArgs b = broad_args(c, 0, 0);
-      if (launch_broad_phase(b, c->broad_grid, c->pairs_grid, c->stream, nullptr, nullptr) !=
+      if (launch_broad_phase(b, c->broad_grid, c->pairs_grid, c->pairs_t, c->stream, nullptr, nullptr) !=
           hipSuccess)
         st = fail(c, VB_EDEVICE, "capture of the broad phase failed");
       else if ((st = queue_step(c)) == VB_OK)
@@ -1296,6 +1359,106 @@ extern "C" vb_status vb_get_pairs_noalloc(vb_ctx *c, int32_t sys, int32_t which,
   HIP_OK(c, hipStreamSynchronize(c->stream));
   if (c->sys_h[sys].n == 0) total = 0;
   if (h_n) *h_n = total;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_set_launch(vb_ctx *c, int32_t unroll, int32_t xcd_order, int32_t pairs_threads) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  const Shape sh{unroll, xcd_order, pairs_threads};
+  if (!shape_ok(sh))
+    return fail(c, VB_EINVAL, "launch shape: unroll 1, 2, 4 or 8; xcd_order 0 or 1; pairs_threads "
+                              "256, 384 or 512");
+  apply_shape(c, sh);
+  return VB_OK;
+}
+
+extern "C" vb_status vb_get_launch(vb_ctx *c, int32_t *h_unroll, int32_t *h_xcd_order,
+                                   int32_t *h_pairs_threads) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (h_unroll) *h_unroll = c->step_unroll;
+  if (h_xcd_order) *h_xcd_order = c->xcd_remap;
+  if (h_pairs_threads) *h_pairs_threads = c->pairs_t;
+  return VB_OK;
+}
+
+extern "C" vb_status vb_tune(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) {
+  if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
+  if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded (vb_set_state)");
+  const Shape step_cands[] = {{8, 0, 0}, {8, 1, 0}, {4, 0, 0}, {4, 1, 0}, {2, 0, 0}, {2, 1, 0}};
+  const int pair_cands[] = {256, 384, 512};
+  constexpr int N_STEP = 6, N_PAIR = 3, PAIR_REPS = 2;
+  const int32_t trial = std::max<int32_t>(2, n_steps / 16);
+  if (n_steps < N_STEP * trial + N_PAIR * PAIR_REPS)
+    return fail(c, VB_EINVAL, "vb_tune needs at least " +
+                                  std::to_string(N_STEP * 2 + N_PAIR * PAIR_REPS) + " steps");
+  // the caller's timing totals are set aside while the tuner times its trials
+  const bool timing0 = c->timing;
+  const double ms_rebuild0 = c->ms_rebuild, ms_step0 = c->ms_step;
+  const int64_t t_steps0 = c->t_steps, t_rebuild0 = c->t_rebuild_steps;
+  std::vector<vb_step_record> part;
+  int32_t done = 0;
+  auto run = [&](int32_t steps) -> vb_status {
+    part.assign((size_t)c->n_sys * steps, vb_step_record{});
+    vb_status st = vb_run(c, steps, part.data());
+    if (st != VB_OK) return st;
+    if (h_hist)
+      for (int s = 0; s < c->n_sys; ++s)
+        for (int32_t r = 0; r < steps; ++r)
+          h_hist[(int64_t)s * n_steps + done + r] = part[(size_t)s * steps + r];
+    done += steps;
+    return VB_OK;
+  };
+  auto restore_timing = [&]() {
+    c->timing = timing0;
+    c->ms_rebuild = ms_rebuild0;
+    c->ms_step = ms_step0;
+    c->t_steps = t_steps0;
+    c->t_rebuild_steps = t_rebuild0;
+  };
+  vb_status st = VB_OK;
+  Shape best = current_shape(c);
+  // 1) the step kernel: every gather count and tile order for `trial` steps,
+  //    timed by HIP events on the kernel itself
+  double best_ms = INFINITY;
+  c->timing = true;
+  for (int i = 0; i < N_STEP && st == VB_OK; ++i) {
+    const Shape sh{step_cands[i].unroll, step_cands[i].xcd, best.pairs_t};
+    apply_shape(c, sh);
+    c->ms_step = 0.0;
+    c->t_steps = 0;
+    if ((st = run(trial)) == VB_OK && c->ms_step / trial < best_ms) {
+      best_ms = c->ms_step / trial;
+      best.unroll = sh.unroll;
+      best.xcd = sh.xcd;
+    }
+  }
+  // 2) the pair search: every workgroup size on PAIR_REPS forced broad phases
+  //    (which change no result, theorem of Sec. 4.2), timed from the start of the
+  //    binning to the end of the pair search
+  best_ms = INFINITY;
+  for (int i = 0; i < N_PAIR && st == VB_OK; ++i) {
+    const Shape sh{best.unroll, best.xcd, pair_cands[i]};
+    apply_shape(c, sh);
+    c->ms_rebuild = 0.0;
+    for (int r = 0; r < PAIR_REPS && st == VB_OK; ++r) {
+      c->force_pending = 1;
+      st = run(1);
+    }
+    if (st == VB_OK && c->ms_rebuild < best_ms) {
+      best_ms = c->ms_rebuild;
+      best.pairs_t = sh.pairs_t;
+    }
+  }
+  restore_timing();
+  if (st != VB_OK) return st;
+  // 3) the rest of the steps with the chosen shape, which later contexts of
+  //    this kind start from
+  apply_shape(c, best);
+  {
+    std::lock_guard<std::mutex> lock(g_shapes_mutex);
+    g_shapes[shape_key(c)] = best;
+  }
+  if (n_steps > done && (st = run(n_steps - done)) != VB_OK) return st;
   return VB_OK;
 }
 

@@ -649,17 +649,17 @@ __device__ __forceinline__ void bitonic_sort(int32_t (&key)[N]) {
 }
 
 // Writes this thread's row of n <= N staged-entry indices (column threadIdx.x
-// of a [.][PAIRS_T] LDS array) to the Verlet list as slots, ordered by original
+// of a [.][NT] LDS array) to the Verlet list as slots, ordered by original
 // index: the original indices are sorted in registers, then turned into slots
 // through inv (inv[orig] = slot of the system's particle orig).
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void row_write_sorted(const uint16_t *s_row, const int32_t *s_key,
                                                  const int32_t *__restrict__ inv, int n,
                                                  int32_t *nbr, int64_t stride, int64_t k) {
   static_assert(N % ROW_GROUP == 0, "whole groups");
   int32_t key[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) key[q] = q < n ? s_key[s_row[q * PAIRS_T + threadIdx.x]] : INT32_MAX;
+  for (int q = 0; q < N; ++q) key[q] = q < n ? s_key[s_row[q * NT + threadIdx.x]] : INT32_MAX;
   bitonic_sort<N>(key);
 #pragma unroll
   for (int q = 0; q < N; ++q) key[q] = q < n ? inv[key[q]] : 0;
@@ -673,22 +673,23 @@ __device__ __forceinline__ void row_write_sorted(const uint16_t *s_row, const in
 }
 
 // The same for a row of any length up to W: insertion sort in LDS.
+template <int NT>
 __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int32_t *s_key,
                                                      const int32_t *s_slot, int n, int32_t *nbr,
                                                      int64_t stride, int64_t k) {
   for (int i = 1; i < n; ++i) {
-    const int e = s_row[i * PAIRS_T + threadIdx.x];
+    const int e = s_row[i * NT + threadIdx.x];
     const int32_t key = s_key[e];
     int j = i;
     while (j > 0) {
-      const int prev = s_row[(j - 1) * PAIRS_T + threadIdx.x];
+      const int prev = s_row[(j - 1) * NT + threadIdx.x];
       if (s_key[prev] <= key) break;
-      s_row[j * PAIRS_T + threadIdx.x] = (uint16_t)prev;
+      s_row[j * NT + threadIdx.x] = (uint16_t)prev;
       --j;
     }
-    s_row[j * PAIRS_T + threadIdx.x] = (uint16_t)e;
+    s_row[j * NT + threadIdx.x] = (uint16_t)e;
   }
-  for (int q = 0; q < n; ++q) nbr[row_index(stride, k, q)] = s_slot[s_row[q * PAIRS_T + threadIdx.x]];
+  for (int q = 0; q < n; ++q) nbr[row_index(stride, k, q)] = s_slot[s_row[q * NT + threadIdx.x]];
 }
 
 // The FP32 inclusion test of Alg. 1 on the extended spheres, |x_i - x_j| <=
@@ -703,9 +704,9 @@ __device__ __forceinline__ bool within_reach(const float4 &me, const float4 &o, 
 
 // Four staged entries e..e+3 against the particle `me` (position and R_NL +
 // eps): each entry index is written at the row's end (offset wofs, capped at
-// the spare row wend), and the row grows by PAIRS_T for each entry within
+// the spare row wend), and the row grows by NT for each entry within
 // reach.  TAIL masks entries at or past e1; OWN masks the particle's own entry.
-template <bool TAIL, bool OWN>
+template <bool TAIL, bool OWN, int NT>
 __device__ __forceinline__ void pair_test4(const float4 *s_pos, int e, int e1, int me_e,
                                            const float4 &me, float reach, uint16_t *myrow,
                                            unsigned wend, unsigned &wofs) {
@@ -716,17 +717,17 @@ __device__ __forceinline__ void pair_test4(const float4 *s_pos, int e, int e1, i
     if (TAIL) hit = hit && e + u < e1;
     if (OWN) hit = hit && e + u != me_e;
     myrow[min(wofs, wend)] = (uint16_t)(e + u);
-    wofs += hit ? PAIRS_T : 0;
+    wofs += hit ? NT : 0;
   }
 }
 
 // The staged range [e, e1): groups of four, the last one masked.
-template <bool OWN>
+template <bool OWN, int NT>
 __device__ __forceinline__ void pair_scan_range(const float4 *s_pos, int e, int e1, int me_e,
                                                 const float4 &me, float reach, uint16_t *myrow,
                                                 unsigned wend, unsigned &wofs) {
-  for (; e + 4 <= e1; e += 4) pair_test4<false, OWN>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
-  if (e < e1) pair_test4<true, OWN>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
+  for (; e + 4 <= e1; e += 4) pair_test4<false, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
+  if (e < e1) pair_test4<true, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
 }
 
 // Alg. 1 on the extended spheres, one workgroup per brick of cells: the bins of
@@ -737,24 +738,25 @@ __device__ __forceinline__ void pair_scan_range(const float4 *s_pos, int e, int 
 // the row is then sorted by original index and stored as slots.  A
 // neighbourhood too full for LDS is read from the bins directly, by half the
 // workgroup.
-__global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int HALF = PAIRS_T / 2;
+  constexpr int HALF = NT / 2;
   const int W = a.width;
   float4 *s_pos = reinterpret_cast<float4 *>(lds);                          // [pmax + 4]
   int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax + 4);         // [pmax]
   int32_t *s_slot = s_key + a.pmax;                                         // [pmax]
   unsigned char *rows = reinterpret_cast<unsigned char *>(s_slot + a.pmax);
-  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W + 1][PAIRS_T]
+  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W + 1][NT]
   int32_t *s_row32 = reinterpret_cast<int32_t *>(rows);                     // [W][HALF]
   __shared__ int s_cnt[8 * 8 * 8];
   __shared__ int s_off[8 * 8 * 8 + 1];
   __shared__ int s_home[BRICK * BRICK * BRICK + 1];
   static_assert(BRICK * BRICK * BRICK == WAVE, "one lane per cell of a brick");
-  static_assert(2 * PAIRS_T >= 8 * 8 * 8, "two box cells per thread in the prefix");
+  static_assert(2 * NT >= 8 * 8 * 8, "two box cells per thread in the prefix");
   const int tid = threadIdx.x;
   int any = 0;
-  for (int s = tid; s < a.n_sys; s += PAIRS_T) any |= a.go[s];
+  for (int s = tid; s < a.n_sys; s += NT) any |= a.go[s];
   if (!__syncthreads_or(any)) return;
   for (int64_t b = blockIdx.x; b < a.n_bricks; b += gridDim.x) {
     const int s = a.brick_sys[b];
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
     const int bx = lb % S.nb[0], by = (lb / S.nb[0]) % S.nb[1], bz = lb / (S.nb[0] * S.nb[1]);
     const int ox = bx * BRICK - r, oy = by * BRICK - r, oz = bz * BRICK - r;
     // occupancy of every cell of the neighbourhood box (0 outside the grid)
-    for (int v = tid; v < V; v += PAIRS_T) {
+    for (int v = tid; v < V; v += NT) {
       const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
       int n = 0;
       if (cx >= 0 && cy >= 0 && cz >= 0 && cx < S.nc[0] && cy < S.nc[1] && cz < S.nc[2])
@@ -777,7 +779,7 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
       const int v0 = 2 * tid;
       const int c0 = v0 < V ? s_cnt[v0] : 0, c1 = v0 + 1 < V ? s_cnt[v0 + 1] : 0;
       int tot;
-      const int incl = block_inclusive_scan<PAIRS_T>(c0 + c1, &tot);
+      const int incl = block_inclusive_scan<NT>(c0 + c1, &tot);
       if (v0 < V) s_off[v0] = incl - c0 - c1;
       if (v0 + 1 < V) s_off[v0 + 1] = incl - c1;
       if (tid == 0) s_off[V] = tot;
@@ -798,7 +800,7 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
     __syncthreads();
     const bool staged = s_off[V] <= a.pmax;
     if (staged) {
-      for (int v = tid; v < V; v += PAIRS_T) {
+      for (int v = tid; v < V; v += NT) {
         const int n = s_cnt[v];
         if (n == 0) continue;
         const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
@@ -825,7 +827,7 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
       __syncthreads();
     }
     const int H = s_home[WAVE];
-    const int step_h = staged ? PAIRS_T : HALF;
+    const int step_h = staged ? NT : HALF;
     if (staged || tid < HALF)
       for (int h = tid; h < H; h += step_h) {
         int lo = 0, hi = WAVE;  // home cell j: s_home[j] <= h < s_home[j+1]
@@ -853,29 +855,29 @@ __global__ __launch_bounds__(PAIRS_T) void k_pairs(BroadArgs a) {
           // the staged array, which has four spare entries), and only the
           // particle's own row of cells can hold the particle itself.
           uint16_t *myrow = s_row16 + tid;
-          const unsigned wend = (unsigned)W * PAIRS_T;
-          unsigned wofs = 0;  // count * PAIRS_T
+          const unsigned wend = (unsigned)W * NT;
+          unsigned wofs = 0;  // count * NT
           for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy) {
               const int vrow = v + (dz * E + dy) * E;
               const int e0 = s_off[vrow - r], e1 = s_off[vrow + r + 1];
               if (dz == 0 && dy == 0)
-                pair_scan_range<true>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
+                pair_scan_range<true, NT>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
               else
-                pair_scan_range<false>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
+                pair_scan_range<false, NT>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
             }
-          count = (int)(wofs / PAIRS_T);
+          count = (int)(wofs / NT);
           const int kept = count < W ? count : W;
           // one sort for the whole wave, sized by its longest row (no divergence)
           const int32_t *inv = a.inv + S.p_off;
           if (!__any(kept > 8))
-            row_write_sorted<8>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
+            row_write_sorted<8, NT>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else if (!__any(kept > 16))
-            row_write_sorted<16>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
+            row_write_sorted<16, NT>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else if (!__any(kept > 32))
-            row_write_sorted<32>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
+            row_write_sorted<32, NT>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else
-            row_write_sorted_lds(s_row16, s_key, s_slot, kept, a.nbr, a.stride, k);
+            row_write_sorted_lds<NT>(s_row16, s_key, s_slot, kept, a.nbr, a.stride, k);
         } else {
           const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
           const float4 me = a.bins_bp[mybase + i];
@@ -1389,38 +1391,53 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
   return hipGetLastError();
 }
 
-// Dynamic LDS of k_pairs: staged candidates (position and R_NL with four spare
-// entries for the scan's reads past a range, original index, slot) and the rows
-// (W + 1 rows of 16-bit staged indices, the last a spare for full rows, or W
-// rows of 32-bit keys for half the threads in the fallback path).
-size_t pairs_lds_bytes(int width, int pmax) {
+// Dynamic LDS of k_pairs<nt>: staged candidates (position and R_NL with four
+// spare entries for the scan's reads past a range, original index, slot) and the
+// rows (W + 1 rows of 16-bit staged indices, the last a spare for full rows, or
+// W rows of 32-bit keys for half the threads in the fallback path).
+size_t pairs_lds_bytes(int width, int pmax, int nt) {
   return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * 2 * sizeof(int32_t) +
-         (size_t)PAIRS_T * (size_t)(width + 1) * sizeof(uint16_t);
+         (size_t)nt * (size_t)(width + 1) * sizeof(uint16_t);
 }
 
-// Workgroups of the pair search resident on one CU at once (at least 1).
-int pairs_blocks_per_cu(int width, int pmax) {
+// Threads per pair-search workgroup the library is built for.
+bool pairs_threads_supported(int nt) { return nt == 256 || nt == 384 || nt == 512; }
+
+// Workgroups of the pair search with nt threads resident on one CU at once (at
+// least 1).
+int pairs_blocks_per_cu(int width, int pmax, int nt) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs, PAIRS_T, pairs_lds_bytes(width, pmax)) !=
-      hipSuccess)
-    return 1;
+  const size_t lds = pairs_lds_bytes(width, pmax, nt);
+  hipError_t e;
+  if (nt == 256) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<256>, 256, lds);
+  else if (nt == 512) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<512>, 512, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pairs<384>, 384, lds);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
+template <int NT>
+static void launch_pairs_t(const BroadArgs &a, int grid_pairs, uint32_t lds, hipStream_t st,
+                           hipEvent_t t1) {
+  if (t1) hipExtLaunchKernelGGL(k_pairs<NT>, dim3(grid_pairs), dim3(NT), lds, st, nullptr, t1, 0, a);
+  else hipLaunchKernelGGL(k_pairs<NT>, dim3(grid_pairs), dim3(NT), lds, st, a);
+}
+
 // t0 takes the start of the binning kernel, t1 the end of the pair search
-// (both null, or both events).
-hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, hipStream_t st,
+// (both null, or both events).  The pair search runs nt threads per workgroup.
+hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, int nt, hipStream_t st,
                               hipEvent_t t0, hipEvent_t t1) {
   if (grid_bin <= 0) return hipSuccess;
-  const uint32_t lds = (uint32_t)pairs_lds_bytes(a.width, a.pmax);
-  if (t0 || t1) {
+  const uint32_t lds = (uint32_t)pairs_lds_bytes(a.width, a.pmax, nt);
+  if (t0 || t1)
     hipExtLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, t0, grid_pairs > 0 ? nullptr : t1,
                           0, a);
-    if (grid_pairs > 0)
-      hipExtLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(PAIRS_T), lds, st, nullptr, t1, 0, a);
-  } else {
+  else
     hipLaunchKernelGGL(k_bin, dim3(grid_bin), dim3(TILE), 0, st, a);
-    if (grid_pairs > 0) hipLaunchKernelGGL(k_pairs, dim3(grid_pairs), dim3(PAIRS_T), lds, st, a);
+  if (grid_pairs > 0) {
+    if (nt == 256) launch_pairs_t<256>(a, grid_pairs, lds, st, t1);
+    else if (nt == 512) launch_pairs_t<512>(a, grid_pairs, lds, st, t1);
+    else launch_pairs_t<384>(a, grid_pairs, lds, st, t1);
   }
   return hipGetLastError();
 }

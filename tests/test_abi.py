@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_header_declares_the_abi():
     names = declared_functions()
-    assert "vb_create" in names and "vb_run" in names and len(names) == 18
+    assert "vb_create" in names and "vb_run" in names and len(names) == 21
 
 
 @pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")

@@ -1117,3 +1117,60 @@ def test_tuning_variants_against_oracle(env):
     assert_close(s, xf, vf, xo, vo, "variant with friction")
     assert np.array_equal(hf[0]["contacts"], ho["contacts"])
     assert np.array_equal(xf, xfn) and np.array_equal(vf, vfn)
+
+
+def test_launch_shapes_give_identical_bits():
+    """Every launch shape (vb_set_launch: 1, 2, 4 or 8 partner gathers in flight,
+    launch or XCD tile order, 256, 384 or 512 pair-search threads) gives the
+    same positions, velocities and records, bit for bit: with the local buffer,
+    with friction, and with a broad phase at every step (every pair-search shape
+    at work every step)."""
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=13)[0]
+    for name, ov in (("K=200", {}), ("friction", _frictional(s)), ("no buffer", {"skin_mode": 2})):
+        ref = None
+        for unroll in (8, 4, 2, 1):
+            for xcd in (0, 1):
+                for pt in (256, 384, 512):
+                    with GpuRun([s], ov) as g:
+                        vb.vb_set_launch(g.ctx, unroll, xcd, pt)
+                        assert vb.vb_get_launch(g.ctx) == {"unroll": unroll, "xcd_order": xcd,
+                                                           "pairs_threads": pt}
+                        h = g.run(120)
+                        x, v, _ = g.state()
+                    if ref is None:
+                        ref = (x, v, h)
+                        continue
+                    what = f"{name} unroll={unroll} xcd={xcd} threads={pt}"
+                    assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), what
+                    assert np.array_equal(h, ref[2]), what
+        say(f"  {name}: 24 launch shapes, identical")
+    with GpuRun([s]) as g:
+        for bad in ((3, 0, 384), (8, 2, 384), (8, 0, 300)):
+            with pytest.raises(vb.VbError) as e:
+                vb.vb_set_launch(g.ctx, *bad)
+            assert e.value.code == vb.VB_EINVAL
+
+
+def test_tuner_runs_the_same_steps_and_remembers_its_choice():
+    """vb_tune advances the state exactly as vb_run does (its forced broad phases
+    change no result) while it times every launch shape, and a later context of
+    the same kind starts from the shape it chose."""
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=14)[0]
+    xa, va, ha = gpu_trajectory([s], 240)
+    with GpuRun([s]) as g:
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_tune(g.ctx, 10)
+        assert e.value.code == vb.VB_EINVAL
+        h = vb.vb_tune(g.ctx, 240)
+        x, v, _ = g.state()
+        chosen = vb.vb_get_launch(g.ctx)
+    say(f"  tuned shape {chosen}; broad phases {int(h[0]['rebuilt'].sum())} "
+        f"(plain run {int(ha[0]['rebuilt'].sum())})")
+    assert np.array_equal(x, xa) and np.array_equal(v, va)
+    assert np.array_equal(h[0]["contacts"], ha[0]["contacts"])
+    assert h[0]["step"].tolist() == list(range(240))
+    assert h[0]["rebuilt"].sum() >= ha[0]["rebuilt"].sum()
+    with GpuRun([s]) as g:
+        assert vb.vb_get_launch(g.ctx) == chosen
