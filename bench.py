@@ -93,7 +93,11 @@ def copy_bandwidth(torch, nbytes=4 << 30):
     return 2 * nbytes / dt / 1e9
 
 
-def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500, repeats=1):
+DEFAULT_SHAPE = (8, 0, 384)  # gathers in flight, tile order, pair-search threads
+
+
+def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500, repeats=1,
+             shape=None):
     """One context over `systems` (a batch when more than one).  After `warmup`
     untimed steps, `repeats` timed runs of `steps` steps, each from the loaded
     initial state (step 0, whose broad phase is timed).  Returns the wall times,
@@ -103,6 +107,8 @@ def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=50
     ctx = vb.vb_batch_create(params, [s.n for s in systems])
     walls, hist = [], None
     try:
+        if shape is not None:
+            vb.vb_set_launch(ctx, *shape)
         x, v, rc, invm = vb.state_tensors(systems)
         if warmup > 0:
             vb.vb_set_state(ctx, x, v, rc, invm)
@@ -122,10 +128,26 @@ def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=50
         del x, v, rc, invm
         pt = vb.vb_phase_times(ctx)
         info = vb.vb_get_info(ctx)
+        info["launch"] = vb.vb_get_launch(ctx)
     finally:
         vb.vb_destroy(ctx)
         torch.cuda.synchronize()
     return walls, hist, pt, info
+
+
+def tune_shape(vb, torch, systems, steps):
+    """An untimed run of `steps` steps that chooses the launch shape by
+    measurement (vb_tune); contexts of the same kind created afterwards start
+    from it.  Returns the chosen shape."""
+    ctx = vb.vb_batch_create([dict(s.params) for s in systems], [s.n for s in systems])
+    try:
+        x, v, rc, invm = vb.state_tensors(systems)
+        vb.vb_set_state(ctx, x, v, rc, invm)
+        vb.vb_tune(ctx, steps, want_history=False)
+        return vb.vb_get_launch(ctx)
+    finally:
+        vb.vb_destroy(ctx)
+        torch.cuda.synchronize()
 
 
 def cpu_model():
@@ -191,6 +213,10 @@ def main():
     ap.add_argument("--call-steps", type=int, default=500,
                     help="steps per vb_run call (a call whose rows or cell bins overflow runs "
                          "again from its own start)")
+    ap.add_argument("--tune", type=int, default=0, metavar="STEPS",
+                    help="first choose the launch shape by measurement over STEPS untimed steps "
+                         "(vb_tune); the timed runs use it, and the same runs with the fixed "
+                         "default shape are timed beside them")
     ap.add_argument("--repeats", type=int, default=100,
                     help="timed runs of the same steps without instrumentation, each from step 0 "
                          "(value is their mean; the plain baseline runs a tenth as many)")
@@ -225,6 +251,9 @@ def main():
     # an identical run with HIP events on every kernel (the events cost a few
     # per cent of wall time)
     cs = args.call_steps
+    tuned = tune_shape(vb, torch, systems, args.tune) if args.tune > 0 else None
+    if tuned:
+        log(f"tuned launch shape: {tuned}")
     walls, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False, cs,
                                     repeats=args.repeats)
     wall = float(np.mean(walls))
@@ -268,6 +297,17 @@ def main():
         }
         log(f"plain (broad phase every step): {wall_p * 1e3:.1f} ms; Eq. impr "
             f"{plain['improvement_pct']:.1f} %")
+
+    launch = {"shape": info["launch"], "tuned": tuned is not None}
+    if tuned:  # the same runs with the fixed default shape
+        walls_f, hist_f, _, info_f = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False,
+                                              cs, repeats=args.repeats, shape=DEFAULT_SHAPE)
+        assert np.array_equal(hist_f, hist)
+        launch.update(fixed_shape=info_f["launch"], fixed_ms_mean=float(np.mean(walls_f)) * 1e3,
+                      tuned_ms_mean=wall * 1e3, tune_steps=args.tune,
+                      speedup=float(np.mean(walls_f)) / wall)
+        log(f"fixed shape {info_f['launch']}: {np.mean(walls_f) * 1e3:.1f} ms; tuned "
+            f"{wall * 1e3:.1f} ms")
 
     sequential = None
     if args.sequential and len(systems) > 1:
@@ -331,6 +371,7 @@ def main():
         "repeats": {"n": len(walls), "ms_mean": float(np.mean(walls)) * 1e3,
                     "ms_std": float(np.std(walls, ddof=1)) * 1e3 if len(walls) > 1 else 0.0,
                     "ms_min": min(walls) * 1e3, "ms_max": max(walls) * 1e3},
+        "launch": launch,
         "broad_phases": n_rebuild,
         "executed_broad_phase_pct": report.executed_fraction(n_rebuild, args.steps * len(systems)),
         "broad_phase_ms_total": pt["ms_rebuild"],
