@@ -93,7 +93,7 @@ def copy_bandwidth(torch, nbytes=4 << 30):
     return 2 * nbytes / dt / 1e9
 
 
-DEFAULT_SHAPE = (8, 0, 384)  # gathers in flight, tile order, pair-search threads
+DEFAULT_SHAPE = (8, 2, 384)  # gathers in flight, tile order, pair-search threads
 
 
 def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500, repeats=1,
@@ -217,10 +217,17 @@ def main():
                     help="first choose the launch shape by measurement over STEPS untimed steps "
                          "(vb_tune); the timed runs use it, and the same runs with the fixed "
                          "default shape are timed beside them")
+    ap.add_argument("--launch", default=None, metavar="U,X,T",
+                    help="fixed launch shape for every run: gathers in flight per step-kernel "
+                         "thread U (1, 2, 4, 8), tile order X (0 launch order, 1 contiguous per "
+                         "XCD, 2 runs of 32 tiles per XCD), pair-search threads T (256, 384, 512); default: the library's")
     ap.add_argument("--repeats", type=int, default=100,
                     help="timed runs of the same steps without instrumentation, each from step 0 "
                          "(value is their mean; the plain baseline runs a tenth as many)")
     args = ap.parse_args()
+    shape = tuple(int(t) for t in args.launch.split(",")) if args.launch else None
+    if shape is not None and (len(shape) != 3 or args.tune > 0):
+        ap.error("--launch takes U,X,T and excludes --tune")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the method's "
               "hot path is measured on one GPU's share; multi-GPU sharding is a design "
@@ -255,10 +262,11 @@ def main():
     if tuned:
         log(f"tuned launch shape: {tuned}")
     walls, hist, _, info = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False, cs,
-                                    repeats=args.repeats)
+                                    repeats=args.repeats, shape=shape)
     wall = float(np.mean(walls))
     value = n * args.steps / wall / 1e6
-    walls_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True, cs)
+    walls_ev, hist_ev, pt, _ = run_mode(vb, torch, systems, args.steps, 0, {}, True, cs,
+                                        shape=shape)
     wall_ev = walls_ev[0]
     assert np.array_equal(hist_ev["contacts"], hist["contacts"])
     rebuilt = hist["rebuilt"].astype(bool)            # [n_sys, steps]
@@ -281,10 +289,10 @@ def main():
     if not args.no_plain:
         walls_p, hist_p, _, _ = run_mode(vb, torch, systems, args.steps, args.warmup,
                                          {"skin_mode": vb.VB_NO_BUFFER}, False, cs,
-                                         repeats=max(1, args.repeats // 10))
+                                         repeats=max(1, args.repeats // 10), shape=shape)
         wall_p = float(np.mean(walls_p))
         _, _, pt_p, _ = run_mode(vb, torch, systems, args.steps, 0,
-                                 {"skin_mode": vb.VB_NO_BUFFER}, True, cs)
+                                 {"skin_mode": vb.VB_NO_BUFFER}, True, cs, shape=shape)
         plain = {
             "time_s": wall_p,
             "runs": len(walls_p),

@@ -272,8 +272,10 @@ vb_status vb_get_pairs_noalloc(vb_ctx *ctx, int32_t sys, int32_t which, int32_t 
 
 /* Launch shape of a context: the partner gathers each thread of the step kernel
  * keeps in flight (unroll 1, 2, 4 or 8), the step kernel's tile order (xcd_order
- * 0: launch order, 1: each of the 8 XCDs a contiguous range of tiles) and the
- * threads of a pair-search workgroup (256, 384 or 512).  Results, records and
+ * 0: launch order, 1: each of the 8 XCDs a contiguous range of tiles, 2: each
+ * XCD runs of 32 consecutive tiles, the 8 runs of a group side by side) and the
+ * threads of a pair-search workgroup (256, 384 or 512); a new context starts
+ * from (8, 2, 384), or from the shape vb_tune chose for its kind.  Results, records and
  * the schedule of broad phases do not depend on it (the steps are those of the
  * time loop of Sec. 3.1 whatever the shape), so it may change between any two
  * calls.  Errors: VB_EINVAL for a value outside those sets. */
@@ -290,7 +292,7 @@ vb_status vb_get_launch(vb_ctx *ctx, int32_t *h_unroll, int32_t *h_xcd_order,
  * the fastest shape.  The chosen shape stays with the context and, for the life
  * of the process, with its kind (log2 of its particle count, particles per cell,
  * friction on or off): a context of that kind created later starts from it.
- * h_hist as for vb_run.  Errors: VB_EINVAL for fewer than 18 steps; those of
+ * h_hist as for vb_run.  Errors: VB_EINVAL for fewer than 24 steps; those of
  * vb_run. */
 vb_status vb_tune(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 

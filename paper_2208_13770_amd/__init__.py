@@ -326,7 +326,7 @@ def vb_set_history(ctx, partner, spring):
     _check(lib().vb_set_history(ctx, pp, ps, cap), ctx)
 
 
-def vb_set_launch(ctx, unroll=8, xcd_order=0, pairs_threads=384):
+def vb_set_launch(ctx, unroll=8, xcd_order=2, pairs_threads=384):
     """Launch shape of the context (results do not depend on it)."""
     _check(lib().vb_set_launch(ctx, int(unroll), int(xcd_order), int(pairs_threads)), ctx)
 

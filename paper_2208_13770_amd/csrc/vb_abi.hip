@@ -185,7 +185,7 @@ struct vb_ctx {
   int loaded = 0;
   int fresh = 0;               // a state was loaded and no step has run since
   // launch shape (results do not depend on it): see Shape below
-  int xcd_remap = 0;
+  int xcd_remap = 2;
   int step_unroll = 8;
   int pairs_t = PAIRS_T;
   int shape_fixed = 0;  // the shape was set by the environment: the tuned cache does not apply
@@ -344,7 +344,8 @@ static vb_status alloc_rows(vb_ctx *c, int32_t width) {
 // ------------------------------------------------------------------ launch shapes
 // The launch shape of a context: the partner gathers each step-kernel thread
 // keeps in flight (1, 2, 4 or 8), the step kernel's tile order (0: launch
-// order, 1: each XCD a contiguous range) and the pair search's threads per
+// order, 1: each XCD a contiguous range, 2: each XCD runs of consecutive tiles
+// inside one window) and the pair search's threads per
 // workgroup (256, 384 or 512).  Results do not depend on it (the FP64 contact
 // law and integration are rounded after every operation and summed in one
 // order), so it may change between any two steps.
@@ -354,7 +355,7 @@ struct Shape {
 
 static bool shape_ok(const Shape &sh) {
   return (sh.unroll == 1 || sh.unroll == 2 || sh.unroll == 4 || sh.unroll == 8) &&
-         (sh.xcd == 0 || sh.xcd == 1) && pairs_threads_supported(sh.pairs_t);
+         (sh.xcd >= 0 && sh.xcd <= 2) && pairs_threads_supported(sh.pairs_t);
 }
 
 static Shape current_shape(const vb_ctx *c) { return Shape{c->step_unroll, c->xcd_remap, c->pairs_t}; }
@@ -436,7 +437,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   if (!c) return fail(nullptr, VB_ENOMEM, "host allocation failed");
   c->stream = reinterpret_cast<hipStream_t>(stream);
   const char *env = std::getenv("VBUF_XCD_REMAP");
-  if (env) c->xcd_remap = std::atoi(env) != 0, c->shape_fixed = 1;
+  if (env) c->xcd_remap = std::min(2, std::max(0, std::atoi(env))), c->shape_fixed = 1;
   if ((env = std::getenv("VBUF_STEP_UNROLL"))) c->step_unroll = std::atoi(env), c->shape_fixed = 1;
   if ((env = std::getenv("VBUF_GRAPHS"))) c->use_graphs = std::atoi(env) != 0;
   vb_status st = VB_OK;
@@ -1366,7 +1367,7 @@ extern "C" vb_status vb_set_launch(vb_ctx *c, int32_t unroll, int32_t xcd_order,
   if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
   const Shape sh{unroll, xcd_order, pairs_threads};
   if (!shape_ok(sh))
-    return fail(c, VB_EINVAL, "launch shape: unroll 1, 2, 4 or 8; xcd_order 0 or 1; pairs_threads "
+    return fail(c, VB_EINVAL, "launch shape: unroll 1, 2, 4 or 8; xcd_order 0, 1 or 2; pairs_threads "
                               "256, 384 or 512");
   apply_shape(c, sh);
   return VB_OK;
@@ -1384,9 +1385,10 @@ extern "C" vb_status vb_get_launch(vb_ctx *c, int32_t *h_unroll, int32_t *h_xcd_
 extern "C" vb_status vb_tune(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist) {
   if (!c) return fail(nullptr, VB_EINVAL, "ctx is NULL");
   if (!c->loaded) return fail(c, VB_EINVAL, "no state loaded (vb_set_state)");
-  const Shape step_cands[] = {{8, 0, 0}, {8, 1, 0}, {4, 0, 0}, {4, 1, 0}, {2, 0, 0}, {2, 1, 0}};
+  const Shape step_cands[] = {{8, 2, 0}, {8, 0, 0}, {8, 1, 0}, {4, 2, 0}, {4, 0, 0},
+                              {4, 1, 0}, {2, 2, 0}, {2, 0, 0}, {2, 1, 0}};
   const int pair_cands[] = {256, 384, 512};
-  constexpr int N_STEP = 6, N_PAIR = 3, PAIR_REPS = 2;
+  constexpr int N_STEP = 9, N_PAIR = 3, PAIR_REPS = 2;
   const int32_t trial = std::max<int32_t>(2, n_steps / 16);
   if (n_steps < N_STEP * trial + N_PAIR * PAIR_REPS)
     return fail(c, VB_EINVAL, "vb_tune needs at least " +

@@ -170,7 +170,8 @@ struct StepArgs {
   int32_t step;          // the step, or its offset from *step_base when step_base is set
   const int32_t *step_base;  // device step counter of a replayed graph (else null)
   int32_t first;         // 1: the velocities are the full-step v^0 (no first half kick)
-  int32_t xcd_remap;     // 1: give each XCD a contiguous range of tiles
+  int32_t xcd_remap;     // tile order: 0 launch order, 1 a contiguous range per XCD,
+                         // 2 runs of consecutive tiles per XCD
   int32_t width;         // row capacity W (entries below it are allocated)
   // friction history (used only when some system has friction): column-major,
   // entry c of slot k at hist[c * stride + k]

@@ -170,12 +170,29 @@ __device__ __forceinline__ bool posq_candidate(const QSelf &m, uint64_t o, float
   return __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz)) <= reach * reach;
 }
 
-// Maps a workgroup index to a tile so that each of the 8 XCDs (which receive
-// workgroups round-robin) walks a contiguous range of tiles.
-__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n) {
-  const int64_t x = i & 7, k = i >> 3;
-  const int64_t q = n >> 3, r = n & 7;
-  return x * q + (x < r ? x : r) + k;
+// Tile of workgroup i of n in the step kernel's tile order.  The 8 XCDs receive
+// workgroups round-robin (workgroup i on XCD i % 8), and each has its own L2.
+//  0: tile i.  Tiles in flight at one time form one window of consecutive
+//     tiles, spread over all XCDs.
+//  1: each XCD walks a contiguous eighth of the tiles.
+//  2: runs of XCD_RUN consecutive tiles go to one XCD, the 8 runs of a group
+//     side by side, so that a tile's neighbours along the storage order are
+//     mostly on its own XCD while the window stays one (a last group shorter
+//     than 8 runs keeps order 0).
+constexpr int64_t XCD_RUN = 32;
+__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t n, int order) {
+  if (order == 1) {
+    const int64_t x = i & 7, k = i >> 3;
+    const int64_t q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + k;
+  }
+  if (order == 2) {
+    const int64_t g = i / (8 * XCD_RUN);
+    if ((g + 1) * 8 * XCD_RUN > n) return i;
+    const int64_t r = i - g * 8 * XCD_RUN;
+    return g * 8 * XCD_RUN + (r & 7) * XCD_RUN + (r >> 3);
+  }
+  return i;
 }
 
 // Cell number of integer cell coordinates.  Cells are numbered brick by brick
@@ -267,7 +284,7 @@ __device__ __forceinline__ void nt_store24(double *dst, double a, double b, doub
 
 template <int UNROLL, bool FRIC>
 __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
-  const int64_t t = a.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_remap);
   const int s = a.tile_sys[t];
   const SysDev &S = a.sys[s];
   const int lt = (int)(t - S.tile_off);

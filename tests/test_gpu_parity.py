@@ -1121,7 +1121,7 @@ def test_tuning_variants_against_oracle(env):
 
 def test_launch_shapes_give_identical_bits():
     """Every launch shape (vb_set_launch: 1, 2, 4 or 8 partner gathers in flight,
-    launch or XCD tile order, 256, 384 or 512 pair-search threads) gives the
+    tile order 0, 1 or 2, 256, 384 or 512 pair-search threads) gives the
     same positions, velocities and records, bit for bit: with the local buffer,
     with friction, and with a broad phase at every step (every pair-search shape
     at work every step)."""
@@ -1130,7 +1130,7 @@ def test_launch_shapes_give_identical_bits():
     for name, ov in (("K=200", {}), ("friction", _frictional(s)), ("no buffer", {"skin_mode": 2})):
         ref = None
         for unroll in (8, 4, 2, 1):
-            for xcd in (0, 1):
+            for xcd in (0, 1, 2):
                 for pt in (256, 384, 512):
                     with GpuRun([s], ov) as g:
                         vb.vb_set_launch(g.ctx, unroll, xcd, pt)
@@ -1144,12 +1144,33 @@ def test_launch_shapes_give_identical_bits():
                     what = f"{name} unroll={unroll} xcd={xcd} threads={pt}"
                     assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), what
                     assert np.array_equal(h, ref[2]), what
-        say(f"  {name}: 24 launch shapes, identical")
+        say(f"  {name}: 36 launch shapes, identical")
     with GpuRun([s]) as g:
-        for bad in ((3, 0, 384), (8, 2, 384), (8, 0, 300)):
+        for bad in ((3, 0, 384), (8, 3, 384), (8, -1, 384), (8, 0, 300)):
             with pytest.raises(vb.VbError) as e:
                 vb.vb_set_launch(g.ctx, *bad)
             assert e.value.code == vb.VB_EINVAL
+
+
+def test_tile_orders_on_a_system_of_several_tile_groups():
+    """The tile orders permute whole groups of 8 runs of 32 tiles (order 2) or
+    split the tiles in eight (order 1); on a system of 320 tiles (one whole group
+    of 256 and a shorter last group) every order gives the same bits."""
+    import paper_2208_13770_amd as vb
+    s = synth.lattice_system(64, 64, 20, 16, 8, 0.1, 21)
+    assert s.n == 81920
+    ref = None
+    for xcd in (0, 1, 2):
+        with GpuRun([s]) as g:
+            vb.vb_set_launch(g.ctx, 8, xcd, 384)
+            h = g.run(100)
+            x, v, _ = g.state()
+        if ref is None:
+            ref = (x, v, h)
+            continue
+        assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), xcd
+        assert np.array_equal(h, ref[2]), xcd
+    assert ref[2]["contacts"][0].sum() > 0
 
 
 def test_tuner_runs_the_same_steps_and_remembers_its_choice():
