@@ -93,7 +93,10 @@ def copy_bandwidth(torch, nbytes=4 << 30):
     return 2 * nbytes / dt / 1e9
 
 
-DEFAULT_SHAPE = (8, 2, 384)  # gathers in flight, tile order, pair-search threads
+def default_shape(n, friction):
+    """The library's launch shape for a new context (gathers in flight, tile
+    order, pair-search threads) that no tuner has seen."""
+    return (4 if friction or n < 2 ** 20 else 8, 2, 384)
 
 
 def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500, repeats=1,
@@ -309,7 +312,8 @@ def main():
     launch = {"shape": info["launch"], "tuned": tuned is not None}
     if tuned:  # the same runs with the fixed default shape
         walls_f, hist_f, _, info_f = run_mode(vb, torch, systems, args.steps, args.warmup, {}, False,
-                                              cs, repeats=args.repeats, shape=DEFAULT_SHAPE)
+                                              cs, repeats=args.repeats,
+                                              shape=default_shape(n, args.friction > 0.0))
         assert np.array_equal(hist_f, hist)
         launch.update(fixed_shape=info_f["launch"], fixed_ms_mean=float(np.mean(walls_f)) * 1e3,
                       tuned_ms_mean=wall * 1e3, tune_steps=args.tune,

@@ -154,7 +154,7 @@ struct vb_ctx {
   int2 *bins_so = nullptr;
   int32_t bin_cap = 0;
   int32_t *cellid = nullptr, *inv = nullptr;
-  int32_t *brick_sys = nullptr;
+  int32_t *act = nullptr;      // systems of the current broad phase (see BroadArgs)
   int64_t n_bricks = 0;
   int32_t pmax = 0;            // candidates k_pairs stages in LDS per workgroup
   size_t lds_limit = 0;        // LDS bytes a workgroup may use on this device
@@ -234,7 +234,7 @@ static void free_all(vb_ctx *c) {
                   c->orig[0], c->orig[1], c->posq[0],
                   c->posq[1], c->rrange, c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
                   c->hcnt_snap, c->snap_x, c->snap_v, c->snap_ri, c->snap_orig, c->snap_bp, c->snap_flags, c->bp, c->bp_alt, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
-                  c->brick_sys, c->cellid, c->inv,
+                  c->act, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
                   c->go, c->overflow, c->err, c->stats, c->rebuilt_ring, c->hist_d,
                   c->pair_counts, c->pair_offsets, c->pair_total};
@@ -553,11 +553,6 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   std::vector<int32_t> ts(std::max<int64_t>(c->n_tiles, 1), 0);
   for (int s = 0; s < n_sys; ++s)
     for (int t = 0; t < c->sys_h[s].n_tiles; ++t) ts[c->sys_h[s].tile_off + t] = s;
-  std::vector<int32_t> bs(std::max<int64_t>(c->n_bricks, 1), 0);
-  for (int s = 0; s < n_sys; ++s) {
-    const SysDev &S = c->sys_h[s];
-    for (int64_t b = 0; b < (int64_t)S.nb[0] * S.nb[1] * S.nb[2]; ++b) bs[S.b_off + b] = s;
-  }
 
 #define ALLOC(ptr, count)                                         \
   if (dalloc(&(ptr), (count)) != hipSuccess) {                    \
@@ -578,7 +573,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   ALLOC(c->bp_alt, c->slots);
   ALLOC(c->cnt, c->slots);
   ALLOC(c->bin_count, c->n_cells);
-  ALLOC(c->brick_sys, c->n_bricks);
+  ALLOC(c->act, 2 * MAX_SYS + 2);
   ALLOC(c->cellid, c->slots);
   ALLOC(c->inv, c->slots);
   ALLOC(c->cell_count, c->n_cells);
@@ -609,8 +604,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
           hipSuccess ||
       hipMemcpy(c->tile_sys, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(c->brick_sys, bs.data(), sizeof(int32_t) * bs.size(), hipMemcpyHostToDevice) !=
-          hipSuccess ||
+      hipMemset(c->act, 0, sizeof(int32_t) * (2 * MAX_SYS + 2)) != hipSuccess ||
       hipMemset(c->bin_count, 0, sizeof(int32_t) * std::max<int64_t>(c->n_cells, 1)) !=
           hipSuccess ||
       hipMemset(c->cell_count, 0, sizeof(int32_t) * std::max<int64_t>(c->n_cells, 1)) !=
@@ -624,7 +618,12 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     c->msg = "device initialisation failed";
     return bail(VB_EDEVICE);
   }
-  if (!c->shape_fixed) {  // a shape tuned earlier in this process for batches like this one
+  if (!c->shape_fixed) {
+    // the default shape keeps fewer partner gathers in flight per thread where
+    // the registers they take cost more than they hide: batches under 2^20
+    // particles (a few thousand tiles) and friction
+    if (c->any_friction || c->n_total < (int64_t)1 << 20) c->step_unroll = 4;
+    // a shape tuned earlier in this process for batches like this one
     std::lock_guard<std::mutex> lock(g_shapes_mutex);
     auto it = g_shapes.find(shape_key(c));
     if (it != g_shapes.end()) apply_shape(c, it->second);
@@ -711,7 +710,7 @@ static BroadArgs broad_args(vb_ctx *c, int force, int relist) {
   a.bins_bp = c->bins_bp;
   a.bins_so = c->bins_so;
   a.bin_cap = c->bin_cap;
-  a.brick_sys = c->brick_sys;
+  a.act = c->act;
   a.n_bricks = c->n_bricks;
   a.pmax = c->pmax;
   a.inv = c->inv;

@@ -129,7 +129,10 @@ struct BroadArgs {
   float4 *bins_bp;      // [cells][bin_cap] x0 and R_NL of the binned particles
   int2 *bins_so;        // [cells][bin_cap] (local slot, original index) of the binned particles
   int32_t bin_cap;
-  const int32_t *brick_sys;  // [bricks] system of each brick
+  // the systems that take part in this broad phase, written by the binning for
+  // the pair search: act[0] = their count A, act[1 + i] = system i of them (in
+  // index order), act[1 + MAX_SYS + i] = bricks of the systems before it (i <= A)
+  int32_t *act;
   int64_t n_bricks;
   int32_t pmax;         // candidates a workgroup can stage in LDS
   int32_t *inv;         // [slots] inv[p_off + orig] = local slot

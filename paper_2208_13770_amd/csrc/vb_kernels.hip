@@ -564,33 +564,76 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
 // a broad phase at this step; with relist set, the other systems bin their
 // stored x0 and R_NL unchanged (their rows are then rebuilt by the pair search
 // without a broad phase: after a storage sort, a resumed checkpoint or a retried
-// block).  Grid-stride over tiles.
+// block).  The systems that take part are listed first, in index order, with
+// the prefix of their tiles; the grid then walks their tiles only, grid-stride,
+// so that a batch in which few systems rebuild pays for those alone.
 __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
+  constexpr int SYS_PER = MAX_SYS / TILE;  // systems looked at by each thread
+  __shared__ int32_t s_act[MAX_SYS];       // 2 s + 1 if system s runs a broad phase, else 2 s
+  __shared__ int32_t s_tpre[MAX_SYS + 1];  // tiles of the listed systems before entry i
   const int tid = threadIdx.x;
   const int step = a.step + (a.step_base ? *a.step_base : 0);
-  int any = a.force | a.relist;
-  for (int s = tid; s < a.n_sys; s += TILE)
-    any |= needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, step, a.force);
-  if (!__syncthreads_or(any)) {  // the same decision in every workgroup
-    if (blockIdx.x == 0)
-      for (int s = tid; s < a.n_sys; s += TILE) {
-        a.go[s] = 0;
-        a.rebuilt_ring[(step % STATS_RING) * a.n_sys + s] = 0;
-      }
-    return;
-  }
-  if (blockIdx.x == 0)
-    for (int s = tid; s < a.n_sys; s += TILE) {
+  int code[SYS_PER];
+  int n_act = 0;
+#pragma unroll
+  for (int q = 0; q < SYS_PER; ++q) {
+    const int s = tid * SYS_PER + q;
+    code[q] = -1;
+    if (s < a.n_sys) {
       const int nd = needs_broad_phase(a.sys[s], a.flags, a.n_sys, s, step, a.force);
-      a.go[s] = nd | a.relist;
-      a.rebuilt_ring[(step % STATS_RING) * a.n_sys + s] = nd;
+      if (blockIdx.x == 0) {
+        a.go[s] = nd | a.relist;
+        a.rebuilt_ring[(step % STATS_RING) * a.n_sys + s] = nd;
+      }
+      if (nd || a.relist) {
+        code[q] = 2 * s + nd;
+        n_act += 1;
+      }
     }
-  for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-    const int s = a.tile_sys[t];
+  }
+  // a step without broad phase (the common case) ends here, after one barrier
+  if (!__syncthreads_or(n_act)) return;
+  int n_tl = 0, n_bk = 0;
+#pragma unroll
+  for (int q = 0; q < SYS_PER; ++q)
+    if (code[q] >= 0) {
+      const SysDev &S = a.sys[code[q] >> 1];
+      n_tl += S.n_tiles;
+      n_bk += S.nb[0] * S.nb[1] * S.nb[2];
+    }
+  int tot_act, tot_tl, tot_bk;  // the same in every workgroup
+  int i_act = block_inclusive_scan<TILE>(n_act, &tot_act) - n_act;
+  int i_tl = block_inclusive_scan<TILE>(n_tl, &tot_tl) - n_tl;
+  int i_bk = block_inclusive_scan<TILE>(n_bk, &tot_bk) - n_bk;
+#pragma unroll
+  for (int q = 0; q < SYS_PER; ++q)
+    if (code[q] >= 0) {
+      const int s = code[q] >> 1;
+      const SysDev &S = a.sys[s];
+      s_act[i_act] = code[q];
+      s_tpre[i_act] = i_tl;
+      if (blockIdx.x == 0) {
+        a.act[1 + i_act] = s;
+        a.act[1 + MAX_SYS + i_act] = i_bk;
+      }
+      ++i_act;
+      i_tl += S.n_tiles;
+      i_bk += S.nb[0] * S.nb[1] * S.nb[2];
+    }
+  if (tid == 0) {
+    s_tpre[tot_act] = tot_tl;
+    if (blockIdx.x == 0) {
+      a.act[0] = tot_act;
+      a.act[1 + MAX_SYS + tot_act] = tot_bk;
+    }
+  }
+  __syncthreads();
+  int e = 0;  // entry of the listed system that holds tile u
+  for (int64_t u = blockIdx.x; u < tot_tl; u += gridDim.x) {
+    while (s_tpre[e + 1] <= u) ++e;
+    const int s = s_act[e] >> 1, nd = s_act[e] & 1;
     const SysDev &S = a.sys[s];
-    const int nd = needs_broad_phase(S, a.flags, a.n_sys, s, step, a.force);
-    if (!nd && !a.relist) continue;
-    const int local = (int)(t - S.tile_off) * TILE + tid;
+    const int local = (int)(u - s_tpre[e]) * TILE + tid;
     int64_t key = -1;
     float4 b = make_float4(0.f, 0.f, 0.f, 0.f);
     uint32_t orig = 0;
@@ -775,12 +818,17 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
   int any = 0;
   for (int s = tid; s < a.n_sys; s += NT) any |= a.go[s];
   if (!__syncthreads_or(any)) return;
-  for (int64_t b = blockIdx.x; b < a.n_bricks; b += gridDim.x) {
-    const int s = a.brick_sys[b];
-    if (!a.go[s]) continue;
+  // the bricks of the systems that take part, as the binning listed them
+  const int n_act = a.act[0];
+  const int32_t *act_sys = a.act + 1, *act_bpre = a.act + 1 + MAX_SYS;
+  const int64_t n_bk = act_bpre[n_act];
+  int e = 0;  // entry of the listed system that holds brick u
+  for (int64_t u = blockIdx.x; u < n_bk; u += gridDim.x) {
+    while (act_bpre[e + 1] <= u) ++e;
+    const int s = act_sys[e];
     const SysDev &S = a.sys[s];
     const int r = S.ring, E = BRICK + 2 * r, V = E * E * E;
-    const int lb = (int)(b - S.b_off);
+    const int lb = (int)(u - act_bpre[e]);
     const int bx = lb % S.nb[0], by = (lb / S.nb[0]) % S.nb[1], bz = lb / (S.nb[0] * S.nb[1]);
     const int ox = bx * BRICK - r, oy = by * BRICK - r, oz = bz * BRICK - r;
     // occupancy of every cell of the neighbourhood box (0 outside the grid)

@@ -1173,6 +1173,22 @@ def test_tile_orders_on_a_system_of_several_tile_groups():
     assert ref[2]["contacts"][0].sum() > 0
 
 
+def test_default_launch_shape_follows_batch_size_and_friction():
+    """A new context of a kind no tuner has seen starts from 8 gathers in flight
+    for batches of 2^20 particles and more, 4 below that or with friction, tile
+    order 2 and 384 pair-search threads."""
+    import paper_2208_13770_amd as vb
+    small = synth.lattice_system(24, 24, 16, 2, 1, 0.1, 22)
+    large = synth.lattice_system(128, 128, 64, 8, 4, 0.1, 23)
+    assert small.n < 2 ** 20 <= large.n
+    for s, ov, unroll in ((small, {}, 4), (small, _frictional(small), 4), (large, {}, 8)):
+        ctx = vb.vb_batch_create([dict(s.params, **ov)], [s.n])
+        try:
+            assert vb.vb_get_launch(ctx) == {"unroll": unroll, "xcd_order": 2, "pairs_threads": 384}
+        finally:
+            vb.vb_destroy(ctx)
+
+
 def test_tuner_runs_the_same_steps_and_remembers_its_choice():
     """vb_tune advances the state exactly as vb_run does (its forced broad phases
     change no result) while it times every launch shape, and a later context of
