@@ -376,9 +376,12 @@ def main():
                                    "duration; frac uses the scope table's count (84 + 4 n_v B "
                                    "per particle, FP32 state); byte_counts also gives the FP64 "
                                    "state's count and what the kernel's records move; traffic is "
-                                   "the measured HBM bytes per launch (rocprofv3 counters)",
+                                   "the measured HBM bytes per launch (rocprofv3 counters), "
+                                   "traffic_gbs the rate at which the kernel moves them, to "
+                                   "set against copy_bandwidth_gbs",
                      "bytes_per_launch": counts["alg"]["bytes_per_launch"], "n_v": n_v,
                      "byte_counts": counts, "mean_launch_us": step_ms * 1e3,
+                     "traffic_gbs": traffic / (step_ms * 1e-3) / 1e9 if traffic else None,
                      "copy_bandwidth_gbs": copy_gbs, "events_run_ms": wall_ev * 1e3},
         "repeats": {"n": len(walls), "ms_mean": float(np.mean(walls)) * 1e3,
                     "ms_std": float(np.std(walls, ddof=1)) * 1e3 if len(walls) > 1 else 0.0,
