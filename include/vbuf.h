@@ -285,15 +285,16 @@ vb_status vb_get_launch(vb_ctx *ctx, int32_t *h_unroll, int32_t *h_xcd_order,
                         int32_t *h_pairs_threads);
 
 /* Advance n_steps steps as vb_run does (the same positions and velocities)
- * while choosing the launch shape by measurement: every gather count and tile
- * order of the step kernel for n_steps/16 steps each (at least 2), then every
- * pair-search workgroup size on two forced broad phases each (which change no
- * result, theorem of Sec. 4.2, but show in the records' rebuilt flags), each
- * timed by HIP events on the kernels themselves; the rest of the steps run with
- * the fastest shape.  The chosen shape stays with the context and, for the life
+ * while choosing the launch shape by measurement: the starting shape, then every
+ * other gather count and tile order of the step kernel for n_steps/16 steps each
+ * (at least 2), then every pair-search workgroup size on two forced broad phases
+ * each (which change no result, theorem of Sec. 4.2, but show in the records'
+ * rebuilt flags), each timed by HIP events on the kernels themselves; another
+ * shape replaces the starting one only if it is more than 1 % faster.  The rest
+ * of the steps run with the chosen shape.  The chosen shape stays with the context and, for the life
  * of the process, with its kind (log2 of its particle count, particles per cell,
  * friction on or off): a context of that kind created later starts from it.
- * h_hist as for vb_run.  Errors: VB_EINVAL for fewer than 24 steps; those of
+ * h_hist as for vb_run.  Errors: VB_EINVAL for fewer than 26 steps; those of
  * vb_run. */
 vb_status vb_tune(vb_ctx *ctx, int32_t n_steps, vb_step_record *h_hist);
 

@@ -1388,10 +1388,12 @@ extern "C" vb_status vb_tune(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist)
                               {4, 1, 0}, {2, 2, 0}, {2, 0, 0}, {2, 1, 0}};
   const int pair_cands[] = {256, 384, 512};
   constexpr int N_STEP = 9, N_PAIR = 3, PAIR_REPS = 2;
+  // trials: the starting shape and up to N_STEP others (the starting one may
+  // lie outside the list), then the pair-search sizes
   const int32_t trial = std::max<int32_t>(2, n_steps / 16);
-  if (n_steps < N_STEP * trial + N_PAIR * PAIR_REPS)
+  if (n_steps < (N_STEP + 1) * trial + N_PAIR * PAIR_REPS)
     return fail(c, VB_EINVAL, "vb_tune needs at least " +
-                                  std::to_string(N_STEP * 2 + N_PAIR * PAIR_REPS) + " steps");
+                                  std::to_string((N_STEP + 1) * 2 + N_PAIR * PAIR_REPS) + " steps");
   // the caller's timing totals are set aside while the tuner times its trials
   const bool timing0 = c->timing;
   const double ms_rebuild0 = c->ms_rebuild, ms_step0 = c->ms_step;
@@ -1417,37 +1419,47 @@ extern "C" vb_status vb_tune(vb_ctx *c, int32_t n_steps, vb_step_record *h_hist)
     c->t_rebuild_steps = t_rebuild0;
   };
   vb_status st = VB_OK;
-  Shape best = current_shape(c);
+  const Shape start = current_shape(c);
+  Shape best = start;
+  // The shape the context starts from is timed first and kept unless another
+  // is faster by more than SWITCH_MARGIN: trials are short, and a shape that
+  // wins by less is within their noise.
+  constexpr double SWITCH_MARGIN = 0.01;
   // 1) the step kernel: every gather count and tile order for `trial` steps,
   //    timed by HIP events on the kernel itself
   double best_ms = INFINITY;
   c->timing = true;
-  for (int i = 0; i < N_STEP && st == VB_OK; ++i) {
-    const Shape sh{step_cands[i].unroll, step_cands[i].xcd, best.pairs_t};
+  for (int i = -1; i < N_STEP && st == VB_OK; ++i) {
+    const Shape sh = i < 0 ? start : Shape{step_cands[i].unroll, step_cands[i].xcd, start.pairs_t};
+    if (i >= 0 && sh.unroll == start.unroll && sh.xcd == start.xcd) continue;
     apply_shape(c, sh);
     c->ms_step = 0.0;
     c->t_steps = 0;
-    if ((st = run(trial)) == VB_OK && c->ms_step / trial < best_ms) {
-      best_ms = c->ms_step / trial;
+    if ((st = run(trial)) != VB_OK) break;
+    const double ms = c->ms_step / trial;
+    if (i < 0 || ms < best_ms * (1.0 - SWITCH_MARGIN)) {
+      best_ms = ms;
       best.unroll = sh.unroll;
       best.xcd = sh.xcd;
     }
   }
   // 2) the pair search: every workgroup size on PAIR_REPS forced broad phases
   //    (which change no result, theorem of Sec. 4.2), timed from the start of the
-  //    binning to the end of the pair search
+  //    binning to the end of the pair search, the starting size first
   best_ms = INFINITY;
-  for (int i = 0; i < N_PAIR && st == VB_OK; ++i) {
-    const Shape sh{best.unroll, best.xcd, pair_cands[i]};
+  for (int i = -1; i < N_PAIR && st == VB_OK; ++i) {
+    const int nt = i < 0 ? start.pairs_t : pair_cands[i];
+    if (i >= 0 && nt == start.pairs_t) continue;
+    const Shape sh{best.unroll, best.xcd, nt};
     apply_shape(c, sh);
     c->ms_rebuild = 0.0;
     for (int r = 0; r < PAIR_REPS && st == VB_OK; ++r) {
       c->force_pending = 1;
       st = run(1);
     }
-    if (st == VB_OK && c->ms_rebuild < best_ms) {
+    if (st == VB_OK && (i < 0 || c->ms_rebuild < best_ms * (1.0 - SWITCH_MARGIN))) {
       best_ms = c->ms_rebuild;
-      best.pairs_t = sh.pairs_t;
+      best.pairs_t = nt;
     }
   }
   restore_timing();
