@@ -16,6 +16,7 @@ SKIN_LOCAL, SKIN_UNIFORM, NO_BUFFER, FIXED_INTERVAL, NAIVE = 0, 1, 2, 3, 4
 
 
 MAX_PLANES = 4
+MAX_CYLINDERS = 2
 
 
 class Params(ctypes.Structure):
@@ -44,6 +45,9 @@ class Params(ctypes.Structure):
         ("kt", ctypes.c_double),
         ("gamma_t", ctypes.c_double),
         ("mu", ctypes.c_double),
+        ("n_cylinders", ctypes.c_int32),
+        ("pad3_", ctypes.c_int32),
+        ("cylinders", (ctypes.c_double * 4) * MAX_CYLINDERS),
     ]
 
 
@@ -129,6 +133,12 @@ def make_params(p: dict) -> Params:
     q.n_planes = len(planes)
     for w, pl in enumerate(planes):
         q.planes[w][:] = [float(t) for t in pl]
+    cylinders = p.get("cylinders", ())
+    if len(cylinders) > MAX_CYLINDERS:
+        raise ValueError(f"at most {MAX_CYLINDERS} cylindrical walls")
+    q.n_cylinders = len(cylinders)
+    for w, cy in enumerate(cylinders):
+        q.cylinders[w][:] = [float(t) for t in cy]
     return q
 
 

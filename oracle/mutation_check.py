@@ -39,6 +39,11 @@ MUT = [
  ("max_excess without the skin", "double excess = disp - skin_test[i];", "double excess = disp;"),
  ("list_pairs as contact count", "r->list_pairs = p->skin_mode == ORC_NAIVE ? 0 : list_pairs;", "r->list_pairs = p->skin_mode == ORC_NAIVE ? 0 : C.n;"),
  ("violators off by one", "if (disp > skin_test[i]) viol++;", "if (disp > skin_test[i]) viol += 2;"),
+ ("cylinder normal outward", "double nx = -ex / rho;\n        double ny = -ey / rho;", "double nx = ex / rho;\n        double ny = ey / rho;"),
+ ("cylinder overlap outside the wall", "double delta = rc[i] - (cyl[2] - rho);", "double delta = rc[i] - (cyl[2] + rho);"),
+ ("cylinder height ignored", "if (!(xi[2] > cyl[3])) continue;", ";"),
+ ("cylinder damping sign", "double fm = p->kn * delta - p->gamma_n * vn;\n        f[0] += fm * nx;", "double fm = p->kn * delta + p->gamma_n * vn;\n        f[0] += fm * nx;"),
+ ("cylinder y force dropped", "        f[1] += fm * ny;", "        ;"),
 ]
 dst = os.path.join(tempfile.mkdtemp(prefix='orc_mut_'), 'repo')
 results = []

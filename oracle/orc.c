@@ -2,8 +2,9 @@
  * orc.c -- FP64 CPU oracle for the local Verlet buffer DEM step.
  *
  * TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the CPU
- * baseline leg of the benchmark; never by the product path.  Plain, slow and
- * single-threaded on purpose.  Every function below names the passage of the
+ * baseline leg of the benchmark; never by the product path.  Plain and slow on
+ * purpose (its loops over particles may use several host threads, with results
+ * bit-identical to one thread).  Every function below names the passage of the
  * paper (Mainassara Checkaraou et al., local Verlet buffer for DEM) it follows.
  *
  * Readings taken where the paper is silent or ambiguous (each is listed with its
@@ -25,11 +26,12 @@
  *   R10 the broad-phase inclusion test is inflated by an absolute eps.
  *   R12 the contact law is a normal linear spring-dashpot (Sec. 5.1 names the
  *       model, not its constants, which are inputs here), against particles and
- *       against the walls (box faces and planar walls) alike.
+ *       against the walls (box faces, planar and cylindrical walls) alike.
  *   R13 the dashpot uses the half-step velocity available when forces are evaluated.
  *   R14 the forces on a particle are summed in ascending partner index, then
  *       the box faces (-x, +x, -y, +y, -z, +z), then the planar walls in order,
- *       so that the sum does not depend on what the Verlet list holds.
+ *       then the cylindrical walls in order, so that the sum does not depend on
+ *       what the Verlet list holds.
  *   R16 friction, when on, is a translational tangential spring-dashpot capped
  *       by Coulomb's law, with a spring per contact that starts at zero when the
  *       contact forms (Sec. 5.1 names static friction without its form).
@@ -433,6 +435,25 @@ static int forces_core(const orc_params *p, int64_t n, const double *x, const do
         f[2] += fm * pl[2];
       }
     }
+    /* vertical cylindrical walls (a silo): the same law against the inside of a
+     * cylinder; the centre lies rho from the axis, so R - rho from the wall, and
+     * the wall pushes towards the axis.  A centre on the axis has no normal. */
+    for (int w = 0; w < p->n_cylinders; w++) {
+      const double *cyl = p->cylinders[w];
+      if (!(xi[2] > cyl[3])) continue;
+      double ex = xi[0] - cyl[0];
+      double ey = xi[1] - cyl[1];
+      double rho = sqrt(ex * ex + ey * ey);
+      double delta = rc[i] - (cyl[2] - rho);
+      if (delta > 0.0 && rho > 0.0) {
+        double nx = -ex / rho;
+        double ny = -ey / rho;
+        double vn = vi[0] * nx + vi[1] * ny;
+        double fm = p->kn * delta - p->gamma_n * vn;
+        f[0] += fm * nx;
+        f[1] += fm * ny;
+      }
+    }
     F[3 * i] = f[0];
     F[3 * i + 1] = f[1];
     F[3 * i + 2] = f[2];
@@ -443,7 +464,7 @@ static int forces_core(const orc_params *p, int64_t n, const double *x, const do
 
 /* Linear spring-dashpot (Sec. 5.1) on the contact pairs (i < j), normal part:
  * pair terms summed in ascending partner index, then the walls -x,+x,-y,+y,-z,+z,
- * then the planar walls. */
+ * then the planar walls, then the cylindrical walls. */
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *v,
                const double *rc, int64_t ncontacts, const int32_t *contacts, double *F) {
   return forces_core(p, n, x, v, rc, ncontacts, contacts, F, NULL, NULL);
@@ -483,6 +504,9 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
   if (n < 0 || n_steps < 0 || !(p->dt > 0.0) || !(p->cell_size > 0.0) || p->eps < 0.0) return -1;
   if (p->skin_mode == ORC_FIXED_INTERVAL && p->fixed_interval < 1) return -1;
   if (p->n_planes < 0 || p->n_planes > ORC_MAX_PLANES) return -1;
+  if (p->n_cylinders < 0 || p->n_cylinders > ORC_MAX_CYLINDERS) return -1;
+  for (int w = 0; w < p->n_cylinders; w++)
+    if (!(p->cylinders[w][2] > 0.0)) return -1;
   int32_t ring = p->ring > 0 ? p->ring : (p->cap_mode == 0 ? 1 : 2);
   /* the smallest cell edge that keeps Alg. 1 complete for the chosen cap: every
      reach R_NL,i + R_NL,j + eps is at most ring * edge */

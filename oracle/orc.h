@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #define ORC_MAX_PLANES 4
+#define ORC_MAX_CYLINDERS 2
 
 enum {
   ORC_SKIN_LOCAL = 0,      /* skin_p = K |v_p| dt (the paper's method)              */
@@ -58,6 +59,11 @@ typedef struct {
                            /*     centre has z > z_min (a finite wall, e.g. a hopper side)     */
   double kt, gamma_t, mu;  /* tangential spring, tangential dashpot, Coulomb coefficient of   */
                            /*     particle-particle friction; all 0 = frictionless            */
+  int32_t n_cylinders;     /* vertical cylindrical walls, 0..ORC_MAX_CYLINDERS               */
+  int32_t pad3_;
+  double cylinders[ORC_MAX_CYLINDERS][4]; /* (c_x, c_y, R, z_min): the domain is the inside  */
+                           /*     of the cylinder of radius R about the vertical line through */
+                           /*     (c_x, c_y); the wall acts on centres with z > z_min         */
 } orc_params;
 
 typedef struct {

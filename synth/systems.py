@@ -303,6 +303,49 @@ def incline_system(n_target: int, seed: int, theta_deg: float = 25.0,
                     "a": a, "depth": nz, "static_overlap_bound": STATIC_OVERLAP * float(rad.min())})
 
 
+def silo_system(n_target: int, seed: int, gap: int = 4, polydisperse: bool = True,
+                K: float = 200.0, cell_factor: float = 1.7, eps: float = 2e-6,
+                sigma: float = 0.05) -> ParticleSystem:
+    """A vertical cylindrical silo (a cylinder wall of diameter s lattice spacings
+    about the centre of a box twice as wide) holding about n_target particles on a
+    jittered lattice, a column about twice as tall as it is wide, on the box
+    floor; gravity along -z.  The cylinder acts only above `gap` spacings, so the
+    grains discharge through the ring between the silo's lower edge and the floor
+    and spread over the floor.  A stand-in for the silo and hopper discharge cases
+    of Sec. 5.2, whose geometry is not published."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = max(6, int(round((2.0 * n_target / np.pi) ** (1.0 / 3.0))))  # diameter, in sites
+    r_wall = 0.5 * s + 0.5                                             # wall radius, in sites
+    nxy = 2 * s + 2                                                    # box width, in sites
+    c = 0.5 * (nxy + 1)                                                # axis, in sites
+    g = np.arange(nxy) + 1.0
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    inside = np.hypot(X - c, Y - c) <= r_wall - 0.5                    # clear of the wall
+    col = np.stack([X[inside], Y[inside]], axis=1)
+    layers = max(2, int(np.ceil(n_target / len(col))))
+    nz = layers + 2
+    a = 1.0 / (max(nxy, nz) + 1)
+    pos = np.concatenate([np.concatenate([col, np.full((len(col), 1), k + 1.0)], axis=1)
+                          for k in range(layers)], axis=0) * a
+    n = pos.shape[0]
+    pos = pos + rng.uniform(-0.04 * a, 0.04 * a, size=(n, 3))
+    rad = rng.uniform(0.35 * a, 0.45 * a, size=n) if polydisperse else np.full(n, 0.45 * a)
+    mass = (rad / (0.45 * a)) ** 3
+    phys = physics_constants(a)
+    v_max = phys["v_max"]
+    vel = rng.normal(0.0, sigma * v_max, size=(n, 3))
+    g0 = _gravity_for_depth(phys["kn"], layers, rad.min(), mass.max())
+    cylinders = [(float(np.float32(c * a)), float(np.float32(c * a)), float(np.float32(r_wall * a)),
+                  float(np.float32((gap + 0.5) * a)))]
+    sysm = _system(pos, rad, mass, vel, a, phys, (nxy + 1) * a, (nxy + 1) * a, (nz + 1) * a,
+                   (0.0, 0.0, -g0), [], K, cell_factor, eps,
+                   {"kind": "silo", "diameter_sites": s, "gap_sites": gap, "layers": layers,
+                    "depth": layers, "seed": seed, "v_max": v_max, "a": a,
+                    "static_overlap_bound": STATIC_OVERLAP * float(rad.min())})
+    sysm.params["cylinders"] = cylinders
+    return sysm
+
+
 def _system(pos, rad, mass, vel, a, phys, hx, hy, hz, gravity, planes, K, cell_factor, eps, meta):
     n = pos.shape[0]
     pos_r = np.empty((n, 4), dtype=np.float32)
@@ -365,6 +408,8 @@ def config_systems(name: str, seed: int = 0, scale: float = 1.0, workers: int = 
         return [hopper_system(max(n, 200), 3000 + seed)]
     if name == "INCLINE":
         return [incline_system(max(int(round(250000 * scale ** 3)), 200), 4000 + seed)]
+    if name == "SILO":
+        return [silo_system(max(int(round(125000 * scale ** 3)), 200), 5000 + seed)]
     args = _lattice_args(name, seed, scale)
     if workers <= 1 or len(args) == 1:
         return [_make(a) for a in args]

@@ -332,7 +332,8 @@ def test_gravity_stand_in_static_overlap_is_one_percent():
     a linear spring under a static load, Sec. 5.1's linear spring-dashpot), and
     that is at most 1 % of the smallest R_C."""
     for s in (synth.hopper_system(2000, 5), synth.config_systems("H125")[0],
-              synth.config_systems("H500")[0], synth.config_systems("INCLINE")[0]):
+              synth.config_systems("H500")[0], synth.config_systems("INCLINE")[0],
+              synth.silo_system(2000, 5), synth.config_systems("SILO")[0]):
         g = np.linalg.norm(s.params["g"])
         if s.meta["kind"] == "incline":
             g *= np.cos(np.radians(s.meta["theta_deg"]))  # the load along the floor normal
@@ -685,6 +686,113 @@ def test_plane_count_is_bounded(orc):
          "kn": 1.0, "planes": [(0, 0, 1, 0, 0)] * 5}
     with pytest.raises(ValueError):
         orc.run(p, np.zeros((1, 3)) + 0.5, np.zeros((1, 3)), np.array([0.01]), np.array([1.0]), 1)
+
+
+# ---------------------------------------------------------------- cylindrical walls
+def _cylinder_base(**kw):
+    p = {"skin_mode": 0, "K": 200.0, "dt": 2.0 ** -10, "cell_size": 2.0 ** -3, "eps": 0.0,
+         "lo": (-1.0, -1.0, -1.0), "hi": (1.0, 1.0, 1.0), "kn": 1e3, "gamma_n": 2.0,
+         "g": (0.0, 0.0, 0.0)}
+    p.update(kw)
+    return p
+
+
+def test_cylinder_on_an_axis_line_equals_two_plane_walls_bitwise(orc):
+    """Along a line through the axis the inside of a cylinder is, point for point,
+    the pair of planes tangent to it there: the distance of the centre from the
+    wall is R - |x| and the normal is -sign(x) e_x (sqrt(x^2) = |x| exactly in
+    binary floating point).  Two particles fired outward along the x axis
+    collide with a cylinder of radius 3/4 about the z axis and rebound exactly as
+    from the planes x = 3/4 and x = -3/4 (the same spring-dashpot law), bit for
+    bit, before, during and after contact."""
+    x0 = np.array([[0.6, 0.0, 0.0], [-0.6, 0.0, 0.25]])
+    v0 = np.array([[0.5, 0.0, 0.0], [-0.375, 0.0, 0.0]])
+    rc = np.array([2.0 ** -5, 2.0 ** -5])
+    invm = np.array([1.0, 2.0])
+    cyl = _cylinder_base(cylinders=[(0.0, 0.0, 0.75, -np.inf)])
+    planes = _cylinder_base(planes=[(-1.0, 0.0, 0.0, -0.75, -np.inf), (1.0, 0.0, 0.0, -0.75, -np.inf)])
+    for steps in (150, 300, 600):
+        xa, va, _, _ = orc.run(cyl, x0, v0, rc, invm, steps)
+        xb, vb, _, _ = orc.run(planes, x0, v0, rc, invm, steps)
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb), steps
+    assert va[0, 0] < 0 and va[1, 0] > 0                 # both came back
+    assert abs(xa[0, 0]) < 0.75 and abs(xa[1, 0]) < 0.75
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.9, 4.0])
+def test_cylinder_radial_impact_matches_its_tangent_plane(orc, theta):
+    """A particle fired outward along a ray from the axis meets the wall head on;
+    the normal stays the ray's direction, so the impact is that against the plane
+    tangent to the cylinder where the ray crosses it: the same trajectory up to
+    the rounding of the two geometries, and a restitution below one."""
+    u = np.array([np.cos(theta), np.sin(theta), 0.0])
+    c = np.array([0.125, -0.25, 0.0])
+    R = 0.625
+    x0 = (c + 0.4 * u)[None, :]
+    v0 = (0.5 * u)[None, :]
+    rc, invm = np.array([2.0 ** -5]), np.array([1.0])
+    cyl = _cylinder_base(cylinders=[(c[0], c[1], R, -np.inf)])
+    n = -u
+    plane = _cylinder_base(planes=[(n[0], n[1], n[2], float(n @ (c + R * u)), -np.inf)])
+    xa, va, _, _ = orc.run(cyl, x0, v0, rc, invm, 700)
+    xb, vb, _, _ = orc.run(plane, x0, v0, rc, invm, 700)
+    assert np.abs(xa - xb).max() < 1e-12 and np.abs(va - vb).max() < 1e-10
+    vr = float(va[0] @ u)
+    assert -0.5 < vr < 0.0                                # rebounded, energy dissipated
+
+
+def test_cylinder_acts_only_above_its_height(orc):
+    """Below z_min the silo is open: a particle fired outward under its lower
+    edge flies out on the exact straight line (dyadic data); the same particle
+    above z_min is turned back."""
+    dt = 2.0 ** -10
+    x0 = np.array([[0.5, 0.0, 0.0]])
+    v0 = np.array([[0.5, 0.0, 0.0]])
+    rc, invm = np.array([2.0 ** -5]), np.array([1.0])
+    open_below = _cylinder_base(cylinders=[(0.0, 0.0, 0.75, 0.25)])
+    n = 512
+    xo, vo, _, _ = orc.run(open_below, x0, v0, rc, invm, n)
+    assert np.array_equal(xo[0], x0[0] + n * dt * v0[0]) and np.array_equal(vo, v0)
+    held = _cylinder_base(cylinders=[(0.0, 0.0, 0.75, -0.25)])
+    xh, vh, _, _ = orc.run(held, x0, v0, rc, invm, n)
+    assert xh[0, 0] < 0.75 and vh[0, 0] < 0
+
+
+def test_cylinder_parameters_are_checked(orc):
+    x, v = np.zeros((1, 3)), np.zeros((1, 3))
+    with pytest.raises(ValueError):
+        orc.run(_cylinder_base(cylinders=[(0.0, 0.0, 0.5, 0.0)] * 3), x, v, np.array([0.01]),
+                np.array([1.0]), 1)
+    with pytest.raises(ValueError):
+        orc.run(_cylinder_base(cylinders=[(0.0, 0.0, 0.0, 0.0)]), x, v, np.array([0.01]),
+                np.array([1.0]), 1)
+
+
+def test_silo_stand_in_holds_its_column_and_discharges(orc):
+    """The reduced silo stand-in over 5,000 steps, the paper's shortest run
+    (Sec. 5.1), under the gravity of its column depth: sampled every 500 steps,
+    every overlap (pairs, box faces and the cylinder above its lower edge) stays
+    below 8 % of the smallest R_C, no centre above the lower edge lies outside
+    the cylinder, and grains leave through the ring under the lower edge."""
+    s = synth.silo_system(2000, 5)
+    x, v, rc, invm = arrays(s)
+    lo, hi = np.array(s.params["lo"]), np.array(s.params["hi"])
+    cx, cy, R, z_min = s.params["cylinders"][0]
+    worst = 0.0
+    for c in range(10):
+        x, v, h, _ = orc.run(dict(s.params, v_in_is_half_step=int(c > 0)), x, v, rc, invm, 500)
+        pr = orc.contacts_brute(x, rc)
+        if len(pr):
+            worst = max(worst, (rc[pr[:, 0]] + rc[pr[:, 1]]
+                                - np.linalg.norm(x[pr[:, 0]] - x[pr[:, 1]], axis=1)).max())
+        worst = max(worst, np.maximum(rc[:, None] - (x - lo), rc[:, None] - (hi - x)).max())
+        rho = np.hypot(x[:, 0] - cx, x[:, 1] - cy)
+        above = x[:, 2] > z_min
+        if above.any():
+            worst = max(worst, (rc[above] - (R - rho[above])).max())
+            assert (rho[above] < R).all()
+    assert worst < 0.08 * rc.min(), worst / rc.min()
+    assert (rho > R).sum() > 50                           # discharged through the ring
 
 
 def test_mutation_check_patterns_match_the_oracle():
