@@ -10,10 +10,10 @@ every particle of every system.
 
 --workload M3 runs the 64 uneven systems as one batch (and, with --sequential,
 also one context per system, one after the other); --workload M5 runs 16
-systems of 16.8M particles (268M in all); H125, H250, H500 and INCLINE are the
-gravity-driven stand-ins for the paper's hopper and inclined-plane cases
-(planar walls, polydisperse radii).  Only the default workload times the CPU
-oracle.
+systems of 16.8M particles (268M in all); H125, H250, H500, INCLINE and SILO are
+the gravity-driven stand-ins for the paper's hopper, inclined-plane and silo
+cases (planar and cylindrical walls, polydisperse radii).  Only the default
+workload times the CPU oracle.
 
 Prints ONE JSON line:
   value       whole-job throughput, Mparticle*step/s, of the method (K = 200) with
@@ -192,6 +192,8 @@ WORKLOADS = {
             "particles under gravity, K=200",
     "INCLINE": "inclined-plane stand-in: slab of {n} polydisperse particles, gravity tilted "
                "25 deg, K=200",
+    "SILO": "silo stand-in: vertical cylinder wall (open below 4a) holding {n} polydisperse "
+            "particles under gravity, discharging onto the floor, K=200",
 }
 
 

@@ -73,6 +73,7 @@ typedef int32_t vb_status;
                             /* fixed-update practice the automatic scheme replaces (Sec. 1, 4.2)  */
 
 #define VB_MAX_PLANES 4
+#define VB_MAX_CYLINDERS 2
 
 /* Parameters of one particle system.  Float fields are read as given; positions,
  * velocities and the contact law are evaluated in FP64. */
@@ -107,6 +108,14 @@ typedef struct vb_params {
   int32_t contact_capacity; /* initial contacts per particle the friction history holds (grown  */
                           /* on overflow), 1..64; 0 = 16                                           */
   int32_t reserved2_;
+  int32_t n_cylinders;    /* vertical cylindrical walls, 0..VB_MAX_CYLINDERS                      */
+  int32_t reserved3_;
+  double cylinders[VB_MAX_CYLINDERS][4]; /* (c_x, c_y, R, z_min): the domain is the inside of   */
+                          /* the cylinder of radius R > 0 about the vertical axis through         */
+                          /* (c_x, c_y) (a silo); the wall acts, with the contact law of the box  */
+                          /* faces, on particles whose centre has z > z_min, with the normal      */
+                          /* towards the axis (none for a centre on the axis).  Cylinders act     */
+                          /* after the planar walls, in index order.                              */
 } vb_params;
 
 /* Diagnostics of one time step n of one system (the state x^n whose forces the

@@ -18,6 +18,7 @@ VB_SKIN_LOCAL, VB_SKIN_UNIFORM, VB_NO_BUFFER, VB_FIXED_INTERVAL = 0, 1, 2, 3
 
 
 VB_MAX_PLANES = 4
+VB_MAX_CYLINDERS = 2
 
 
 class vb_params(ctypes.Structure):
@@ -46,6 +47,9 @@ class vb_params(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("contact_capacity", ctypes.c_int32),
         ("reserved2_", ctypes.c_int32),
+        ("n_cylinders", ctypes.c_int32),
+        ("reserved3_", ctypes.c_int32),
+        ("cylinders", (ctypes.c_double * 4) * VB_MAX_CYLINDERS),
     ]
 
 
@@ -154,6 +158,12 @@ def make_params(p: dict) -> vb_params:
     q.n_planes = len(planes)
     for w, pl in enumerate(planes):
         q.planes[w][:] = [float(t) for t in pl]
+    cylinders = p.get("cylinders", ())
+    if len(cylinders) > VB_MAX_CYLINDERS:
+        raise ValueError(f"at most {VB_MAX_CYLINDERS} cylindrical walls")
+    q.n_cylinders = len(cylinders)
+    for w, cy in enumerate(cylinders):
+        q.cylinders[w][:] = [float(t) for t in cy]
     return q
 
 

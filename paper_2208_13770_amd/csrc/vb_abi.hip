@@ -27,8 +27,8 @@
 #include "vb_device.h"
 
 namespace vb {
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, hipStream_t st,
-                       hipEvent_t t0, hipEvent_t t1);
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, int walls,
+                       hipStream_t st, hipEvent_t t0, hipEvent_t t1);
 hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, int nt, hipStream_t st,
                               hipEvent_t t0, hipEvent_t t1);
 size_t pairs_lds_bytes(int width, int pmax, int nt);
@@ -119,6 +119,7 @@ struct vb_ctx {
   int32_t *rrange = nullptr;               // [2][n_sys] smallest and largest R_C (FP32 bits)
   // friction history (allocated only when some system has friction)
   int any_friction = 0;
+  int any_walls = 0;           // some system has planar or cylindrical walls
   int32_t hcap = 0;
   HistEntry *hist[2] = {nullptr, nullptr};
   int32_t *hcnt[2] = {nullptr, nullptr};
@@ -289,6 +290,14 @@ static std::string check_params(const vb_params &p, int64_t n) {
       if (!std::isfinite(pl[c]) && !(c == 4 && pl[c] == -INFINITY)) return "plane values must be finite";
     const double nn = pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2];
     if (std::fabs(nn - 1.0) > 1e-9) return "plane normals must have unit length";
+  }
+  if (p.n_cylinders < 0 || p.n_cylinders > VB_MAX_CYLINDERS) return "n_cylinders must be 0..2";
+  for (int w = 0; w < p.n_cylinders; ++w) {
+    const double *cy = p.cylinders[w];
+    for (int c = 0; c < 4; ++c)
+      if (!std::isfinite(cy[c]) && !(c == 3 && cy[c] == -INFINITY))
+        return "cylinder values must be finite";
+    if (!(cy[2] > 0.0)) return "cylinder radii must be positive";
   }
   return "";
 }
@@ -512,6 +521,10 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     S.n_planes = p.n_planes;
     for (int w = 0; w < p.n_planes; ++w)
       for (int c = 0; c < 5; ++c) S.planes[w][c] = p.planes[w][c];
+    c->any_walls |= p.n_planes > 0 || p.n_cylinders > 0;
+    S.n_cyl = p.n_cylinders;
+    for (int w = 0; w < p.n_cylinders; ++w)
+      for (int c = 0; c < 4; ++c) S.cyl[w][c] = p.cylinders[w][c];
     {  // grid of the coded positions: the box and two cells beyond each face,
        // 2^19 - 1 steps along its longest edge
       double span = 0.0;
@@ -808,7 +821,8 @@ static vb_status queue_step(vb_ctx *c, hipEvent_t t0 = nullptr, hipEvent_t t1 = 
   a.hcnt_dst = c->hcnt[c->cur ^ 1];
   a.hcap = c->hcap;
   a.overflow = c->overflow;
-  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->any_friction, c->stream, t0, t1));
+  HIP_OK(c, launch_step(a, c->n_tiles, c->step_unroll, c->any_friction, c->any_walls, c->stream,
+                        t0, t1));
   return VB_OK;
 }
 

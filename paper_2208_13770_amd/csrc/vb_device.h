@@ -80,6 +80,9 @@ struct SysDev {
   int32_t friction;   // 1: tangential spring-dashpot with Coulomb limit on the contacts
   double planes[VB_MAX_PLANES][5];  // (n_x, n_y, n_z, d, z_min) as in vb_params
   double kt, gamma_t, mu;           // friction law
+  int32_t n_cyl;      // vertical cylindrical walls
+  int32_t pad_cyl;
+  double cyl[VB_MAX_CYLINDERS][4];  // (c_x, c_y, R, z_min) as in vb_params
 };
 
 // One entry of a particle's friction history: a contact of the previous step

@@ -282,7 +282,7 @@ __device__ __forceinline__ void nt_store24(double *dst, double a, double b, doub
 
 // ------------------------------------------------------------------ k_step
 
-template <int UNROLL, bool FRIC>
+template <int UNROLL, bool FRIC, bool WALLS>
 __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_remap);
   const int s = a.tile_sys[t];
@@ -481,19 +481,41 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       const double dhi = (double)mrc - (S.hi[ax] - pos[ax]);
       if (dhi > 0.0) f[ax] -= S.kn * dhi - S.gamma_n * (-vel[ax]);
     }
-    // planar walls, in index order: the same law against the half-space n.x < d,
-    // for centres above the wall's height bound
-    for (int w = 0; w < S.n_planes; ++w) {
-      const double *pl = S.planes[w];
-      if (!(pos[2] > pl[4])) continue;
-      const double sd = pl[0] * pos[0] + pl[1] * pos[1] + pl[2] * pos[2] - pl[3];
-      const double dw = (double)mrc - sd;
-      if (dw > 0.0) {
-        const double vn = vel[0] * pl[0] + vel[1] * pl[1] + vel[2] * pl[2];
-        const double fm = S.kn * dw - S.gamma_n * vn;
-        f[0] += fm * pl[0];
-        f[1] += fm * pl[1];
-        f[2] += fm * pl[2];
+    // planar and cylindrical walls (instances for batches that have them: the
+    // loops cost the step kernel time even when they run no iteration)
+    if constexpr (WALLS) {
+      // planar walls, in index order: the same law against the half-space n.x < d,
+      // for centres above the wall's height bound
+      for (int w = 0; w < S.n_planes; ++w) {
+        const double *pl = S.planes[w];
+        if (!(pos[2] > pl[4])) continue;
+        const double sd = pl[0] * pos[0] + pl[1] * pos[1] + pl[2] * pos[2] - pl[3];
+        const double dw = (double)mrc - sd;
+        if (dw > 0.0) {
+          const double vn = vel[0] * pl[0] + vel[1] * pl[1] + vel[2] * pl[2];
+          const double fm = S.kn * dw - S.gamma_n * vn;
+          f[0] += fm * pl[0];
+          f[1] += fm * pl[1];
+          f[2] += fm * pl[2];
+        }
+      }
+      // vertical cylindrical walls, in index order: the same law against the inside
+      // of the cylinder, for centres above the wall's height bound; the overlap is
+      // R_C less the distance R - rho of the centre from the wall, the normal
+      // points to the axis
+      for (int w = 0; w < S.n_cyl; ++w) {
+        const double *cy = S.cyl[w];
+        if (!(pos[2] > cy[3])) continue;
+        const double dx = pos[0] - cy[0], dy = pos[1] - cy[1];
+        const double rho = sqrt(dx * dx + dy * dy);
+        const double dw = (double)mrc - (cy[2] - rho);
+        if (dw > 0.0 && rho > 0.0) {
+          const double nx = -dx / rho, ny = -dy / rho;
+          const double vn = vel[0] * nx + vel[1] * ny;
+          const double fm = S.kn * dw - S.gamma_n * vn;
+          f[0] += fm * nx;
+          f[1] += fm * ny;
+        }
       }
     }
     // velocity Verlet: v^n = v^{n-1/2} + dt/2 a^n, v^{n+1/2} = v^n + dt/2 a^n,
@@ -1437,22 +1459,25 @@ static void launch_timed(K kernel, dim3 g, dim3 b, uint32_t lds, hipStream_t st,
   else hipLaunchKernelGGL(kernel, g, b, lds, st, a);
 }
 
-template <bool FRIC>
+template <bool FRIC, bool WALLS>
 static void launch_step_t(const StepArgs &a, int64_t n_tiles, int unroll, hipStream_t st,
                           hipEvent_t t0, hipEvent_t t1) {
   const dim3 g((unsigned)n_tiles), b(TILE);
-  if (unroll >= 8) launch_timed(k_step<8, FRIC>, g, b, 0, st, t0, t1, a);
-  else if (unroll >= 4) launch_timed(k_step<4, FRIC>, g, b, 0, st, t0, t1, a);
-  else if (unroll >= 2) launch_timed(k_step<2, FRIC>, g, b, 0, st, t0, t1, a);
-  else launch_timed(k_step<1, FRIC>, g, b, 0, st, t0, t1, a);
+  if (unroll >= 8) launch_timed(k_step<8, FRIC, WALLS>, g, b, 0, st, t0, t1, a);
+  else if (unroll >= 4) launch_timed(k_step<4, FRIC, WALLS>, g, b, 0, st, t0, t1, a);
+  else if (unroll >= 2) launch_timed(k_step<2, FRIC, WALLS>, g, b, 0, st, t0, t1, a);
+  else launch_timed(k_step<1, FRIC, WALLS>, g, b, 0, st, t0, t1, a);
 }
 
-// friction: 1 if some system of the batch has friction (its history is kept)
-hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, hipStream_t st,
-                       hipEvent_t t0, hipEvent_t t1) {
+// friction: 1 if some system of the batch has friction (its history is kept);
+// walls: 1 if some system has planar or cylindrical walls besides the box faces
+hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int friction, int walls,
+                       hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
   if (n_tiles <= 0) return hipSuccess;
-  if (friction) launch_step_t<true>(a, n_tiles, unroll, st, t0, t1);
-  else launch_step_t<false>(a, n_tiles, unroll, st, t0, t1);
+  if (friction && walls) launch_step_t<true, true>(a, n_tiles, unroll, st, t0, t1);
+  else if (friction) launch_step_t<true, false>(a, n_tiles, unroll, st, t0, t1);
+  else if (walls) launch_step_t<false, true>(a, n_tiles, unroll, st, t0, t1);
+  else launch_step_t<false, false>(a, n_tiles, unroll, st, t0, t1);
   return hipGetLastError();
 }
 

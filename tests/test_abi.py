@@ -40,12 +40,13 @@ def test_struct_layouts_match_c():
 #include <stdio.h>
 #include "vbuf.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(vb_params), offsetof(vb_params, K),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(vb_params), offsetof(vb_params, K),
          offsetof(vb_params, lo), offsetof(vb_params, gravity),
          offsetof(vb_params, max_neighbors), offsetof(vb_params, fixed_interval),
          offsetof(vb_params, bin_capacity), offsetof(vb_params, n_planes),
          offsetof(vb_params, planes), offsetof(vb_params, mu),
-         offsetof(vb_params, contact_capacity));
+         offsetof(vb_params, contact_capacity), offsetof(vb_params, n_cylinders),
+         offsetof(vb_params, cylinders));
   printf("%zu %zu %zu %zu\n", sizeof(vb_step_record), offsetof(vb_step_record, list_pairs),
          offsetof(vb_step_record, max_excess), offsetof(vb_step_record, kinetic_energy));
   return 0;
@@ -61,12 +62,13 @@ int main(void) {
     P = vb.vb_params
     want = [ctypes.sizeof(P), P.K.offset, P.lo.offset, P.gravity.offset,
             P.max_neighbors.offset, P.fixed_interval.offset, P.bin_capacity.offset,
-            P.n_planes.offset, P.planes.offset, P.mu.offset, P.contact_capacity.offset]
-    assert [int(t) for t in out[:11]] == want
+            P.n_planes.offset, P.planes.offset, P.mu.offset, P.contact_capacity.offset,
+            P.n_cylinders.offset, P.cylinders.offset]
+    assert [int(t) for t in out[:13]] == want
     R = vb.STEP_RECORD_DTYPE
     want_r = [R.itemsize, R.fields["list_pairs"][1], R.fields["max_excess"][1],
               R.fields["kinetic_energy"][1]]
-    assert [int(t) for t in out[11:]] == want_r
+    assert [int(t) for t in out[13:]] == want_r
 
 
 def test_params_from_generator_dict():

@@ -152,10 +152,11 @@ def test_m5_every_system_bitwise_with_oracle():
     assert hg["rebuilt"][:, 0].all()
 
 
-@pytest.mark.parametrize("name,steps", [("H125", 200), ("INCLINE", 150)])
+@pytest.mark.parametrize("name,steps", [("H125", 200), ("INCLINE", 150), ("SILO", 200)])
 def test_paper_size_gravity_workloads_parity(name, steps):
-    """The hopper stand-in at the paper's smallest size (125k particles) and the
-    inclined-plane stand-in (250k), every particle against the oracle."""
+    """The hopper stand-in at the paper's smallest size (125k particles), the
+    inclined-plane stand-in (250k) and the cylindrical silo stand-in (126k),
+    every particle against the oracle."""
     s = synth.config_systems(name, seed=0)[0]
     say(f"{name}: N={s.n}, {steps} steps")
     xg, vg, hg = gpu_trajectory([s], steps)

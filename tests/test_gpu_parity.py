@@ -591,6 +591,40 @@ def test_gravity_plane_workloads_parity(name, scale, steps):
     check_schedule(hg[0], ho, name)
 
 
+def test_silo_cylinder_parity(scale=0.3, steps=2500):
+    """The silo stand-in (a vertical cylinder wall open below its lower edge,
+    polydisperse radii, gravity) at reduced size against the oracle, element by
+    element, while its grains discharge through the ring under the wall."""
+    s = synth.config_systems("SILO", scale=scale)[0]
+    say(f"SILO at scale {scale}: N={s.n}, {steps} steps, cylinder {s.params['cylinders'][0]}")
+    xg, vg, hg = gpu_trajectory([s], steps)
+    xo, vo, ho, _ = oracle_run(s, steps)
+    assert_close(s, xg, vg, xo, vo, "SILO")
+    assert np.array_equal(hg[0]["contacts"], ho["contacts"])
+    assert ho["contacts"].max() > 20
+    check_schedule(hg[0], ho, "SILO")
+
+
+def test_silo_cylinder_k_invariance_bitwise():
+    s = synth.config_systems("SILO", scale=0.3)[0]
+    say(f"silo K-invariance: N={s.n}")
+    ref = gpu_trajectory([s], 300, skin_mode=2)
+    for ov in ({}, {"K": 20.0}, {"K": 2000.0}):
+        x, v, h = gpu_trajectory([s], 300, **ov)
+        assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), ov
+
+
+def test_cylinder_parameters_are_checked():
+    import paper_2208_13770_amd as vb
+    s = synth.silo_system(500, 3)
+    for cyl in ([(0.5, 0.5, 0.0, 0.0)], [(0.5, float("nan"), 0.3, 0.0)], [(0.5, 0.5, -0.2, 0.0)]):
+        with pytest.raises(vb.VbError) as e:
+            vb.vb_create(dict(s.params, cylinders=cyl), s.n)
+        assert e.value.code == vb.VB_EINVAL
+    with pytest.raises(ValueError):
+        vb.make_params(dict(s.params, cylinders=[(0.5, 0.5, 0.3, 0.0)] * 3))
+
+
 def test_gravity_plane_k_invariance_bitwise():
     s = synth.config_systems("H125", scale=0.35)[0]
     say(f"hopper K-invariance: N={s.n}")
