@@ -988,12 +988,25 @@ def test_random_mixes_against_oracle(seed):
     uniform skin, friction on or off, narrow rows and bins that must grow.  Every system against the oracle (the 1e-5 bars, contact counts
     exact at every step), and the batch against the broad phase at every step,
     bit for bit (Sec. 4.2)."""
+    _random_mix(1000 + seed, 3)
+
+
+@pytest.mark.parametrize("seed", [2, 11, 15])  # draws that mix silos with other kinds
+def test_random_mixes_with_silos_against_oracle(seed):
+    """The same with cylindrical silos among the kinds, so that cylinders meet
+    friction, the uniform skin, growing rows and bins, and systems without
+    walls in one batch (the walls' instance of the step kernel serves them
+    all)."""
+    _random_mix(2000 + seed, 4)
+
+
+def _random_mix(rng_seed, n_kinds):
     import torch
     import paper_2208_13770_amd as vb
-    rng = np.random.default_rng(1000 + seed)
+    rng = np.random.default_rng(rng_seed)
     systems, params = [], []
     for _ in range(int(rng.integers(1, 4))):
-        kind, sd = int(rng.integers(0, 3)), int(rng.integers(0, 1 << 30))
+        kind, sd = int(rng.integers(0, n_kinds)), int(rng.integers(0, 1 << 30))
         K = float(rng.choice([0.0, 10.0, 200.0, 5000.0]))
         if kind == 0:
             dims = [int(rng.integers(4, 15)) for _ in range(3)]
@@ -1005,8 +1018,10 @@ def test_random_mixes_against_oracle(seed):
                                      polydisperse=bool(rng.integers(0, 2)), K=K, cap_mode=cap)
         elif kind == 1:
             s = synth.hopper_system(int(rng.integers(400, 2500)), sd, K=K)
-        else:
+        elif kind == 2:
             s = synth.incline_system(int(rng.integers(400, 2500)), sd, K=K)
+        else:
+            s = synth.silo_system(int(rng.integers(400, 2500)), sd, K=K)
         p = dict(s.params, max_neighbors=int(rng.choice([4, 16, 32])),
                  bin_capacity=int(rng.choice([2, 8, 16])))
         if rng.random() < 0.3:
@@ -1017,7 +1032,7 @@ def test_random_mixes_against_oracle(seed):
         systems.append(s)
         params.append(p)
     steps = 600
-    say(f"random mix {seed}: " + ", ".join(
+    say(f"random mix {rng_seed}: " + ", ".join(
         f"{s.meta.get('kind', 'lattice')} N={s.n} K={p['K']:g} cap={p.get('cap_mode', 0)} "
         f"skin={p.get('skin_mode', 0)} mu={p.get('mu', 0.0):g}" for s, p in zip(systems, params)))
     x, v, rc, invm = vb.state_tensors(systems)
