@@ -120,10 +120,10 @@ def test_m3_batch_parity_with_oracle():
 
 def test_m5_every_system_bitwise_with_oracle():
     """The largest workload, 16 systems of 512x512x64 (268M particles) in one
-    batch, in the launch configuration bench.py times: every system against the
-    oracle, which runs them in parallel processes on the host.  Each compares the
-    SHA-256 of the FP64 positions and velocities (bit-for-bit equality of all
-    268M particles) and the contact count of every step."""
+    batch, in the launch configuration bench.py times, for 50 steps: every system
+    against the oracle, which runs them in parallel processes on the host.  Each
+    compares the SHA-256 of the FP64 positions and velocities (bit-for-bit
+    equality of all 268M particles) and the contact count of every step."""
     import hashlib
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
@@ -132,7 +132,7 @@ def test_m5_every_system_bitwise_with_oracle():
     from tests._gpu import oracle_digest
     args = _lattice_args("M5", 0, 1.0)
     systems = synth.config_systems("M5", seed=0, workers=16)
-    steps = 10
+    steps = 50
     say(f"M5: {len(systems)} systems, N={sum(s.n for s in systems)}, {steps} steps on the GPU")
     xg, vg, hg = gpu_trajectory(systems, steps)
     sl = _slices(systems)
