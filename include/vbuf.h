@@ -40,9 +40,9 @@
  *   - Environment variables read at create, for tuning: VBUF_GRAPHS=0 (results
  *     bit-identical) launches every step on its own instead of
  *     replaying blocks of 64 steps as one captured HIP graph; VBUF_STEP_UNROLL
- *     = 1, 2, 4 or 8 (default 8) sets the partner gathers each thread of the
- *     step kernel keeps in flight; VBUF_XCD_REMAP=1 gives each of the 8 XCDs a
- *     contiguous range of the step kernel's tiles.  Either of the two fixes the
+ *     = 1, 2, 4 or 8 sets the partner gathers each thread of the step kernel
+ *     keeps in flight; VBUF_XCD_REMAP = 0, 1 or 2 sets the step kernel's tile
+ *     order (see vb_set_launch).  Either of the two fixes the
  *     launch shape of the context (vb_set_launch), which vb_tune then does not
  *     take from its cache.  Results are bit-identical for every setting: the
  *     FP64 contact law and integration round every operation (no contraction),

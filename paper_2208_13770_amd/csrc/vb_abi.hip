@@ -4,12 +4,15 @@
 // three launches on the context's stream: the two broad-phase kernels, which
 // return at once unless some system's list went invalid at the previous step
 // (Def. autoverlet), and the fused step kernel.  The host never reads the
-// validity flag; it synchronises once per vb_run call, to collect the per-step
-// records and to check that no Verlet-list row, cell bin or friction history
-// overflowed.  Every reorder_interval steps (and after a state is loaded) the
-// host also queues a counting sort of the particle storage by cell, followed by
-// a broad phase.  Blocks of STATS_RING steps that need nothing from the host
-// run as one replayed HIP graph.
+// validity flag.  It reads the overflow counters after every block of
+// STATS_RING steps, one block behind the device, and waits on them only to
+// take a snapshot (every SNAP_BLOCKS blocks) or at the end of a vb_run call; a
+// Verlet-list row, cell bin or friction history that overflowed is grown and
+// the steps since the last snapshot run again.  Every reorder_interval steps
+// (and after a state is loaded) the host also queues a counting sort of the
+// particle storage by cell, after which every row is rebuilt from the stored
+// x0 and R_NL.  Blocks of STATS_RING steps that need nothing from the host run
+// as one replayed HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

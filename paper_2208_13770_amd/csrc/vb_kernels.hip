@@ -12,7 +12,7 @@
 //            in LDS, one thread per particle, each row sorted by original index;
 //   k_step   narrow phase (Eq. delta), normal spring-dashpot contact force (and
 //            the tangential one with its per-contact history when friction is
-//            on), box and planar walls, gravity, velocity-Verlet integration and
+//            on), box, planar and cylindrical walls, gravity, velocity-Verlet integration and
 //            the displacement test of Eq. update for the next step, fused, one
 //            thread per particle.
 // Both broad-phase kernels return at once when no system needs a broad phase,
@@ -470,7 +470,8 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       }
     }
     // walls: half-spaces of infinite mass at rest, normals into the box,
-    // in the order -x, +x, -y, +y, -z, +z, then the planar walls
+    // in the order -x, +x, -y, +y, -z, +z, then the planar and the cylindrical
+    // walls
     const double pos[3] = {me.x, me.y, me.z};
     const double vel[3] = {mv.vx, mv.vy, mv.vz};
     double f[3] = {fx, fy, fz};
@@ -998,7 +999,8 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
 // ------------------------------------------------------------------ spatial sort
 
 // Counting sort of every system's slots by cell, then by original index inside a
-// cell (deterministic).  Scheduled by the host; followed by a broad phase.
+// cell (deterministic).  Scheduled by the host; every row is then rebuilt from
+// the stored x0 and R_NL (no new broad phase: the schedule is kept).
 __global__ __launch_bounds__(TILE) void k_sort_count(SortArgs a) {
   const int64_t t = blockIdx.x;
   const SysDev &S = a.sys[a.tile_sys[t]];
