@@ -42,7 +42,9 @@
  *     replaying blocks of 64 steps as one captured HIP graph; VBUF_STEP_UNROLL
  *     = 1, 2, 4 or 8 sets the partner gathers each thread of the step kernel
  *     keeps in flight; VBUF_XCD_REMAP = 0, 1 or 2 sets the step kernel's tile
- *     order (see vb_set_launch).  Either of the two fixes the
+ *     order (see vb_set_launch); VBUF_PAIR_WINDOWS=0 makes the pair search
+ *     test whole rows of cells instead of the x windows within reach (the same
+ *     lists).  VBUF_STEP_UNROLL or VBUF_XCD_REMAP fixes the
  *     launch shape of the context (vb_set_launch), which vb_tune then does not
  *     take from its cache.  Results are bit-identical for every setting: the
  *     FP64 contact law and integration round every operation (no contraction),

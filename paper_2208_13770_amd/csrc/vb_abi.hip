@@ -36,6 +36,7 @@ hipError_t launch_broad_phase(const BroadArgs &a, int grid_bin, int grid_pairs, 
                               hipEvent_t t0, hipEvent_t t1);
 size_t pairs_lds_bytes(int width, int pmax, int nt);
 int pairs_blocks_per_cu(int width, int pmax, int nt);
+int64_t pairs_static_lds(int nt);
 bool pairs_threads_supported(int nt);
 hipError_t launch_get_history(const SysDev *sys, const int32_t *tile_sys, int64_t n_tiles,
                               const uint32_t *origs, const HistEntry *hist, const int32_t *hcnt,
@@ -161,6 +162,7 @@ struct vb_ctx {
   int32_t *act = nullptr;      // systems of the current broad phase (see BroadArgs)
   int64_t n_bricks = 0;
   int32_t pmax = 0;            // candidates k_pairs stages in LDS per workgroup
+  int32_t xwindows = 1;        // k_pairs searches staged rows in x windows
   size_t lds_limit = 0;        // LDS bytes a workgroup may use on this device
   size_t lds_cu = 0;           // LDS bytes of one CU
   int pairs_grid = 0;
@@ -329,15 +331,16 @@ static int64_t make_grid(const vb_params &p, SysDev &S) {
 
 // LDS and grid of the pair search for the current row width and threads per
 // workgroup.  LDS: rows plus staged candidates of 24 bytes; half the CU's LDS per
-// workgroup (two resident per CU), less 5 KB for the kernel's static arrays,
-// unless wide rows need more; never beyond the device limit.  Grid: the pair
+// workgroup (two resident per CU), less the kernel's static arrays
+// (PAIRS_STATIC_LDS), unless wide rows need more; never beyond the device limit.  Grid: the pair
 // search walks the bricks grid-stride with exactly the workgroups that are
 // resident at once, so that at any time they work on one window of consecutive
 // bricks, whose staged neighbourhoods overlap in L2.
 static void size_pair_search(vb_ctx *c) {
   const int64_t rows = (int64_t)pairs_lds_bytes(c->width, 0, c->pairs_t);
-  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - 6144,
-                                           std::max<int64_t>((int64_t)c->lds_cu / 2 - 5120, rows + 1024 * 24));
+  const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - PAIRS_STATIC_LDS,
+                                           std::max<int64_t>((int64_t)c->lds_cu / 2 - PAIRS_STATIC_LDS,
+                                                             rows + 1024 * 24));
   c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
   c->pairs_grid = (int)std::max<int64_t>(
       1, std::min<int64_t>(c->n_bricks,
@@ -419,8 +422,8 @@ static vb_status alloc_bins(vb_ctx *c, int32_t cap) {
   if (c->bins_so) (void)hipFree(c->bins_so);
   c->bins_bp = nullptr;
   c->bins_so = nullptr;
-  HIP_OK(c, dalloc(&c->bins_bp, c->n_cells * (int64_t)cap));
-  HIP_OK(c, dalloc(&c->bins_so, c->n_cells * (int64_t)cap));
+  HIP_OK(c, dalloc(&c->bins_bp, c->n_cells * (int64_t)cap + BIN_PAD));
+  HIP_OK(c, dalloc(&c->bins_so, c->n_cells * (int64_t)cap + BIN_PAD));
   c->bin_cap = cap;
   return VB_OK;
 }
@@ -452,6 +455,7 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   if (env) c->xcd_remap = std::min(2, std::max(0, std::atoi(env))), c->shape_fixed = 1;
   if ((env = std::getenv("VBUF_STEP_UNROLL"))) c->step_unroll = std::atoi(env), c->shape_fixed = 1;
   if ((env = std::getenv("VBUF_GRAPHS"))) c->use_graphs = std::atoi(env) != 0;
+  if ((env = std::getenv("VBUF_PAIR_WINDOWS"))) c->xwindows = std::atoi(env) != 0;
   vb_status st = VB_OK;
   auto bail = [&](vb_status code) {
     g_create_error = c->msg;
@@ -475,9 +479,14 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   c->n_cu = prop.multiProcessorCount;
   c->lds_limit = prop.sharedMemPerBlock;
   c->lds_cu = std::max(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
+  for (int nt : {256, 384, 512})
+    if (pairs_static_lds(nt) < 0 || pairs_static_lds(nt) > PAIRS_STATIC_LDS) {
+      c->msg = "pair search: static LDS above its reserve";
+      return bail(VB_EDEVICE);
+    }
   // rows are sorted in LDS: the widest row any pair-search shape (up to 512
   // threads per workgroup) can hold
-  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - 6144 - pairs_lds_bytes(0, 0, 512)) /
+  c->row_limit = (int32_t)std::min<size_t>(MAX_ROW, (c->lds_limit - PAIRS_STATIC_LDS - pairs_lds_bytes(0, 0, 512)) /
                                                          (512 * sizeof(uint16_t)));
   c->row_limit -= c->row_limit % ROW_GROUP;  // rows are stored in whole groups
   c->n_sys = n_sys;
@@ -729,6 +738,7 @@ static BroadArgs broad_args(vb_ctx *c, int force, int relist) {
   a.act = c->act;
   a.n_bricks = c->n_bricks;
   a.pmax = c->pmax;
+  a.xwindows = c->xwindows;
   a.inv = c->inv;
   a.flags = c->flags;
   a.go = c->go;

@@ -28,6 +28,10 @@ constexpr int MAX_CAND = 32;      // row entries per segment of the step kernel'
 constexpr int CONTACT_UNROLL = 2; // candidates whose records are requested together (4 waves/SIMD)
 constexpr int PAIRS_T = 384;      // threads of a pair-search workgroup (one brick): a brick of
                                   // 64 cells at about 5 particles per cell in one pass
+constexpr int BIN_PAD = 8;        // entries allocated past the last cell bin (read, never used)
+constexpr int XRES = 8;           // sub-bins per cell edge along x that bound the pair
+                                  // search's candidate windows
+constexpr int PAIRS_STATIC_LDS = 13 * 1024;  // bound on the pair search's static LDS (bytes)
 // Rows of the Verlet list are stored in groups of ROW_GROUP entries: group g of
 // slot k is the int4 at nbr[(g * stride + k) * ROW_GROUP], entry q is component
 // q % ROW_GROUP of group q / ROW_GROUP.  One 16-byte load fetches four entries of
@@ -138,6 +142,7 @@ struct BroadArgs {
   int32_t *act;
   int64_t n_bricks;
   int32_t pmax;         // candidates a workgroup can stage in LDS
+  int32_t xwindows;     // 1: staged rows are searched in x windows (0: whole rows)
   int32_t *inv;         // [slots] inv[p_off + orig] = local slot
   const int32_t *flags; // [2][n_sys] validity-violation flags; slot (step & 1) is read
   int32_t *go;          // [n_sys] 1 if the system runs a broad phase at this step

@@ -813,6 +813,14 @@ __device__ __forceinline__ void pair_scan_range(const float4 *s_pos, int e, int 
   if (e < e1) pair_test4<true, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
 }
 
+// Sub-bin of a coordinate along a line of box cells, floor((x - xl) * qinv)
+// clamped to [-1, nq] (NaN gives -1).  Every operation is non-decreasing in x,
+// so the sub-bin is too: the candidate windows of the pair search rest on it.
+__device__ __forceinline__ int xsub(float x, float xl, float qinv, int nq) {
+  const float f = floorf((x - xl) * qinv);
+  return (int)fminf(fmaxf(f, -1.f), (float)nq);
+}
+
 // Alg. 1 on the extended spheres, one workgroup per brick of cells: the bins of
 // the brick and of the cells within `ring` cells around it are staged in LDS,
 // then every particle of the brick is tested against the particles of the cells
@@ -821,8 +829,14 @@ __device__ __forceinline__ void pair_scan_range(const float4 *s_pos, int e, int 
 // the row is then sorted by original index and stored as slots.  A
 // neighbourhood too full for LDS is read from the bins directly, by half the
 // workgroup.
+// Staged cells are ordered by x sub-bin (XRES per cell edge), so each line of box
+// cells along x is too, and a table gives where each sub-bin starts.  A
+// particle tests, in each (dz, dy) row, only the sub-bins within
+// R_NL,i + eps + max R_NL (plus a rounding margin) of its x: a window that holds
+// every entry the test can pass, so the rows are the same as over the whole
+// range, for about half the tests.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pairs(BroadArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int HALF = NT / 2;
   const int W = a.width;
@@ -835,8 +849,11 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
   __shared__ int s_cnt[8 * 8 * 8];
   __shared__ int s_off[8 * 8 * 8 + 1];
   __shared__ int s_home[BRICK * BRICK * BRICK + 1];
+  __shared__ uint16_t s_xstart[8 * 8 * (8 * XRES + 1)];  // [line][sub-bin]: first staged entry
+  __shared__ int s_rmax, s_nowin;  // largest staged R_NL (float bits); windows off
   static_assert(BRICK * BRICK * BRICK == WAVE, "one lane per cell of a brick");
   static_assert(2 * NT >= 8 * 8 * 8, "two box cells per thread in the prefix");
+  static_assert(XRES == 8, "a cell's sub-bin counts are eight nibbles of one word");
   const int tid = threadIdx.x;
   int any = 0;
   for (int s = tid; s < a.n_sys; s += NT) any |= a.go[s];
@@ -855,6 +872,7 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
     const int bx = lb % S.nb[0], by = (lb / S.nb[0]) % S.nb[1], bz = lb / (S.nb[0] * S.nb[1]);
     const int ox = bx * BRICK - r, oy = by * BRICK - r, oz = bz * BRICK - r;
     // occupancy of every cell of the neighbourhood box (0 outside the grid)
+    if (tid == 0) s_rmax = 0, s_nowin = a.xwindows ? 0 : 1;
     for (int v = tid; v < V; v += NT) {
       const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
       int n = 0;
@@ -887,31 +905,93 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
     }
     __syncthreads();
     const bool staged = s_off[V] <= a.pmax;
+    // x frame of the sub-bins: box cell t of a line holds sub-bins [t, t + 1) * XRES
+    const int NQ = E * XRES;
+    const float xl = (float)(S.lo[0] + (double)ox / S.inv_edge[0]);
+    const float qinv = (float)(S.inv_edge[0] * XRES);
     if (staged) {
+      // largest R_NL as float bits: every positive float orders as its bits,
+      // and a NaN or infinite radius orders above every finite one
+      int nowin = 0, rmax = 0;
       for (int v = tid; v < V; v += NT) {
-        const int n = s_cnt[v];
-        if (n == 0) continue;
-        const int cx = ox + v % E, cy = oy + (v / E) % E, cz = oz + v / (E * E);
+        const int n = s_cnt[v], off = s_off[v], t = v % E, qlo = t * XRES;
+        uint16_t *tab = s_xstart + (v / E) * (NQ + 1);
+        if (t == E - 1) tab[NQ] = (uint16_t)(off + n);
+        if (n == 0 || n > 8) {  // the starts of a cell without windows: its first entry
+#pragma unroll
+          for (int qq = 0; qq < XRES; ++qq) tab[qlo + qq] = (uint16_t)off;
+          if (n == 0) continue;
+        }
+        const int cx = ox + t, cy = oy + (v / E) % E, cz = oz + v / (E * E);
         const int64_t base = (S.c_off + cell_key(S, cx, cy, cz)) * a.bin_cap;
-        const int off = s_off[v];
-        for (int i0 = 0; i0 < n; i0 += 8) {  // eight loads in flight per thread
+        if (n <= 8) {
+          // the whole cell in registers, written in sub-bin order (a counting
+          // sort over the cell's XRES sub-bins, ties in bin order): nibble q of
+          // `below` counts the entries below sub-bin qlo + q, nibble q of `seen`
+          // those of sub-bin qlo + q written so far.  Within a cell, x order
+          // implies sub-bin order, since xsub is non-decreasing in x.
           float4 bp[8];
           int2 so[8];
+          const float4 *pb = a.bins_bp + base;
+          const int2 *ps = a.bins_so + base;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {  // entries past n re-read entry n - 1
-            const int64_t q = base + min(i0 + u, n - 1);
-            bp[u] = a.bins_bp[q];
-            so[u] = a.bins_so[q];
+          for (int u = 0; u < 8; ++u) {  // entries at or past n: read, not used
+            bp[u] = pb[u];               // (the bins are padded by BIN_PAD)
+            so[u] = ps[u];
+          }
+          // every load above is issued before any of them is used (one round
+          // trip, not one for the positions and one for the indices)
+          __builtin_amdgcn_sched_barrier(0);
+          int rb[8];
+          uint32_t below = 0, seen = 0;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            // a sub-bin outside the cell's (a position outside the grid, rounded
+            // across a face, or NaN) turns the brick's windows off; entries past
+            // n count in the last sub-bin, which adds to no nibble
+            const bool in = u < n;
+            const int bq = xsub(bp[u].x, xl, qinv, NQ) - qlo;
+            nowin |= (in && (unsigned)bq >= (unsigned)XRES) ? 1 : 0;
+            rb[u] = in ? 4 * min(max(bq, 0), XRES - 1) : 4 * (XRES - 1);
+            below += 0x11111110u << rb[u];
+            rmax = max(rmax, in ? __float_as_int(bp[u].w) : 0);
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
-            if (i0 + u < n) {
-              s_pos[off + i0 + u] = bp[u];
-              s_key[off + i0 + u] = so[u].y;
-              s_slot[off + i0 + u] = so[u].x;
+            if (u < n) {
+              const int e = off + (int)(((below >> rb[u]) & 15u) + ((seen >> rb[u]) & 15u));
+              seen += 1u << rb[u];
+              s_pos[e] = bp[u];
+              s_key[e] = so[u].y;
+              s_slot[e] = so[u].x;
             }
+#pragma unroll
+          for (int qq = 0; qq < XRES; ++qq) tab[qlo + qq] = (uint16_t)(off + ((below >> (4 * qq)) & 15u));
+        } else {
+          // more than eight in the cell: staged in bin order, and the brick
+          // tests whole rows
+          nowin = 1;
+          for (int i0 = 0; i0 < n; i0 += 8) {  // eight loads in flight per thread
+            float4 bp[8];
+            int2 so[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {  // entries past n re-read entry n - 1
+              const int64_t q = base + min(i0 + u, n - 1);
+              bp[u] = a.bins_bp[q];
+              so[u] = a.bins_so[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (i0 + u < n) {
+                s_pos[off + i0 + u] = bp[u];
+                s_key[off + i0 + u] = so[u].y;
+                s_slot[off + i0 + u] = so[u].x;
+              }
+          }
         }
       }
+      if (rmax > 0) atomicMax(&s_rmax, rmax);
+      if (nowin) s_nowin = 1;
       __syncthreads();
     }
     const int H = s_home[WAVE];
@@ -934,6 +1014,16 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
           const float4 me = s_pos[me_e];
           const float reach = me.w + S.eps;
           k = S.p_off + s_slot[me_e];
+          // the sub-bins [q0, q1e) that can hold a partner: a pair that passes
+          // the test below lies within (R_NL,i + eps + R_NL,j)(1 + 2^-22) in x,
+          // and the margins also cover the rounding of x -+ bw
+          int q0 = 0, q1e = NQ;
+          const float rmx = __int_as_float(s_rmax);
+          if (s_nowin == 0 && rmx <= __FLT_MAX__) {
+            const float bw = (reach + rmx) * (1.f + 0x1p-19f) + fabsf(me.x) * 0x1p-21f;
+            q0 = max(xsub(me.x - bw, xl, qinv, NQ), 0);
+            q1e = min(xsub(me.x + bw, xl, qinv, NQ) + 1, NQ);
+          }
           // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
           // row of the neighbourhood are one contiguous range of staged entries.
           // The test has no branch: every entry is written at the row's end,
@@ -948,7 +1038,9 @@ __global__ __launch_bounds__(NT) void k_pairs(BroadArgs a) {
           for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy) {
               const int vrow = v + (dz * E + dy) * E;
-              const int e0 = s_off[vrow - r], e1 = s_off[vrow + r + 1];
+              const uint16_t *tab = s_xstart + ((iz + dz) * E + iy + dy) * (NQ + 1);
+              const int e0 = max(s_off[vrow - r], (int)tab[q0]);
+              const int e1 = min(s_off[vrow + r + 1], (int)tab[q1e]);
               if (dz == 0 && dy == 0)
                 pair_scan_range<true, NT>(s_pos, e0, e1, me_e, me, reach, myrow, wend, wofs);
               else
@@ -1490,6 +1582,16 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
 size_t pairs_lds_bytes(int width, int pmax, int nt) {
   return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * 2 * sizeof(int32_t) +
          (size_t)nt * (size_t)(width + 1) * sizeof(uint16_t);
+}
+
+// Static LDS of the pair search with nt threads (bytes); -1 if not known.
+int64_t pairs_static_lds(int nt) {
+  hipFuncAttributes fa;
+  hipError_t e;
+  if (nt == 256) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_pairs<256>));
+  else if (nt == 512) e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_pairs<512>));
+  else e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(k_pairs<384>));
+  return e == hipSuccess ? (int64_t)fa.sharedSizeBytes : -1;
 }
 
 // Threads per pair-search workgroup the library is built for.

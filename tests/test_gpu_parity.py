@@ -715,11 +715,9 @@ def test_particles_at_rest_on_gpu():
     assert np.array_equal(lst, ref)
 
 
-def test_cell_face_placements_broad_phase():
-    """Particles placed exactly on cell faces and corners (dyadic coordinates on
-    the cell grid): the GPU list contains every pair the oracle's brute-force
-    broad phase finds with a margin, and nothing beyond the eps band."""
-    import paper_2208_13770_amd as vb
+def _face_system():
+    """Particles placed exactly on cell faces, edges, corners and centres
+    (dyadic coordinates on a grid of 16 cells per axis)."""
     rng = np.random.default_rng(11)
     edge = 2.0 ** -4                      # 16 cells per axis: L_C (1 + 2^-10) + 2 eps <= 1/16
     L_C = (edge - 4.5e-6) / (1 + 2.0 ** -10)
@@ -741,6 +739,15 @@ def test_cell_face_placements_broad_phase():
     s.params = p
     s.n = n
     s.meta = {"v_max": 1e-3}
+    return s
+
+
+def test_cell_face_placements_broad_phase():
+    """Particles placed exactly on cell faces and corners (dyadic coordinates on
+    the cell grid): the GPU list contains every pair the oracle's brute-force
+    broad phase finds with a margin, and nothing beyond the eps band."""
+    s = _face_system()
+    p = s.params
     xh, vh, rc, invm = host_arrays([s])
     with GpuRun([s]) as g:
         g.pairs(0, 1)
@@ -757,6 +764,77 @@ def test_cell_face_placements_broad_phase():
     assert len(sure) > 100
     assert not [t for t in map(tuple, sure.tolist()) if t not in gset]
     assert (margin(gl) > -1e-6).all()
+
+
+def _windows_case(case):
+    """(systems, overrides, steps) of the pair-window comparison below."""
+    if case == "M1":
+        return synth.config_systems("M1", seed=3), {}, 200
+    if case == "literal_cap":
+        return [synth.lattice_system(10, 9, 7, 3, 2, 0.2, 21)], {"cap_mode": 1}, 150
+    if case in ("H125", "SILO"):
+        return synth.config_systems(case, scale=0.3), {}, 300
+    if case == "faces":
+        return [_face_system()], {}, 100
+    if case == "big_cells":
+        # a twentieth of the particles moved next to others, so that some cells
+        # hold more than eight (their bricks test whole rows; no steps run)
+        s = synth.lattice_system(20, 20, 16, 4, 2, 0.1, seed=9)
+        rng = np.random.default_rng(6)
+        idx = rng.choice(s.n, size=s.n // 20, replace=False)
+        to = rng.choice(s.n, size=len(idx), replace=False)
+        a = s.params["cell_size"] / 1.7
+        s.pos_r[idx, :3] = (s.pos_r[to, :3] + rng.uniform(-0.3, 0.3, size=(len(idx), 3)) * a
+                            ).astype(np.float32)
+        return [s], {}, 0
+    if case == "outside":
+        # a tenth of the particles moved out of the box across each face, so that
+        # they are binned into border cells they do not lie in (no steps run)
+        s = synth.lattice_system(20, 18, 16, 4, 2, 0.2, 8)
+        rng = np.random.default_rng(4)
+        lo, hi = np.asarray(s.params["lo"], float), np.asarray(s.params["hi"], float)
+        idx = rng.choice(s.n, size=s.n // 10, replace=False)
+        ax = rng.integers(0, 3, size=len(idx))
+        side = rng.integers(0, 2, size=len(idx))
+        d = rng.uniform(0.0, 2.0 * s.params["cell_size"], size=len(idx))
+        s.pos_r[idx, ax] = np.where(side == 0, lo[ax] - d, hi[ax] + d).astype(np.float32)
+        return [s], {}, 0
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["M1", "literal_cap", "H125", "SILO", "faces", "big_cells",
+                                  "outside"])
+def test_pair_windows_leave_the_lists_unchanged(case):
+    """The pair search tests, in each row of cells, only the x sub-bins within
+    reach of the particle.  Against the search over whole rows (windows off
+    through the environment) the Verlet list is the same pair for pair at the
+    first broad phase and at the end, and the run is bit-identical with the same
+    records: lattice, two-ring (literal cap), hopper and silo systems, particles
+    on cell faces (on sub-bin bounds too), cells of more than eight particles,
+    and particles outside the box, binned into border cells they do not lie in."""
+    import os
+    systems, ov, steps = _windows_case(case)
+    out = {}
+    for win in ("0", "1"):
+        os.environ["VBUF_PAIR_WINDOWS"] = win
+        try:
+            with GpuRun(systems, ov) as g:
+                g.pairs(0, 1)
+                first, _ = g.pairs(0, 0)
+                hist = g.run(steps) if steps else None
+                last, _ = g.pairs(0, 0)
+                x, v, _ = g.state()
+        finally:
+            del os.environ["VBUF_PAIR_WINDOWS"]
+        out[win] = (first, last, x, v, hist)
+        say(f"  {case}, windows {win}: {len(first)} pairs at the first broad phase, "
+            f"{len(last)} at step {steps}")
+    (f0, l0, x0, v0, h0), (f1, l1, x1, v1, h1) = out["0"], out["1"]
+    assert len(f0) > 0
+    assert np.array_equal(f0, f1) and np.array_equal(l0, l1)
+    assert np.array_equal(x0, x1) and np.array_equal(v0, v1)
+    if steps:
+        assert_same_records(h0[0], h1[0], case)
 
 
 @pytest.mark.parametrize("radii", ["polydisperse", "monodisperse", "tiny"])
