@@ -330,7 +330,7 @@ static int64_t make_grid(const vb_params &p, SysDev &S) {
 }
 
 // LDS and grid of the pair search for the current row width and threads per
-// workgroup.  LDS: rows plus staged candidates of 24 bytes; half the CU's LDS per
+// workgroup.  LDS: rows plus staged candidates of 20 bytes; half the CU's LDS per
 // workgroup (two resident per CU), less the kernel's static arrays
 // (PAIRS_STATIC_LDS), unless wide rows need more; never beyond the device limit.  Grid: the pair
 // search walks the bricks grid-stride with exactly the workgroups that are
@@ -340,8 +340,8 @@ static void size_pair_search(vb_ctx *c) {
   const int64_t rows = (int64_t)pairs_lds_bytes(c->width, 0, c->pairs_t);
   const int64_t budget = std::min<int64_t>((int64_t)c->lds_limit - PAIRS_STATIC_LDS,
                                            std::max<int64_t>((int64_t)c->lds_cu / 2 - PAIRS_STATIC_LDS,
-                                                             rows + 1024 * 24));
-  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 24));
+                                                             rows + 1024 * 20));
+  c->pmax = (int32_t)std::max<int64_t>(0, std::min<int64_t>(4096, (budget - rows) / 20));
   c->pairs_grid = (int)std::max<int64_t>(
       1, std::min<int64_t>(c->n_bricks,
                            (int64_t)pairs_blocks_per_cu(c->width, c->pmax, c->pairs_t) * c->n_cu));

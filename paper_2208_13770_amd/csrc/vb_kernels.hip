@@ -758,8 +758,8 @@ __device__ __forceinline__ void row_write_sorted(const uint16_t *s_row, const in
 // The same for a row of any length up to W: insertion sort in LDS.
 template <int NT>
 __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int32_t *s_key,
-                                                     const int32_t *s_slot, int n, int32_t *nbr,
-                                                     int64_t stride, int64_t k) {
+                                                     const int32_t *__restrict__ inv, int n,
+                                                     int32_t *nbr, int64_t stride, int64_t k) {
   for (int i = 1; i < n; ++i) {
     const int e = s_row[i * NT + threadIdx.x];
     const int32_t key = s_key[e];
@@ -772,7 +772,7 @@ __device__ __forceinline__ void row_write_sorted_lds(uint16_t *s_row, const int3
     }
     s_row[j * NT + threadIdx.x] = (uint16_t)e;
   }
-  for (int q = 0; q < n; ++q) nbr[row_index(stride, k, q)] = s_slot[s_row[q * NT + threadIdx.x]];
+  for (int q = 0; q < n; ++q) nbr[row_index(stride, k, q)] = inv[s_key[s_row[q * NT + threadIdx.x]]];
 }
 
 // The FP32 inclusion test of Alg. 1 on the extended spheres, |x_i - x_j| <=
@@ -821,6 +821,103 @@ __device__ __forceinline__ int xsub(float x, float xl, float qinv, int nq) {
   return (int)fminf(fmaxf(f, -1.f), (float)nq);
 }
 
+// Stages one cell of n <= NM entries (positions pb[0..n), original indices at
+// po[0], po[2], ...) at LDS entries off.. in x sub-bin order, and writes the
+// starts of the cell's sub-bins [qlo, qlo + XRES) into tab.  The whole cell is
+// loaded into registers at once (entries at or past n are read, not used: the
+// bins are padded by BIN_PAD), then placed by a counting sort over the
+// sub-bins, ties in bin order: byte q of `below` counts the entries below
+// sub-bin qlo + q, byte q of `seen` those of sub-bin qlo + q placed so far.
+// Within a cell, x order implies sub-bin order, since xsub is non-decreasing in
+// x.  A sub-bin outside the cell's (a position outside the grid, rounded
+// across a face, or NaN) sets nowin; rmax takes the largest R_NL as float bits.
+template <int NM>
+__device__ __forceinline__ void stage_cell(const float4 *pb, const int32_t *po, int n, int off,
+                                           int qlo, float xl, float qinv, int nq, float4 *s_pos,
+                                           int32_t *s_key, uint16_t *tab, int &nowin, int &rmax) {
+  static_assert(NM <= BIN_PAD && NM < 256, "loads stay inside the padded bins; byte counters");
+  float4 bp[NM];
+  int32_t og[NM];
+#pragma unroll
+  for (int u = 0; u < NM; ++u) {
+    bp[u] = pb[u];
+    og[u] = po[2 * u];
+  }
+  // every load above is issued before any of them is used (one round trip,
+  // not one for the positions and one for the indices)
+  __builtin_amdgcn_sched_barrier(0);
+  int rb[NM];
+  uint64_t below = 0, seen = 0;
+#pragma unroll
+  for (int u = 0; u < NM; ++u) {
+    // entries past n count in the last sub-bin, which adds to no byte
+    const bool in = u < n;
+    const int bq = xsub(bp[u].x, xl, qinv, nq) - qlo;
+    nowin |= (in && (unsigned)bq >= (unsigned)XRES) ? 1 : 0;
+    rb[u] = in ? 8 * min(max(bq, 0), XRES - 1) : 8 * (XRES - 1);
+    below += 0x0101010101010100ull << rb[u];
+    rmax = max(rmax, in ? __float_as_int(bp[u].w) : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < NM; ++u)
+    if (u < n) {
+      const int e = off + (int)(((below >> rb[u]) & 255u) + ((seen >> rb[u]) & 255u));
+      seen += 1ull << rb[u];
+      s_pos[e] = bp[u];
+      s_key[e] = og[u];
+    }
+#pragma unroll
+  for (int qq = 0; qq < XRES; ++qq) tab[qlo + qq] = (uint16_t)(off + (int)((below >> (8 * qq)) & 255u));
+}
+
+// The same for a cell of 8 < n <= 64 entries, in chunks of eight: a first pass
+// counts the sub-bins, a second places the entries (its loads mostly hit the
+// cache).  Bins are padded by BIN_PAD >= 8, so a chunk's reads past n stay
+// inside the allocation.
+__device__ __forceinline__ void stage_cell_chunks(const float4 *pb, const int32_t *po, int n, int off,
+                                                  int qlo, float xl, float qinv, int nq,
+                                                  float4 *s_pos, int32_t *s_key, uint16_t *tab,
+                                                  int &nowin, int &rmax) {
+  static_assert(BIN_PAD >= 8, "a chunk reads up to seven entries past the cell");
+  uint64_t below = 0, seen = 0;
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    float xw[8][2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      xw[u][0] = pb[i0 + u].x;
+      xw[u][1] = pb[i0 + u].w;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = i0 + u < n;
+      const int bq = xsub(xw[u][0], xl, qinv, nq) - qlo;
+      nowin |= (in && (unsigned)bq >= (unsigned)XRES) ? 1 : 0;
+      below += in ? (0x0101010101010100ull << (8 * min(max(bq, 0), XRES - 1))) : 0ull;
+      rmax = max(rmax, in ? __float_as_int(xw[u][1]) : 0);
+    }
+  }
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    float4 bp[8];
+    int32_t og[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      bp[u] = pb[i0 + u];
+      og[u] = po[2 * (i0 + u)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < n) {
+        const int rb = 8 * min(max(xsub(bp[u].x, xl, qinv, nq) - qlo, 0), XRES - 1);
+        const int e = off + (int)(((below >> rb) & 255u) + ((seen >> rb) & 255u));
+        seen += 1ull << rb;
+        s_pos[e] = bp[u];
+        s_key[e] = og[u];
+      }
+  }
+#pragma unroll
+  for (int qq = 0; qq < XRES; ++qq) tab[qlo + qq] = (uint16_t)(off + (int)((below >> (8 * qq)) & 255u));
+}
+
 // Alg. 1 on the extended spheres, one workgroup per brick of cells: the bins of
 // the brick and of the cells within `ring` cells around it are staged in LDS,
 // then every particle of the brick is tested against the particles of the cells
@@ -842,8 +939,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const int W = a.width;
   float4 *s_pos = reinterpret_cast<float4 *>(lds);                          // [pmax + 4]
   int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax + 4);         // [pmax]
-  int32_t *s_slot = s_key + a.pmax;                                         // [pmax]
-  unsigned char *rows = reinterpret_cast<unsigned char *>(s_slot + a.pmax);
+  unsigned char *rows = reinterpret_cast<unsigned char *>(s_key + a.pmax);
   uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W + 1][NT]
   int32_t *s_row32 = reinterpret_cast<int32_t *>(rows);                     // [W][HALF]
   __shared__ int s_cnt[8 * 8 * 8];
@@ -853,7 +949,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   __shared__ int s_rmax, s_nowin;  // largest staged R_NL (float bits); windows off
   static_assert(BRICK * BRICK * BRICK == WAVE, "one lane per cell of a brick");
   static_assert(2 * NT >= 8 * 8 * 8, "two box cells per thread in the prefix");
-  static_assert(XRES == 8, "a cell's sub-bin counts are eight nibbles of one word");
+  static_assert(XRES == 8, "a cell's sub-bin counts are the eight bytes of one word");
   const int tid = threadIdx.x;
   int any = 0;
   for (int s = tid; s < a.n_sys; s += NT) any |= a.go[s];
@@ -917,59 +1013,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int n = s_cnt[v], off = s_off[v], t = v % E, qlo = t * XRES;
         uint16_t *tab = s_xstart + (v / E) * (NQ + 1);
         if (t == E - 1) tab[NQ] = (uint16_t)(off + n);
-        if (n == 0 || n > 8) {  // the starts of a cell without windows: its first entry
+        if (n == 0 || n > 64) {  // the starts of a cell without windows: its first entry
 #pragma unroll
           for (int qq = 0; qq < XRES; ++qq) tab[qlo + qq] = (uint16_t)off;
           if (n == 0) continue;
         }
         const int cx = ox + t, cy = oy + (v / E) % E, cz = oz + v / (E * E);
         const int64_t base = (S.c_off + cell_key(S, cx, cy, cz)) * a.bin_cap;
+        const float4 *pb = a.bins_bp + base;
+        const int32_t *po = reinterpret_cast<const int32_t *>(a.bins_so + base) + 1;
         if (n <= 8) {
-          // the whole cell in registers, written in sub-bin order (a counting
-          // sort over the cell's XRES sub-bins, ties in bin order): nibble q of
-          // `below` counts the entries below sub-bin qlo + q, nibble q of `seen`
-          // those of sub-bin qlo + q written so far.  Within a cell, x order
-          // implies sub-bin order, since xsub is non-decreasing in x.
-          float4 bp[8];
-          int2 so[8];
-          const float4 *pb = a.bins_bp + base;
-          const int2 *ps = a.bins_so + base;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {  // entries at or past n: read, not used
-            bp[u] = pb[u];               // (the bins are padded by BIN_PAD)
-            so[u] = ps[u];
-          }
-          // every load above is issued before any of them is used (one round
-          // trip, not one for the positions and one for the indices)
-          __builtin_amdgcn_sched_barrier(0);
-          int rb[8];
-          uint32_t below = 0, seen = 0;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            // a sub-bin outside the cell's (a position outside the grid, rounded
-            // across a face, or NaN) turns the brick's windows off; entries past
-            // n count in the last sub-bin, which adds to no nibble
-            const bool in = u < n;
-            const int bq = xsub(bp[u].x, xl, qinv, NQ) - qlo;
-            nowin |= (in && (unsigned)bq >= (unsigned)XRES) ? 1 : 0;
-            rb[u] = in ? 4 * min(max(bq, 0), XRES - 1) : 4 * (XRES - 1);
-            below += 0x11111110u << rb[u];
-            rmax = max(rmax, in ? __float_as_int(bp[u].w) : 0);
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (u < n) {
-              const int e = off + (int)(((below >> rb[u]) & 15u) + ((seen >> rb[u]) & 15u));
-              seen += 1u << rb[u];
-              s_pos[e] = bp[u];
-              s_key[e] = so[u].y;
-              s_slot[e] = so[u].x;
-            }
-#pragma unroll
-          for (int qq = 0; qq < XRES; ++qq) tab[qlo + qq] = (uint16_t)(off + ((below >> (4 * qq)) & 15u));
+          stage_cell<8>(pb, po, n, off, qlo, xl, qinv, NQ, s_pos, s_key, tab, nowin, rmax);
+        } else if (n <= 64) {
+          stage_cell_chunks(pb, po, n, off, qlo, xl, qinv, NQ, s_pos, s_key, tab, nowin, rmax);
         } else {
-          // more than eight in the cell: staged in bin order, and the brick
-          // tests whole rows
+          // more than 64 in the cell: staged in bin order, and the brick tests
+          // whole rows
           nowin = 1;
           for (int i0 = 0; i0 < n; i0 += 8) {  // eight loads in flight per thread
             float4 bp[8];
@@ -985,7 +1044,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
               if (i0 + u < n) {
                 s_pos[off + i0 + u] = bp[u];
                 s_key[off + i0 + u] = so[u].y;
-                s_slot[off + i0 + u] = so[u].x;
               }
           }
         }
@@ -1013,7 +1071,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const int me_e = s_off[v] + i;  // this particle's staged entry
           const float4 me = s_pos[me_e];
           const float reach = me.w + S.eps;
-          k = S.p_off + s_slot[me_e];
+          k = S.p_off + a.inv[S.p_off + s_key[me_e]];  // the slot, from the original index
           // the sub-bins [q0, q1e) that can hold a partner: a pair that passes
           // the test below lies within (R_NL,i + eps + R_NL,j)(1 + 2^-22) in x,
           // and the margins also cover the rounding of x -+ bw
@@ -1057,7 +1115,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           else if (!__any(kept > 32))
             row_write_sorted<32, NT>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
           else
-            row_write_sorted_lds<NT>(s_row16, s_key, s_slot, kept, a.nbr, a.stride, k);
+            row_write_sorted_lds<NT>(s_row16, s_key, inv, kept, a.nbr, a.stride, k);
         } else {
           const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
           const float4 me = a.bins_bp[mybase + i];
@@ -1576,11 +1634,11 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
 }
 
 // Dynamic LDS of k_pairs<nt>: staged candidates (position and R_NL with four
-// spare entries for the scan's reads past a range, original index, slot) and the
+// spare entries for the scan's reads past a range, and original index) and the
 // rows (W + 1 rows of 16-bit staged indices, the last a spare for full rows, or
 // W rows of 32-bit keys for half the threads in the fallback path).
 size_t pairs_lds_bytes(int width, int pmax, int nt) {
-  return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * 2 * sizeof(int32_t) +
+  return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * sizeof(int32_t) +
          (size_t)nt * (size_t)(width + 1) * sizeof(uint16_t);
 }
 

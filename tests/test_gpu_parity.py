@@ -778,15 +778,19 @@ def _windows_case(case):
         return [_face_system()], {}, 100
     if case == "big_cells":
         # a twentieth of the particles moved next to others, so that some cells
-        # hold more than eight (their bricks test whole rows; no steps run)
+        # hold 9 to 11 (staged in two passes), and 70 into one cell (staged
+        # without windows: its brick tests whole rows); rows of ~80 entries
         s = synth.lattice_system(20, 20, 16, 4, 2, 0.1, seed=9)
         rng = np.random.default_rng(6)
-        idx = rng.choice(s.n, size=s.n // 20, replace=False)
-        to = rng.choice(s.n, size=len(idx), replace=False)
-        a = s.params["cell_size"] / 1.7
-        s.pos_r[idx, :3] = (s.pos_r[to, :3] + rng.uniform(-0.3, 0.3, size=(len(idx), 3)) * a
-                            ).astype(np.float32)
-        return [s], {}, 0
+        idx = rng.choice(s.n, size=s.n // 20 + 70, replace=False)
+        to = rng.choice(s.n, size=len(idx) - 70, replace=False)
+        L = s.params["cell_size"]
+        a = L / 1.7
+        s.pos_r[idx[70:], :3] = (s.pos_r[to, :3] + rng.uniform(-0.3, 0.3, size=(len(to), 3)) * a
+                                 ).astype(np.float32)
+        s.pos_r[idx[:70], :3] = ((np.array([5, 6, 4]) + rng.uniform(0.05, 0.95, size=(70, 3))) * L
+                                 ).astype(np.float32)
+        return [s], {}, 1  # one step: vb_run grows the bins and rows first
     if case == "outside":
         # a tenth of the particles moved out of the box across each face, so that
         # they are binned into border cells they do not lie in (no steps run)
@@ -810,8 +814,9 @@ def test_pair_windows_leave_the_lists_unchanged(case):
     through the environment) the Verlet list is the same pair for pair at the
     first broad phase and at the end, and the run is bit-identical with the same
     records: lattice, two-ring (literal cap), hopper and silo systems, particles
-    on cell faces (on sub-bin bounds too), cells of more than eight particles,
-    and particles outside the box, binned into border cells they do not lie in."""
+    on cell faces (on sub-bin bounds too), cells of 9 to 11 particles and one
+    of 70, and particles outside the box, binned into border cells they do not
+    lie in."""
     import os
     systems, ov, steps = _windows_case(case)
     out = {}
@@ -819,9 +824,13 @@ def test_pair_windows_leave_the_lists_unchanged(case):
         os.environ["VBUF_PAIR_WINDOWS"] = win
         try:
             with GpuRun(systems, ov) as g:
-                g.pairs(0, 1)
-                first, _ = g.pairs(0, 0)
-                hist = g.run(steps) if steps else None
+                if case == "big_cells":  # the bins and rows overflow at first
+                    hist = g.run(steps)
+                    first, _ = g.pairs(0, 0)
+                else:
+                    g.pairs(0, 1)
+                    first, _ = g.pairs(0, 0)
+                    hist = g.run(steps) if steps else None
                 last, _ = g.pairs(0, 0)
                 x, v, _ = g.state()
         finally:
