@@ -156,7 +156,7 @@ struct vb_ctx {
   int32_t width = 0;
   int32_t *bin_count = nullptr;
   float4 *bins_bp = nullptr;
-  int2 *bins_so = nullptr;
+  int32_t *bins_og = nullptr;
   int32_t bin_cap = 0;
   int32_t *cellid = nullptr, *inv = nullptr;
   int32_t *act = nullptr;      // systems of the current broad phase (see BroadArgs)
@@ -239,7 +239,7 @@ static void free_all(vb_ctx *c) {
   void *ptrs[] = {c->sys_d, c->tile_sys, c->xs[0], c->xs[1], c->vs[0], c->vs[1], c->ri[0], c->ri[1],
                   c->orig[0], c->orig[1], c->posq[0],
                   c->posq[1], c->rrange, c->hist[0], c->hist[1], c->hcnt[0], c->hcnt[1], c->hist_snap,
-                  c->hcnt_snap, c->snap_x, c->snap_v, c->snap_ri, c->snap_orig, c->snap_bp, c->snap_flags, c->bp, c->bp_alt, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_so,
+                  c->hcnt_snap, c->snap_x, c->snap_v, c->snap_ri, c->snap_orig, c->snap_bp, c->snap_flags, c->bp, c->bp_alt, c->cnt, c->nbr, c->bin_count, c->bins_bp, c->bins_og,
                   c->act, c->cellid, c->inv,
                   c->cell_count, c->cell_start, c->block_sum, c->inslot, c->perm0, c->flags,
                   c->go, c->overflow, c->err, c->stats, c->rebuilt_ring, c->hist_d,
@@ -419,11 +419,11 @@ static vb_status alloc_hist_tables(vb_ctx *c, int32_t cap) {
 
 static vb_status alloc_bins(vb_ctx *c, int32_t cap) {
   if (c->bins_bp) (void)hipFree(c->bins_bp);
-  if (c->bins_so) (void)hipFree(c->bins_so);
+  if (c->bins_og) (void)hipFree(c->bins_og);
   c->bins_bp = nullptr;
-  c->bins_so = nullptr;
+  c->bins_og = nullptr;
   HIP_OK(c, dalloc(&c->bins_bp, c->n_cells * (int64_t)cap + BIN_PAD));
-  HIP_OK(c, dalloc(&c->bins_so, c->n_cells * (int64_t)cap + BIN_PAD));
+  HIP_OK(c, dalloc(&c->bins_og, c->n_cells * (int64_t)cap + BIN_PAD));
   c->bin_cap = cap;
   return VB_OK;
 }
@@ -733,7 +733,7 @@ static BroadArgs broad_args(vb_ctx *c, int force, int relist) {
   a.width = c->width;
   a.bin_count = c->bin_count;
   a.bins_bp = c->bins_bp;
-  a.bins_so = c->bins_so;
+  a.bins_og = c->bins_og;
   a.bin_cap = c->bin_cap;
   a.act = c->act;
   a.n_bricks = c->n_bricks;
@@ -854,7 +854,7 @@ static uint64_t graph_key(const vb_ctx *c, int cur) {
   const uint64_t parts[] = {(uint64_t)(uintptr_t)c->xs[cur], (uint64_t)(uintptr_t)c->nbr,
                             (uint64_t)(uintptr_t)c->ri[c->scur], (uint64_t)(uintptr_t)c->orig[c->scur],
                             (uint64_t)(uintptr_t)c->bp,
-                            (uint64_t)(uintptr_t)c->bins_bp, (uint64_t)(uintptr_t)c->bins_so,
+                            (uint64_t)(uintptr_t)c->bins_bp, (uint64_t)(uintptr_t)c->bins_og,
                             (uint64_t)(uintptr_t)c->hist[cur], (uint64_t)(uintptr_t)c->hist[cur ^ 1],
                             (uint64_t)(uintptr_t)c->stream, (uint64_t)c->width, (uint64_t)c->pmax,
                             (uint64_t)c->bin_cap, (uint64_t)c->hcap, (uint64_t)c->step_unroll,

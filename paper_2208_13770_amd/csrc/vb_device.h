@@ -134,7 +134,7 @@ struct BroadArgs {
   int32_t width;        // row capacity W
   int32_t *bin_count;   // [cells] particles binned per cell (zeroed by the step kernel)
   float4 *bins_bp;      // [cells][bin_cap] x0 and R_NL of the binned particles
-  int2 *bins_so;        // [cells][bin_cap] (local slot, original index) of the binned particles
+  int32_t *bins_og;     // [cells][bin_cap] original index of the binned particles (slots via inv)
   int32_t bin_cap;
   // the systems that take part in this broad phase, written by the binning for
   // the pair search: act[0] = their count A, act[1 + i] = system i of them (in
@@ -143,7 +143,7 @@ struct BroadArgs {
   int64_t n_bricks;
   int32_t pmax;         // candidates a workgroup can stage in LDS
   int32_t xwindows;     // 1: staged rows are searched in x windows (0: whole rows)
-  int32_t *inv;         // [slots] inv[p_off + orig] = local slot
+  int32_t *inv;         // [slots] inv[p_off + orig] = local slot (written when force or relist is set)
   const int32_t *flags; // [2][n_sys] validity-violation flags; slot (step & 1) is read
   int32_t *go;          // [n_sys] 1 if the system runs a broad phase at this step
   int32_t *rebuilt_ring;  // [STATS_RING][n_sys]

@@ -421,6 +421,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     // flush then requests the FP64 positions and the velocities of the listed
     // partners together, runs the exact test and adds the contact forces in
     // list (= row) order.
+    // candidates whose records the flush requests together: one with friction,
+    // whose contact law holds more registers
+    constexpr int CU = FRIC ? 1 : CONTACT_UNROLL;
     for (int q0 = 0; q0 < rowlen; q0 += MAX_CAND) {
       const int q1 = min(rowlen, q0 + MAX_CAND);
       int nc = 0;
@@ -440,17 +443,17 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) j[u] = jn[u];
       }
-      for (int i0 = 0; i0 < nc; i0 += CONTACT_UNROLL) {
-        int32_t jj[CONTACT_UNROLL];
-        X3 o[CONTACT_UNROLL];
-        V3 ov[CONTACT_UNROLL];
-        float orc[CONTACT_UNROLL];
-        uint32_t oo[CONTACT_UNROLL];
+      for (int i0 = 0; i0 < nc; i0 += CU) {
+        int32_t jj[CU];
+        X3 o[CU];
+        V3 ov[CU];
+        float orc[CU];
+        uint32_t oo[CU];
 #pragma unroll
-        for (int u = 0; u < CONTACT_UNROLL; ++u)
+        for (int u = 0; u < CU; ++u)
           jj[u] = i0 + u < nc ? s_cand[(i0 + u) * TILE + threadIdx.x] : 0;
 #pragma unroll
-        for (int u = 0; u < CONTACT_UNROLL; ++u)
+        for (int u = 0; u < CU; ++u)
           if (i0 + u < nc) {
             const int64_t q = S.p_off + jj[u];
             o[u] = xs[q];
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
             oo[u] = FRIC ? a.orig[q] : 0u;
           }
 #pragma unroll
-        for (int u = 0; u < CONTACT_UNROLL; ++u)
+        for (int u = 0; u < CU; ++u)
           if (i0 + u < nc) contact(o[u], orc[u], ov[u], oo[u]);
       }
     }
@@ -682,13 +685,17 @@ __global__ __launch_bounds__(TILE) void k_bin(BroadArgs a) {
         key = S.c_off + cell_of(S, (double)b.x, (double)b.y, (double)b.z);
       }
       orig = a.orig[k];
-      a.inv[S.p_off + orig] = local;
+      // slots move only when the state is set, the storage sorted or a snapshot
+      // restored, and each of these forces a broad phase or a relist of every
+      // system: the inverse permutation is rewritten then, not at every broad
+      // phase (a scattered 4-byte write per particle)
+      if (a.force || a.relist) a.inv[S.p_off + orig] = local;
     }
     const int slot = wave_bin_slot(a.bin_count, key);
     if (key >= 0) {
       if (slot < a.bin_cap) {
         a.bins_bp[key * a.bin_cap + slot] = b;
-        a.bins_so[key * a.bin_cap + slot] = make_int2(local, (int)orig);
+        a.bins_og[key * a.bin_cap + slot] = (int32_t)orig;
       } else {
         atomicMax(&a.overflow[1], slot + 1);
       }
@@ -821,8 +828,8 @@ __device__ __forceinline__ int xsub(float x, float xl, float qinv, int nq) {
   return (int)fminf(fmaxf(f, -1.f), (float)nq);
 }
 
-// Stages one cell of n <= NM entries (positions pb[0..n), original indices at
-// po[0], po[2], ...) at LDS entries off.. in x sub-bin order, and writes the
+// Stages one cell of n <= NM entries (positions pb[0..n), original indices
+// po[0..n)) at LDS entries off.. in x sub-bin order, and writes the
 // starts of the cell's sub-bins [qlo, qlo + XRES) into tab.  The whole cell is
 // loaded into registers at once (entries at or past n are read, not used: the
 // bins are padded by BIN_PAD), then placed by a counting sort over the
@@ -841,7 +848,7 @@ __device__ __forceinline__ void stage_cell(const float4 *pb, const int32_t *po, 
 #pragma unroll
   for (int u = 0; u < NM; ++u) {
     bp[u] = pb[u];
-    og[u] = po[2 * u];
+    og[u] = po[u];
   }
   // every load above is issued before any of them is used (one round trip,
   // not one for the positions and one for the indices)
@@ -902,7 +909,7 @@ __device__ __forceinline__ void stage_cell_chunks(const float4 *pb, const int32_
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       bp[u] = pb[i0 + u];
-      og[u] = po[2 * (i0 + u)];
+      og[u] = po[i0 + u];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -1021,7 +1028,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const int cx = ox + t, cy = oy + (v / E) % E, cz = oz + v / (E * E);
         const int64_t base = (S.c_off + cell_key(S, cx, cy, cz)) * a.bin_cap;
         const float4 *pb = a.bins_bp + base;
-        const int32_t *po = reinterpret_cast<const int32_t *>(a.bins_so + base) + 1;
+        const int32_t *po = a.bins_og + base;
         if (n <= 8) {
           stage_cell<8>(pb, po, n, off, qlo, xl, qinv, NQ, s_pos, s_key, tab, nowin, rmax);
         } else if (n <= 64) {
@@ -1032,18 +1039,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           nowin = 1;
           for (int i0 = 0; i0 < n; i0 += 8) {  // eight loads in flight per thread
             float4 bp[8];
-            int2 so[8];
+            int32_t og[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {  // entries past n re-read entry n - 1
               const int64_t q = base + min(i0 + u, n - 1);
               bp[u] = a.bins_bp[q];
-              so[u] = a.bins_so[q];
+              og[u] = a.bins_og[q];
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
               if (i0 + u < n) {
                 s_pos[off + i0 + u] = bp[u];
-                s_key[off + i0 + u] = so[u].y;
+                s_key[off + i0 + u] = og[u];
               }
           }
         }
@@ -1120,7 +1127,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           const int64_t mybase = (S.c_off + cell_key(S, ox + ix, oy + iy, oz + iz)) * a.bin_cap;
           const float4 me = a.bins_bp[mybase + i];
           const float reach = me.w + S.eps;
-          k = S.p_off + a.bins_so[mybase + i].x;
+          k = S.p_off + a.inv[S.p_off + a.bins_og[mybase + i]];
           for (int dz = -r; dz <= r; ++dz)
             for (int dy = -r; dy <= r; ++dy)
               for (int dx = -r; dx <= r; ++dx) {
@@ -1132,7 +1139,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 for (int e = 0; e < n2; ++e) {
                   if (v2 == v && e == i) continue;
                   if (within_reach(me, a.bins_bp[base + e], reach))
-                    count = row_insert(s_row32, HALF, count, W, a.bins_so[base + e].y);
+                    count = row_insert(s_row32, HALF, count, W, a.bins_og[base + e]);
                 }
               }
           const int kept = count < W ? count : W;
