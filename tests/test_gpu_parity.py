@@ -768,8 +768,10 @@ def test_cell_face_placements_broad_phase():
 
 def _windows_case(case):
     """(systems, overrides, steps) of the pair-window comparison below."""
-    if case == "M1":
+    if case in ("M1", "M1_256", "M1_512"):
         return synth.config_systems("M1", seed=3), {}, 200
+    if case in ("literal_cap_256", "literal_cap_512"):
+        return [synth.lattice_system(10, 9, 7, 3, 2, 0.2, 21)], {"cap_mode": 1}, 150
     if case == "literal_cap":
         return [synth.lattice_system(10, 9, 7, 3, 2, 0.2, 21)], {"cap_mode": 1}, 150
     if case in ("H125", "SILO"):
@@ -807,7 +809,8 @@ def _windows_case(case):
 
 
 @pytest.mark.parametrize("case", ["M1", "literal_cap", "H125", "SILO", "faces", "big_cells",
-                                  "outside"])
+                                  "outside", "M1_256", "M1_512", "literal_cap_256",
+                                  "literal_cap_512"])
 def test_pair_windows_leave_the_lists_unchanged(case):
     """The pair search tests, in each row of cells, only the x sub-bins within
     reach of the particle.  Against the search over whole rows (windows off
@@ -816,7 +819,8 @@ def test_pair_windows_leave_the_lists_unchanged(case):
     records: lattice, two-ring (literal cap), hopper and silo systems, particles
     on cell faces (on sub-bin bounds too), cells of 9 to 11 particles and one
     of 70, and particles outside the box, binned into border cells they do not
-    lie in."""
+    lie in; the lattice and two-ring cases also with 256 and 512 threads per
+    pair-search workgroup."""
     import os
     systems, ov, steps = _windows_case(case)
     out = {}
@@ -824,6 +828,8 @@ def test_pair_windows_leave_the_lists_unchanged(case):
         os.environ["VBUF_PAIR_WINDOWS"] = win
         try:
             with GpuRun(systems, ov) as g:
+                if case.endswith(("_256", "_512")):  # other pair-search workgroup sizes
+                    vb.vb_set_launch(g.ctx, 8, 2, int(case[-3:]))
                 if case == "big_cells":  # the bins and rows overflow at first
                     hist = g.run(steps)
                     first, _ = g.pairs(0, 0)
