@@ -160,12 +160,14 @@ __device__ __forceinline__ QSelf posq_self(uint64_t q, float rc, float qinv32) {
 // Pre-test of a contact on coded positions: true whenever the exact FP64 test
 // of Eq. delta can be.  rlo_q and step_q are the radius code's origin and step
 // in grid steps.
-__device__ __forceinline__ bool posq_candidate(const QSelf &m, uint64_t o, float rlo_q,
+__device__ __forceinline__ bool posq_candidate(const QSelf &m, uint2 o, float rlo_q,
                                                float step_q) {
-  const float dx = (float)(m.x - (int)(o & QMASK));
-  const float dy = (float)(m.y - (int)((o >> QBITS) & QMASK));
-  const float dz = (float)(m.z - (int)((o >> (2 * QBITS)) & QMASK));
-  const uint32_t c = (uint32_t)(o >> 57);
+  // the code's two 32-bit words: x in bits 0-18 of the low word, y across the
+  // two, z in bits 6-24 of the high word, the radius code in its bits 25-31
+  const float dx = (float)(m.x - (int)(o.x & QMASK));
+  const float dy = (float)(m.y - (int)(__builtin_amdgcn_alignbit(o.y, o.x, QBITS) & QMASK));
+  const float dz = (float)(m.z - (int)((o.y >> (2 * QBITS - 32)) & QMASK));
+  const uint32_t c = o.y >> 25;
   const float reach = c == QFREE ? INFINITY : m.reach0 + __fmaf_rn((float)c, step_q, rlo_q);
   return __fmaf_rn(dx, dx, __fmaf_rn(dy, dy, dz * dz)) <= reach * reach;
 }
@@ -315,7 +317,6 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     // is used only if it lies below the row length.  With UNROLL a multiple of
     // ROW_GROUP the row is read a group (four entries) per load.
     const int64_t st = a.stride;
-    const int spec = min(UNROLL, a.width);
     int32_t j[UNROLL];
     // entries q .. q+UNROLL-1 (q a multiple of UNROLL) that lie below limit
     auto load_entries = [&](int q, int limit, int32_t *dst) {
@@ -330,6 +331,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
           dst[u] = q + u < limit ? nt_load(&a.nbr[row_index(st, k, q + u)]) : 0;
       }
     };
+    const int spec = min(UNROLL, a.width);
     load_entries(0, spec, j);
     const X3 me = xs[k];  // plain loads: the flushes of the neighbours gather them too
     const V3 mv = vs[k];
@@ -428,10 +430,14 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
       const int q1 = min(rowlen, q0 + MAX_CAND);
       int nc = 0;
       for (int q = q0; q < q1; q += UNROLL) {
-        uint64_t o[UNROLL];
+        // one gather per entry, issued for every lane: an entry past the
+        // segment reads the system's first code instead of its stale index, so
+        // no gather sits behind a branch and the compiler waits for each alone
+        // (the extra requests all hit one line)
+        uint2 o[UNROLL];
+        const uint2 *pq = reinterpret_cast<const uint2 *>(a.posq_cur) + S.p_off;
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-          if (q + u < q1) o[u] = a.posq_cur[S.p_off + j[u]];
+        for (int u = 0; u < UNROLL; ++u) o[u] = pq[q + u < q1 ? j[u] : 0];
         int32_t jn[UNROLL];
         load_entries(q + UNROLL, rowlen, jn);
 #pragma unroll
