@@ -120,14 +120,9 @@ __device__ __forceinline__ float radius_bound(float rlo, float step, uint32_t c)
   return __fmaf_rn((float)c, step, rlo);
 }
 
-__device__ __forceinline__ uint64_t posq_encode(const SysDev &S, float rlo, float rhi, double x,
-                                                double y, double z, float rc) {
-  const double lim = (double)QMASK;  // t < 2^19 - 1 keeps floor(t + 1/2) within 19 bits
-  const double tx = (x - S.qlo[0]) * S.qinv;
-  const double ty = (y - S.qlo[1]) * S.qinv;
-  const double tz = (z - S.qlo[2]) * S.qinv;
-  if (!(tx >= 0.0 && tx < lim && ty >= 0.0 && ty < lim && tz >= 0.0 && tz < lim))
-    return (uint64_t)QFREE << 57;
+// The radius code of R_C = rc on the range [rlo, rhi]: the smallest c <= 126
+// whose bound is at least rc, or QFREE if none is.
+__device__ __forceinline__ uint32_t radius_code(float rlo, float rhi, float rc) {
   uint32_t c = QFREE;
   const float step = radius_step(rlo, rhi);
   if (rc <= rlo) {
@@ -138,8 +133,25 @@ __device__ __forceinline__ uint64_t posq_encode(const SysDev &S, float rlo, floa
     while (c0 < 126u && radius_bound(rlo, step, c0) < rc) ++c0;
     if (radius_bound(rlo, step, c0) >= rc) c = c0;
   }
+  return c;
+}
+
+// The coded position of centre (x, y, z) with radius code c.
+__device__ __forceinline__ uint64_t posq_encode_c(const SysDev &S, double x, double y, double z,
+                                                  uint32_t c) {
+  const double lim = (double)QMASK;  // t < 2^19 - 1 keeps floor(t + 1/2) within 19 bits
+  const double tx = (x - S.qlo[0]) * S.qinv;
+  const double ty = (y - S.qlo[1]) * S.qinv;
+  const double tz = (z - S.qlo[2]) * S.qinv;
+  if (!(tx >= 0.0 && tx < lim && ty >= 0.0 && ty < lim && tz >= 0.0 && tz < lim))
+    return (uint64_t)QFREE << 57;
   const uint64_t qx = (uint32_t)(tx + 0.5), qy = (uint32_t)(ty + 0.5), qz = (uint32_t)(tz + 0.5);
   return qx | (qy << QBITS) | (qz << (2 * QBITS)) | ((uint64_t)c << 57);
+}
+
+__device__ __forceinline__ uint64_t posq_encode(const SysDev &S, float rlo, float rhi, double x,
+                                                double y, double z, float rc) {
+  return posq_encode_c(S, x, y, z, radius_code(rlo, rhi, rc));
 }
 
 // One side of the pre-test, decoded once per particle: grid coordinates and
@@ -338,7 +350,8 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const float2 mri = a.ri[k];
     const float mrc = mri.x;
     const float rlo = __int_as_float(a.rrange[s]), rhi = __int_as_float(a.rrange[a.n_sys + s]);
-    const QSelf mq = posq_self(posq_encode(S, rlo, rhi, me.x, me.y, me.z, mrc), mrc, S.qinv32);
+    const uint32_t mcode = radius_code(rlo, rhi, mrc);  // the same for both codes of this step
+    const QSelf mq = posq_self(posq_encode_c(S, me.x, me.y, me.z, mcode), mrc, S.qinv32);
     const float rlo_q = rlo * S.qinv32, step_q = radius_step(rlo, rhi) * S.qinv32;
     const float4 b = nt_load(&a.bp[k]);
     rowlen = nt_load(&a.cnt[k]);
@@ -541,7 +554,7 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     }
     nt_store24(&a.x_dst[k].x, xn[0], xn[1], xn[2]);
     nt_store24(&a.v_dst[k].vx, vn[0], vn[1], vn[2]);
-    __builtin_nontemporal_store(posq_encode(S, rlo, rhi, xn[0], xn[1], xn[2], mrc), &a.posq_dst[k]);
+    __builtin_nontemporal_store(posq_encode_c(S, xn[0], xn[1], xn[2], mcode), &a.posq_dst[k]);
     ke = 0.5 * (vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2]) / im;
     // Eq. update for the next step: straight-line displacement since the last
     // broad phase against the skin left after the cap (R_NL - R_C)
@@ -558,16 +571,18 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
   __shared__ int s_i[3][TILE / WAVE];
   __shared__ float s_x[TILE / WAVE];
   ke = wave_sum(ke);
-  rowlen = wave_sum(rowlen);
-  ncon = wave_sum(ncon);
-  viol = wave_sum(viol);
+  // row lengths and contacts summed together in the two halves of one word
+  // (each is at most 64 x MAX_ROW < 2^16 per wave); violators counted by ballot
+  static_assert(WAVE * MAX_ROW < (1 << 16), "a wave's row or contact sum fits 16 bits");
+  const int rc_sum = wave_sum(rowlen | (ncon << 16));
+  const int n_viol = (int)__popcll(__ballot(viol));
   excess = wave_max(excess);
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   if (lane == 0) {
     s_ke[w] = ke;
-    s_i[0][w] = rowlen;
-    s_i[1][w] = ncon;
-    s_i[2][w] = viol;
+    s_i[0][w] = rc_sum & 0xFFFF;
+    s_i[1][w] = rc_sum >> 16;
+    s_i[2][w] = n_viol;
     s_x[w] = excess;
   }
   __syncthreads();
