@@ -645,9 +645,9 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
   }
   if (!c->shape_fixed) {
     // the default shape keeps fewer partner gathers in flight per thread where
-    // the registers they take cost more than they hide: batches under 2^20
-    // particles (a few thousand tiles) and friction
-    if (c->any_friction || c->n_total < (int64_t)1 << 20) c->step_unroll = 4;
+    // they cost more than they hide: batches under 2^20 particles (a few
+    // thousand tiles)
+    if (c->n_total < (int64_t)1 << 20) c->step_unroll = 4;
     // a shape tuned earlier in this process for batches like this one
     std::lock_guard<std::mutex> lock(g_shapes_mutex);
     auto it = g_shapes.find(shape_key(c));

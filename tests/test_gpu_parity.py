@@ -1315,15 +1315,16 @@ def test_tile_orders_on_a_system_of_several_tile_groups():
     assert ref[2]["contacts"][0].sum() > 0
 
 
-def test_default_launch_shape_follows_batch_size_and_friction():
+def test_default_launch_shape_follows_batch_size():
     """A new context of a kind no tuner has seen starts from 8 gathers in flight
-    for batches of 2^20 particles and more, 4 below that or with friction, tile
-    order 2 and 384 pair-search threads."""
+    for batches of 2^20 particles and more (with or without friction), 4 below
+    that, tile order 2 and 384 pair-search threads."""
     import paper_2208_13770_amd as vb
     small = synth.lattice_system(24, 24, 16, 2, 1, 0.1, 22)
     large = synth.lattice_system(128, 128, 64, 8, 4, 0.1, 23)
     assert small.n < 2 ** 20 <= large.n
-    for s, ov, unroll in ((small, {}, 4), (small, _frictional(small), 4), (large, {}, 8)):
+    for s, ov, unroll in ((small, {}, 4), (small, _frictional(small), 4), (large, {}, 8),
+                          (large, _frictional(large), 8)):
         ctx = vb.vb_batch_create([dict(s.params, **ov)], [s.n])
         try:
             assert vb.vb_get_launch(ctx) == {"unroll": unroll, "xcd_order": 2, "pairs_threads": 384}
