@@ -814,22 +814,31 @@ __device__ __forceinline__ bool within_reach(const float4 &me, const float4 &o, 
 }
 
 // Four staged entries e..e+3 against the particle `me` (position and R_NL +
-// eps): each entry index is written at the row's end (offset wofs, capped at
-// the spare row wend), and the row grows by NT for each entry within
-// reach.  TAIL masks entries at or past e1; OWN masks the particle's own entry.
+// eps): each entry index is written at the row's end, and the row grows by NT
+// for each entry within reach.  wofs keeps the exact length (times NT); the
+// write position is capped once per group, at the first spare row wend (rows
+// W to W+3 are spare: a group adds at most three hits before its last write).
+// ix01 and ix23 hold the four entry indices as 16-bit pairs.  TAIL masks
+// entries at or past e1; OWN masks the particle's own entry.
 template <bool TAIL, bool OWN, int NT>
 __device__ __forceinline__ void pair_test4(const float4 *s_pos, int e, int e1, int me_e,
                                            const float4 &me, float reach, uint16_t *myrow,
-                                           unsigned wend, unsigned &wofs) {
+                                           unsigned wend, unsigned &wofs, uint32_t ix01,
+                                           uint32_t ix23) {
   const float4 o[4] = {s_pos[e], s_pos[e + 1], s_pos[e + 2], s_pos[e + 3]};
+  const uint16_t ix[4] = {(uint16_t)ix01, (uint16_t)(ix01 >> 16), (uint16_t)ix23,
+                          (uint16_t)(ix23 >> 16)};
+  uint16_t *const p0 = myrow + min(wofs, wend);
+  uint16_t *p = p0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     bool hit = within_reach(me, o[u], reach);
     if (TAIL) hit = hit && e + u < e1;
     if (OWN) hit = hit && e + u != me_e;
-    myrow[min(wofs, wend)] = (uint16_t)(e + u);
-    wofs += hit ? NT : 0;
+    *p = ix[u];
+    p += hit ? NT : 0;
   }
+  wofs += (unsigned)(p - p0);
 }
 
 // The staged range [e, e1): groups of four, the last one masked.
@@ -837,8 +846,13 @@ template <bool OWN, int NT>
 __device__ __forceinline__ void pair_scan_range(const float4 *s_pos, int e, int e1, int me_e,
                                                 const float4 &me, float reach, uint16_t *myrow,
                                                 unsigned wend, unsigned &wofs) {
-  for (; e + 4 <= e1; e += 4) pair_test4<false, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
-  if (e < e1) pair_test4<true, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs);
+  // entry indices are below 2^16 (at most 4096 are staged): no carry between
+  // the halves of a pair
+  uint32_t ix01 = (uint32_t)e | ((uint32_t)(e + 1) << 16);
+  uint32_t ix23 = (uint32_t)(e + 2) | ((uint32_t)(e + 3) << 16);
+  for (; e + 4 <= e1; e += 4, ix01 += 0x40004u, ix23 += 0x40004u)
+    pair_test4<false, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs, ix01, ix23);
+  if (e < e1) pair_test4<true, OWN, NT>(s_pos, e, e1, me_e, me, reach, myrow, wend, wofs, ix01, ix23);
 }
 
 // Sub-bin of a coordinate along a line of box cells, floor((x - xl) * qinv)
@@ -968,7 +982,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   float4 *s_pos = reinterpret_cast<float4 *>(lds);                          // [pmax + 4]
   int32_t *s_key = reinterpret_cast<int32_t *>(s_pos + a.pmax + 4);         // [pmax]
   unsigned char *rows = reinterpret_cast<unsigned char *>(s_key + a.pmax);
-  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W + 1][NT]
+  uint16_t *s_row16 = reinterpret_cast<uint16_t *>(rows);                   // [W + 4][NT]
   int32_t *s_row32 = reinterpret_cast<int32_t *>(rows);                     // [W][HALF]
   __shared__ int s_cnt[8 * 8 * 8];
   __shared__ int s_off[8 * 8 * 8 + 1];
@@ -1113,8 +1127,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           // box cells are numbered x fastest, so the 2r+1 cells of one (dz, dy)
           // row of the neighbourhood are one contiguous range of staged entries.
           // The test has no branch: every entry is written at the row's end,
-          // and the row grows only by the entries that pass (row W is a spare
-          // row for overflow).  Ranges are read four entries at a time; the
+          // and the row grows only by the entries that pass (rows W to W+3
+          // are spare rows for overflow).  Ranges are read four entries at a time; the
           // last group of a range is masked (reads past its end stay inside
           // the staged array, which has four spare entries), and only the
           // particle's own row of cells can hold the particle itself.
@@ -1663,11 +1677,11 @@ hipError_t launch_step(const StepArgs &a, int64_t n_tiles, int unroll, int frict
 
 // Dynamic LDS of k_pairs<nt>: staged candidates (position and R_NL with four
 // spare entries for the scan's reads past a range, and original index) and the
-// rows (W + 1 rows of 16-bit staged indices, the last a spare for full rows, or
-// W rows of 32-bit keys for half the threads in the fallback path).
+// rows (W + 4 rows of 16-bit staged indices, the last four spares for full rows,
+// or W rows of 32-bit keys for half the threads in the fallback path).
 size_t pairs_lds_bytes(int width, int pmax, int nt) {
   return (size_t)(pmax + 4) * sizeof(float4) + (size_t)pmax * sizeof(int32_t) +
-         (size_t)nt * (size_t)(width + 1) * sizeof(uint16_t);
+         (size_t)nt * (size_t)(width + 4) * sizeof(uint16_t);
 }
 
 // Static LDS of the pair search with nt threads (bytes); -1 if not known.
