@@ -135,7 +135,7 @@ typedef struct vb_step_record {
 
 typedef struct vb_ctx vb_ctx;
 
-/* Create a context for one system of n particles (n >= 0): the inputs of the
+/* Create a context for one system of n particles (0 <= n <= 2^29 - 256): the inputs of the
  * method as the paper states them, the skin factor K and time step dt (Sec. 4.1,
  * Eq. skin_formulus1), the uniform cell size L_C of the linked-cell grid
  * (Sec. 3.2, Alg. 1; Sec. 5.1, Eq. skin_formulus_mincell) and the contact model

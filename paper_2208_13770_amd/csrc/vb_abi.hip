@@ -259,7 +259,9 @@ static void free_all(vb_ctx *c) {
 
 static std::string check_params(const vb_params &p, int64_t n) {
   if (n < 0) return "n < 0";
-  if (n > (int64_t)INT32_MAX - TILE) return "n too large for one system";
+  // the step kernel addresses a system's 8-byte position codes with 32-bit
+  // byte offsets
+  if (n > ((int64_t)1 << 29) - TILE) return "n too large for one system (at most 2^29 - 256)";
   if (p.skin_mode < 0 || p.skin_mode > 3) return "skin_mode must be 0..3";
   if (p.cap_mode != 0 && p.cap_mode != 1) return "cap_mode must be 0 or 1";
   if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return "dt must be positive";

@@ -447,10 +447,13 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         // segment reads the system's first code instead of its stale index, so
         // no gather sits behind a branch and the compiler waits for each alone
         // (the extra requests all hit one line)
+        // (the system's codes from a base shared by the workgroup and a 32-bit
+        // byte offset: a system holds fewer than 2^28 particles)
         uint2 o[UNROLL];
-        const uint2 *pq = reinterpret_cast<const uint2 *>(a.posq_cur) + S.p_off;
+        const char *pq = reinterpret_cast<const char *>(a.posq_cur + S.p_off);
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) o[u] = pq[q + u < q1 ? j[u] : 0];
+        for (int u = 0; u < UNROLL; ++u)
+          o[u] = *reinterpret_cast<const uint2 *>(pq + (uint32_t)(q + u < q1 ? j[u] : 0) * 8u);
         int32_t jn[UNROLL];
         load_entries(q + UNROLL, rowlen, jn);
 #pragma unroll
@@ -497,12 +500,16 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
     const double pos[3] = {me.x, me.y, me.z};
     const double vel[3] = {mv.vx, mv.vy, mv.vz};
     double f[3] = {fx, fy, fz};
+    // the overlap R_C - t is positive exactly when R_C > t (a difference of
+    // doubles rounds to a positive value iff it is positive), so it is formed
+    // only for the faces a particle touches
+    const double rcd = (double)mrc;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double dlo = (double)mrc - (pos[ax] - S.lo[ax]);
-      if (dlo > 0.0) f[ax] += S.kn * dlo - S.gamma_n * vel[ax];
-      const double dhi = (double)mrc - (S.hi[ax] - pos[ax]);
-      if (dhi > 0.0) f[ax] -= S.kn * dhi - S.gamma_n * (-vel[ax]);
+      const double tlo = pos[ax] - S.lo[ax];
+      if (rcd > tlo) f[ax] += S.kn * (rcd - tlo) - S.gamma_n * vel[ax];
+      const double thi = S.hi[ax] - pos[ax];
+      if (rcd > thi) f[ax] -= S.kn * (rcd - thi) - S.gamma_n * (-vel[ax]);
     }
     // planar and cylindrical walls (instances for batches that have them: the
     // loops cost the step kernel time even when they run no iteration)
@@ -513,8 +520,8 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         const double *pl = S.planes[w];
         if (!(pos[2] > pl[4])) continue;
         const double sd = pl[0] * pos[0] + pl[1] * pos[1] + pl[2] * pos[2] - pl[3];
-        const double dw = (double)mrc - sd;
-        if (dw > 0.0) {
+        if (rcd > sd) {  // overlap R_C - sd positive
+          const double dw = rcd - sd;
           const double vn = vel[0] * pl[0] + vel[1] * pl[1] + vel[2] * pl[2];
           const double fm = S.kn * dw - S.gamma_n * vn;
           f[0] += fm * pl[0];
@@ -531,8 +538,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         if (!(pos[2] > cy[3])) continue;
         const double dx = pos[0] - cy[0], dy = pos[1] - cy[1];
         const double rho = sqrt(dx * dx + dy * dy);
-        const double dw = (double)mrc - (cy[2] - rho);
-        if (dw > 0.0 && rho > 0.0) {
+        const double tw = cy[2] - rho;
+        if (rcd > tw && rho > 0.0) {  // overlap R_C - (R - rho) positive
+          const double dw = rcd - tw;
           const double nx = -dx / rho, ny = -dy / rho;
           const double vn = vel[0] * nx + vel[1] * ny;
           const double fm = S.kn * dw - S.gamma_n * vn;

@@ -92,3 +92,15 @@ def test_create_refuses_a_margin_below_the_fp32_floor(eps):
     with pytest.raises(vb.VbError) as e:
         vb.vb_create(dict(s.params, eps=eps), s.n, stream=ctypes.c_void_p(0))
     assert e.value.code == vb.VB_EINVAL and "eps" in str(e.value)
+
+
+@pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")
+def test_create_refuses_a_system_beyond_2_29_particles():
+    """One system holds at most 2^29 - 256 particles (the step kernel addresses
+    its 8-byte position codes with 32-bit byte offsets); the count is checked
+    before any device call, so this runs without a GPU."""
+    import synth
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    with pytest.raises(vb.VbError) as e:
+        vb.vb_create(s.params, 2 ** 29 - 255, stream=ctypes.c_void_p(0))
+    assert e.value.code == vb.VB_EINVAL and "too large" in str(e.value)
