@@ -95,9 +95,8 @@ def copy_bandwidth(torch, nbytes=4 << 30):
 
 def default_shape(n, friction):
     """The library's launch shape for a new context (gathers in flight, tile
-    order, pair-search threads) that no tuner has seen; friction does not change
-    it."""
-    return (4 if n < 2 ** 20 else 8, 2, 384)
+    order, pair-search threads) that no tuner has seen."""
+    return (8 if friction and n >= 2 ** 20 else 4, 2, 384)
 
 
 def run_mode(vb, torch, systems, steps, warmup, overrides, timing, call_steps=500, repeats=1,

@@ -286,8 +286,8 @@ vb_status vb_get_pairs_noalloc(vb_ctx *ctx, int32_t sys, int32_t which, int32_t 
  * 0: launch order, 1: each of the 8 XCDs a contiguous range of tiles, 2: each
  * XCD runs of 32 consecutive tiles, the 8 runs of a group side by side) and the
  * threads of a pair-search workgroup (256, 384 or 512); a new context starts
- * from (8, 2, 384), or (4, 2, 384) for a batch of fewer than 2^20 particles, or
- * from the shape vb_tune chose for its kind.  Results, records and
+ * from (4, 2, 384), or (8, 2, 384) for a batch with friction of 2^20 particles
+ * or more, or from the shape vb_tune chose for its kind.  Results, records and
  * the schedule of broad phases do not depend on it (the steps are those of the
  * time loop of Sec. 3.1 whatever the shape), so it may change between any two
  * calls.  Errors: VB_EINVAL for a value outside those sets. */

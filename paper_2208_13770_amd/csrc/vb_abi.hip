@@ -646,10 +646,10 @@ extern "C" vb_status vb_batch_create(const vb_params *h_params, const int64_t *h
     return bail(VB_EDEVICE);
   }
   if (!c->shape_fixed) {
-    // the default shape keeps fewer partner gathers in flight per thread where
-    // they cost more than they hide: batches under 2^20 particles (a few
-    // thousand tiles)
-    if (c->n_total < (int64_t)1 << 20) c->step_unroll = 4;
+    // the default shape keeps 4 partner gathers in flight per thread, where the
+    // step kernel runs five waves per SIMD; 8 with friction on batches of 2^20
+    // particles or more, whose step kernel holds more registers (four waves)
+    if (!(c->any_friction && c->n_total >= (int64_t)1 << 20)) c->step_unroll = 4;
     // a shape tuned earlier in this process for batches like this one
     std::lock_guard<std::mutex> lock(g_shapes_mutex);
     auto it = g_shapes.find(shape_key(c));

@@ -24,7 +24,9 @@ constexpr int MAX_BIN = 256;      // largest cell-bin capacity
 constexpr int MAX_HIST = 64;      // largest friction history per particle (contacts)
 constexpr int SCAN_ITEMS = 16;    // cells per thread in the block-level scans
 constexpr int BRICK = 4;          // cells per brick edge: cells are numbered brick by brick
-constexpr int MAX_CAND = 32;      // row entries per segment of the step kernel's two-pass scan
+constexpr int MAX_CAND = 24;      // row entries per segment of the step kernel's two-pass scan
+                                  // (24 KB of LDS candidates: five workgroups per CU)
+static_assert(MAX_CAND % 8 == 0, "segments start on a whole step of the largest unroll");
 constexpr int CONTACT_UNROLL = 2; // candidates whose records are requested together (4 waves/SIMD)
 constexpr int PAIRS_T = 384;      // threads of a pair-search workgroup (one brick): a brick of
                                   // 64 cells at about 5 particles per cell in one pass

@@ -1316,14 +1316,14 @@ def test_tile_orders_on_a_system_of_several_tile_groups():
 
 
 def test_default_launch_shape_follows_batch_size():
-    """A new context of a kind no tuner has seen starts from 8 gathers in flight
-    for batches of 2^20 particles and more (with or without friction), 4 below
-    that, tile order 2 and 384 pair-search threads."""
+    """A new context of a kind no tuner has seen starts from 4 gathers in flight,
+    8 for a batch with friction of 2^20 particles and more, tile order 2 and 384
+    pair-search threads."""
     import paper_2208_13770_amd as vb
     small = synth.lattice_system(24, 24, 16, 2, 1, 0.1, 22)
     large = synth.lattice_system(128, 128, 64, 8, 4, 0.1, 23)
     assert small.n < 2 ** 20 <= large.n
-    for s, ov, unroll in ((small, {}, 4), (small, _frictional(small), 4), (large, {}, 8),
+    for s, ov, unroll in ((small, {}, 4), (small, _frictional(small), 4), (large, {}, 4),
                           (large, _frictional(large), 8)):
         ctx = vb.vb_batch_create([dict(s.params, **ov)], [s.n])
         try:
