@@ -18,7 +18,7 @@ def host_arrays(systems):
             pos[:, 3].astype(np.float64), vel[:, 3].astype(np.float64))
 
 
-class GpuRun:
+class GpuSession:
     """One context over a list of systems (a batch when more than one)."""
 
     def __init__(self, systems, overrides=None):
@@ -65,7 +65,7 @@ class GpuRun:
 
 
 def gpu_trajectory(systems, steps, **overrides):
-    with GpuRun(systems, overrides) as g:
+    with GpuSession(systems, overrides) as g:
         hist = g.run(steps)
         x, v, half = g.state()
     return x, v, hist

@@ -17,7 +17,7 @@ import pytest
 import oracle
 import paper_2208_13770_amd as vb
 import synth
-from tests._gpu import GpuRun, gpu_trajectory, host_arrays, say
+from tests._gpu import GpuSession, gpu_trajectory, host_arrays, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def m2():
 def test_m2_full_size_parity_with_oracle(m2):
     s = m2
     say(f"M2 full size: N={s.n}, {STEPS} steps, GPU then oracle")
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         hg = g.run(STEPS)
         xg, vg, _ = g.state()
         n_list = vb.vb_get_pairs(g.ctx, 0, 0)

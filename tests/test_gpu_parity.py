@@ -21,7 +21,7 @@ import pytest
 import oracle
 import paper_2208_13770_amd as vb
 import synth
-from tests._gpu import GpuRun, gpu_trajectory, host_arrays, say
+from tests._gpu import GpuSession, gpu_trajectory, host_arrays, say
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +76,7 @@ def test_m1_parity_with_oracle(seed):
     """The small workload (16,384 particles, 200 steps, K = 200): GPU vs oracle."""
     s = synth.config_systems("M1", seed=seed)[0]
     say(f"M1 seed {seed}: N={s.n}, 200 steps")
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         hg = g.run(200)
         xg, vg, _ = g.state()
         n_list = vb.vb_get_pairs(g.ctx, 0, 0)
@@ -126,7 +126,7 @@ def test_verlet_list_matches_oracle_broad_phase():
     the GPU list, and every GPU pair lies within 1e-6 of the inclusion bound."""
     s = synth.config_systems("M1", seed=5)[0]
     x, v, rc, invm = host_arrays([s])
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         say("list at step 0")
         g.pairs(0, 1)  # runs the step-0 broad phase
         gl, _ = g.pairs(0, 0)
@@ -153,7 +153,7 @@ def test_contacts_equal_brute_force_after_run():
     Eq. delta) equals brute force over all pairs at the GPU's own positions."""
     s = synth.config_systems("M1", seed=6)[0]
     _, _, rc, _ = host_arrays([s])
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         say("contacts after 150 steps")
         g.run(150)
         xg, _, _ = g.state()
@@ -172,7 +172,7 @@ def test_pair_export_into_a_short_buffer():
     import torch
     import paper_2208_13770_amd as vb
     s = synth.config_systems("M1", seed=6)[0]
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         g.run(40)
         full, fd = g.pairs(0, 0)
         n = len(full)
@@ -239,7 +239,7 @@ def test_ragged_and_empty_systems_in_one_batch():
             s = synth.lattice_system(a, b, c, 1, 1, 0.3, 100 + i)
         systems.append(s)
     say("ragged batch", [s.n for s in systems])
-    with GpuRun(systems) as g:
+    with GpuSession(systems) as g:
         h = g.run(80)
         xg, vg, _ = g.state()
     off = 0
@@ -271,7 +271,7 @@ def test_row_overflow_is_regrown():
     s = synth.config_systems("M1", seed=7)[0]
     say("row overflow")
     xw, vw, hw = gpu_trajectory([s], 100, max_neighbors=64)
-    with GpuRun([s], {"max_neighbors": 2}) as g:
+    with GpuSession([s], {"max_neighbors": 2}) as g:
         hn = g.run(100)
         xn, vn, _ = g.state()
         assert g.info()["row_width"] > 2
@@ -291,7 +291,7 @@ def test_overflow_stops_a_long_call_early():
     say("overflow in a long call")
     n = 1100
     xw, vw, hw = gpu_trajectory([s], n, max_neighbors=64)
-    with GpuRun([s], {"max_neighbors": 2}) as g:
+    with GpuSession([s], {"max_neighbors": 2}) as g:
         vb.vb_set_timing(g.ctx, 1)
         h = g.run(n)
         pt = vb.vb_phase_times(g.ctx)
@@ -311,11 +311,11 @@ def test_checkpoint_resume_bitwise():
     s = synth.config_systems("M1", seed=8)[0]
     say("checkpoint/resume")
     xa, va, _ = gpu_trajectory([s], 200)
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         g.run(120)
         x1, v1, half = g.state()
         assert half
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         vb.vb_set_state(g.ctx, torch.from_numpy(x1).cuda(), torch.from_numpy(v1).cuda(), g.rc,
                         g.invm, v_is_half_step=True)
         g.run(80)
@@ -342,11 +342,11 @@ def test_verlet_state_checkpoint_resumes_the_schedule(case, n1, n2):
         s = synth.config_systems("M1", seed=12)[0]
         ov = _frictional(s) if case == "M1 friction" else {}
     say(f"Verlet-state checkpoint: {case}, N={s.n}")
-    with GpuRun([s], ov) as g:
+    with GpuSession([s], ov) as g:
         ha = g.run(n1 + n2)
         xa, va, _ = g.state()
     x0r = torch.empty((s.n, 4), dtype=torch.float32, device="cuda")
-    with GpuRun([s], ov) as g:
+    with GpuSession([s], ov) as g:
         h1 = g.run(n1)
         x1, v1, half = g.state()
         pending, step = vb.vb_get_verlet_state(g.ctx, x0r)
@@ -356,7 +356,7 @@ def test_verlet_state_checkpoint_resumes_the_schedule(case, n1, n2):
             partner = torch.empty((s.n, need), dtype=torch.int32, device="cuda")
             spring = torch.empty((s.n, need, 3), dtype=torch.float64, device="cuda")
             vb.vb_get_history(g.ctx, partner, spring)
-    with GpuRun([s], ov) as g:
+    with GpuSession([s], ov) as g:
         vb.vb_set_state(g.ctx, torch.from_numpy(x1).cuda(), torch.from_numpy(v1).cuda(), g.rc,
                         g.invm, v_is_half_step=True)
         vb.vb_set_verlet_state(g.ctx, x0r, pending, step)
@@ -379,7 +379,7 @@ def test_verlet_state_input_is_checked():
     import paper_2208_13770_amd as vb
     s = synth.config_systems("M1", scale=0.5, seed=2)[0]
     x0r = torch.empty((s.n, 4), dtype=torch.float32, device="cuda")
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         with pytest.raises(vb.VbError) as e:  # no list before the first step
             vb.vb_get_verlet_state(g.ctx, x0r)
         assert e.value.code == vb.VB_EINVAL
@@ -420,10 +420,10 @@ def test_overflow_late_in_a_call_runs_again_from_a_snapshot():
     s.params["g"] = (0.0, 0.0, float(np.float32(-3.25e-6 * a / dt ** 2)))
     n = 560
     say("late overflow in one call")
-    with GpuRun([s], {"max_neighbors": 32}) as g:
+    with GpuSession([s], {"max_neighbors": 32}) as g:
         hw = g.run(n)
         xw, vw, _ = g.state()
-    with GpuRun([s], {"max_neighbors": 8}) as g:
+    with GpuSession([s], {"max_neighbors": 8}) as g:
         hn = g.run(n)
         xn, vn, _ = g.state()
         assert g.info()["row_width"] > 8
@@ -564,7 +564,7 @@ def test_changing_K_mid_run_changes_nothing():
     s = synth.config_systems("M1", seed=5)[0]
     say("K changed between calls: 200 -> 10 -> 5000 -> 0 -> 100")
     xr, vr, hr = gpu_trajectory([s], 160, skin_mode=2)
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         for K, n in ((200.0, 40), (10.0, 30), (5000.0, 40), (0.0, 20), (100.0, 30)):
             vb.vb_set_K(g.ctx, K)
             g.run(n)
@@ -702,7 +702,7 @@ def test_particles_at_rest_on_gpu():
     s.pos_r[:, :3] = (idx + 1.0) * h
     s.pos_r[:, 3] = 0.5 * h                           # neighbours exactly touching
     x, v, rc, invm = host_arrays([s])
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         hist = g.run(60)
         xo, vo, _ = g.state()
         lst, _ = g.pairs(0, 0)
@@ -731,7 +731,7 @@ def _face_system():
          "skin_uniform": 0.0, "eps": 2e-6, "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1e3,
          "gamma_n": 0.0, "g": (0, 0, 0), "max_neighbors": 64}
 
-    class Sys:  # the minimal system object GpuRun needs
+    class Sys:  # the minimal system object GpuSession needs
         pass
     s = Sys()
     s.pos_r = np.concatenate([x, R[:, None]], axis=1).astype(np.float32)
@@ -749,7 +749,7 @@ def test_cell_face_placements_broad_phase():
     s = _face_system()
     p = s.params
     xh, vh, rc, invm = host_arrays([s])
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         g.pairs(0, 1)
         gl, _ = g.pairs(0, 0)
     rnl, _ = oracle.rebuild_radii(p, vh, rc)
@@ -827,7 +827,7 @@ def test_pair_windows_leave_the_lists_unchanged(case):
     for win in ("0", "1"):
         os.environ["VBUF_PAIR_WINDOWS"] = win
         try:
-            with GpuRun(systems, ov) as g:
+            with GpuSession(systems, ov) as g:
                 if case.endswith(("_256", "_512")):  # other pair-search workgroup sizes
                     vb.vb_set_launch(g.ctx, 8, 2, int(case[-3:]))
                 if case == "big_cells":  # the bins and rows overflow at first
@@ -888,7 +888,7 @@ def test_contact_pretest_at_near_touching_distances(radii):
          "skin_uniform": 0.0, "eps": 2e-6, "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": 1e3,
          "gamma_n": 0.0, "g": (0, 0, 0), "max_neighbors": 32}
 
-    class Sys:  # the minimal system object GpuRun needs
+    class Sys:  # the minimal system object GpuSession needs
         pass
     s = Sys()
     s.pos_r = np.concatenate([x, rc[:, None]], axis=1).astype(np.float32)
@@ -901,7 +901,7 @@ def test_contact_pretest_at_near_touching_distances(radii):
     say(f"pre-test at near-touching distances ({radii}): {n} particles, {brute0} contacts at step 0")
     assert 0.3 * m < brute0 < 0.7 * m
     steps = 6
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         h = g.run(steps)[0]
         xg, vg, _ = g.state()
     xo, vo, ho, _ = oracle_run(s, steps)
@@ -945,7 +945,7 @@ def test_long_rows_sorted_like_short_ones():
     s = synth.lattice_system(18, 18, 18, 3, 2, 0.2, 5, cell_factor=2.2, K=5000.0,
                              max_neighbors=64)
     say(f"long rows: N={s.n}, 120 steps, K=5000 vs no buffer")
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         g.run(1)
         pairs, _ = g.pairs(0, 0)
     deg = np.bincount(pairs.ravel(), minlength=s.n)
@@ -974,10 +974,10 @@ def test_graph_replay_equals_eager_launches(name, scale, friction):
     say(f"graph replay vs eager launches: {name} N={s.n}, friction {friction}")
     os.environ["VBUF_GRAPHS"] = "0"
     try:
-        eager = GpuRun([s], ov)
+        eager = GpuSession([s], ov)
     finally:
         del os.environ["VBUF_GRAPHS"]
-    graph = GpuRun([s], ov)
+    graph = GpuSession([s], ov)
     try:
         for call in range(5):
             he, hg = eager.run(70), graph.run(70)
@@ -1002,7 +1002,7 @@ def test_checkpoint_resume_with_friction_history_bitwise():
     fr = _frictional(s)
     say(f"checkpoint/resume with friction: N={s.n}")
     xa, va, _ = gpu_trajectory([s], 200, **fr)
-    with GpuRun([s], fr) as g:
+    with GpuSession([s], fr) as g:
         g.run(120)
         x1, v1, half = g.state()
         assert half
@@ -1020,7 +1020,7 @@ def test_checkpoint_resume_with_friction_history_bitwise():
     assert (p[:, -1] == -1).all() and (p >= -1).all()
     say(f"  {int((p >= 0).sum())} contacts carried, at most {need} per particle")
     xt, vt = torch.from_numpy(x1).cuda(), torch.from_numpy(v1).cuda()
-    with GpuRun([s], fr) as g:
+    with GpuSession([s], fr) as g:
         vb.vb_set_state(g.ctx, xt, vt, g.rc, g.invm, v_is_half_step=True)
         g.pairs(0, 1)  # runs the storage sort first: the history follows the particles
         vb.vb_set_history(g.ctx, partner, spring)
@@ -1030,7 +1030,7 @@ def test_checkpoint_resume_with_friction_history_bitwise():
             vb.vb_set_history(g.ctx, partner, spring)
         assert e.value.code == vb.VB_EINVAL
     assert np.array_equal(xa, xb) and np.array_equal(va, vb2)
-    with GpuRun([s], fr) as g:
+    with GpuSession([s], fr) as g:
         vb.vb_set_state(g.ctx, xt, vt, g.rc, g.invm, v_is_half_step=True)
         g.run(80)
         xc, _, _ = g.state()
@@ -1045,10 +1045,10 @@ def test_history_input_is_checked():
     say("history input checks")
     partner = torch.full((s.n, 3), -1, dtype=torch.int32, device="cuda")
     spring = torch.zeros((s.n, 3, 3), dtype=torch.float64, device="cuda")
-    with GpuRun([s]) as g:  # no friction
+    with GpuSession([s]) as g:  # no friction
         with pytest.raises(vb.VbError):
             vb.vb_set_history(g.ctx, partner, spring)
-    with GpuRun([s], fr) as g:
+    with GpuSession([s], fr) as g:
         vb.vb_set_history(g.ctx, partner, spring)  # an empty history is fine
         for bad in ([5, 5], [7, 3], [0, s.n], [1, -1, 2]):
             q = partner.clone()
@@ -1163,7 +1163,7 @@ def test_forced_rebuild_timing_and_info():
     s = synth.config_systems("M1", seed=11)[0]
     say("forced rebuild, timing, info")
     xr, vr, hr = gpu_trajectory([s], 61)
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         h1 = g.run(30)
         vb.vb_force_rebuild(g.ctx)
         h2 = g.run(1)
@@ -1274,7 +1274,7 @@ def test_launch_shapes_give_identical_bits():
         for unroll in (8, 4, 2, 1):
             for xcd in (0, 1, 2):
                 for pt in (256, 384, 512):
-                    with GpuRun([s], ov) as g:
+                    with GpuSession([s], ov) as g:
                         vb.vb_set_launch(g.ctx, unroll, xcd, pt)
                         assert vb.vb_get_launch(g.ctx) == {"unroll": unroll, "xcd_order": xcd,
                                                            "pairs_threads": pt}
@@ -1287,7 +1287,7 @@ def test_launch_shapes_give_identical_bits():
                     assert np.array_equal(x, ref[0]) and np.array_equal(v, ref[1]), what
                     assert np.array_equal(h, ref[2]), what
         say(f"  {name}: 36 launch shapes, identical")
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         for bad in ((3, 0, 384), (8, 3, 384), (8, -1, 384), (8, 0, 300)):
             with pytest.raises(vb.VbError) as e:
                 vb.vb_set_launch(g.ctx, *bad)
@@ -1303,7 +1303,7 @@ def test_tile_orders_on_a_system_of_several_tile_groups():
     assert s.n == 81920
     ref = None
     for xcd in (0, 1, 2):
-        with GpuRun([s]) as g:
+        with GpuSession([s]) as g:
             vb.vb_set_launch(g.ctx, 8, xcd, 384)
             h = g.run(100)
             x, v, _ = g.state()
@@ -1339,7 +1339,7 @@ def test_tuner_runs_the_same_steps_and_remembers_its_choice():
     import paper_2208_13770_amd as vb
     s = synth.config_systems("M1", seed=14)[0]
     xa, va, ha = gpu_trajectory([s], 240)
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         with pytest.raises(vb.VbError) as e:
             vb.vb_tune(g.ctx, 10)
         assert e.value.code == vb.VB_EINVAL
@@ -1352,5 +1352,5 @@ def test_tuner_runs_the_same_steps_and_remembers_its_choice():
     assert np.array_equal(h[0]["contacts"], ha[0]["contacts"])
     assert h[0]["step"].tolist() == list(range(240))
     assert h[0]["rebuilt"].sum() >= ha[0]["rebuilt"].sum()
-    with GpuRun([s]) as g:
+    with GpuSession([s]) as g:
         assert vb.vb_get_launch(g.ctx) == chosen

@@ -8,7 +8,7 @@ import pytest
 
 import paper_2208_13770_amd as vb
 import synth
-from tests._gpu import GpuRun, say
+from tests._gpu import GpuSession, say
 
 pytestmark = pytest.mark.gpu
 
@@ -36,14 +36,14 @@ def test_noalloc_export_equals_the_context_export():
     assert small.n < big.n
     for s in (big, small):  # the second call has the smaller input
         say(f"allocation-free export: N={s.n}")
-        with GpuRun([s]) as g:
+        with GpuSession([s]) as g:
             g.run(40)
             for which in (0, 1):
                 got = export(g.ctx, 0, which, True)
                 ref = export(g.ctx, 0, which, False)
                 same(ref, got, f"N={s.n} which={which}")
                 assert got[0] > 0
-    with GpuRun([big, small]) as g:  # one batch: system 0, then the smaller system 1
+    with GpuSession([big, small]) as g:  # one batch: system 0, then the smaller system 1
         g.run(25)
         for sys in (0, 1):
             same(export(g.ctx, sys, 0, False), export(g.ctx, sys, 0, True), f"batch system {sys}")
@@ -53,12 +53,12 @@ def test_noalloc_export_at_and_beyond_its_limit():
     at = synth.config_systems("M2", seed=0)[0]
     assert at.n == vb.VB_NOALLOC_MAX_N
     say(f"allocation-free export at the limit: N={at.n}")
-    with GpuRun([at]) as g:
+    with GpuSession([at]) as g:
         g.run(3)
         same(export(g.ctx, 0, 1, False), export(g.ctx, 0, 1, True), "M2")
     over = synth.lattice_system(257, 256, 64, 0, 0, 0.0, seed=1)
     assert over.n > vb.VB_NOALLOC_MAX_N
-    with GpuRun([over]) as g:
+    with GpuSession([over]) as g:
         with pytest.raises(vb.VbError) as e:
             vb.vb_get_pairs(g.ctx, 0, 0, noalloc=True)
         assert e.value.code == vb.VB_EINVAL and "allocation-free" in str(e.value)
