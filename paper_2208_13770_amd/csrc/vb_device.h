@@ -27,7 +27,8 @@ constexpr int BRICK = 4;          // cells per brick edge: cells are numbered br
 constexpr int MAX_CAND = 24;      // row entries per segment of the step kernel's two-pass scan
                                   // (24 KB of LDS candidates: five workgroups per CU)
 static_assert(MAX_CAND % 8 == 0, "segments start on a whole step of the largest unroll");
-constexpr int CONTACT_UNROLL = 2; // candidates whose records are requested together (4 waves/SIMD)
+constexpr int CONTACT_UNROLL = 2; // candidates whose records are requested together (94 VGPRs
+                                  // at U = 4: five waves per SIMD)
 constexpr int PAIRS_T = 384;      // threads of a pair-search workgroup (one brick): a brick of
                                   // 64 cells at about 5 particles per cell in one pass
 constexpr int BIN_PAD = 8;        // entries allocated past the last cell bin (read, never used)

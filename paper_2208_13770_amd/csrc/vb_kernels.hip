@@ -446,9 +446,9 @@ __global__ __launch_bounds__(TILE) void k_step(StepArgs a) {
         // one gather per entry, issued for every lane: an entry past the
         // segment reads the system's first code instead of its stale index, so
         // no gather sits behind a branch and the compiler waits for each alone
-        // (the extra requests all hit one line)
-        // (the system's codes from a base shared by the workgroup and a 32-bit
-        // byte offset: a system holds fewer than 2^28 particles)
+        // (the extra requests all hit one line).  Codes are addressed from the
+        // system's base, shared by the workgroup, with a 32-bit byte offset: a
+        // system holds at most 2^29 - 256 particles, so 8 x index fits.
         uint2 o[UNROLL];
         const char *pq = reinterpret_cast<const char *>(a.posq_cur + S.p_off);
 #pragma unroll
