@@ -104,3 +104,100 @@ def test_create_refuses_a_system_beyond_2_29_particles():
     with pytest.raises(vb.VbError) as e:
         vb.vb_create(s.params, 2 ** 29 - 255, stream=ctypes.c_void_p(0))
     assert e.value.code == vb.VB_EINVAL and "too large" in str(e.value)
+
+
+def _bad_params():
+    """(case, mutation of a valid vb_params, expected words of the message).
+    Every rejection that vb_create makes before touching the device."""
+    def setf(name, value):
+        return lambda q: setattr(q, name, value)
+
+    def seta(name, i, value):
+        return lambda q: getattr(q, name).__setitem__(i, value)
+
+    def plane(values):
+        def f(q):
+            q.n_planes = 1
+            q.planes[0][:] = values
+        return f
+
+    def cyl(values):
+        def f(q):
+            q.n_cylinders = 1
+            q.cylinders[0][:] = values
+        return f
+
+    def fixed_zero(q):
+        q.skin_mode = vb.VB_FIXED_INTERVAL
+        q.fixed_interval = 0
+
+    inf, nan = float("inf"), float("nan")
+    return [
+        ("skin_mode", setf("skin_mode", 4), "skin_mode"),
+        ("cap_mode", setf("cap_mode", 2), "cap_mode"),
+        ("dt zero", setf("dt", 0.0), "dt"),
+        ("dt negative", setf("dt", -1e-5), "dt"),
+        ("dt infinite", setf("dt", inf), "dt"),
+        ("dt nan", setf("dt", nan), "dt"),
+        ("cell_size zero", setf("cell_size", 0.0), "cell_size"),
+        ("cell_size nan", setf("cell_size", nan), "cell_size"),
+        ("K negative", setf("K", -1.0), "K must"),
+        ("K infinite", setf("K", inf), "K must"),
+        ("K nan", setf("K", nan), "K must"),
+        ("skin_uniform negative", setf("skin_uniform", -0.1), "skin_uniform"),
+        ("kn negative", setf("kn", -1.0), "kn and gamma_n"),
+        ("gamma_n nan", setf("gamma_n", nan), "kn and gamma_n"),
+        ("box empty", seta("hi", 0, 0.0), "lo < hi"),
+        ("box inverted", seta("lo", 2, 2.0), "lo < hi"),
+        ("box infinite", seta("hi", 1, inf), "lo < hi"),
+        ("gravity nan", seta("gravity", 2, nan), "gravity"),
+        ("max_neighbors zero", setf("max_neighbors", 0), "max_neighbors"),
+        ("max_neighbors above the row limit", setf("max_neighbors", 129), "max_neighbors"),
+        ("fixed interval zero", fixed_zero, "fixed_interval"),
+        ("reorder_interval negative", setf("reorder_interval", -1), "reorder_interval"),
+        ("bin_capacity negative", setf("bin_capacity", -1), "bin_capacity"),
+        ("bin_capacity above the limit", setf("bin_capacity", 257), "bin_capacity"),
+        ("kt negative", setf("kt", -1.0), "kt, gamma_t and mu"),
+        ("mu nan", setf("mu", nan), "kt, gamma_t and mu"),
+        ("contact_capacity above the limit", setf("contact_capacity", 65), "contact_capacity"),
+        ("n_planes above the limit", setf("n_planes", vb.VB_MAX_PLANES + 1), "n_planes"),
+        ("n_planes negative", setf("n_planes", -1), "n_planes"),
+        ("plane normal not unit", plane([0.0, 0.0, 2.0, 0.1, 0.0]), "unit length"),
+        ("plane nan", plane([0.0, 0.0, 1.0, nan, 0.0]), "plane values"),
+        ("plane height +inf", plane([0.0, 0.0, 1.0, 0.1, inf]), "plane values"),
+        ("n_cylinders above the limit", setf("n_cylinders", vb.VB_MAX_CYLINDERS + 1), "n_cylinders"),
+        ("cylinder radius zero", cyl([0.5, 0.5, 0.0, 0.0]), "radii"),
+        ("cylinder nan", cyl([nan, 0.5, 0.4, 0.0]), "cylinder values"),
+    ]
+
+
+@pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")
+@pytest.mark.parametrize("case,mutate,words", _bad_params(), ids=[c[0] for c in _bad_params()])
+def test_create_refuses_invalid_parameters(case, mutate, words):
+    """Each parameter check of vb_create and vb_batch_create returns VB_EINVAL
+    with a message that names the parameter, before any device call (so this
+    runs without a GPU) and without leaving a context behind."""
+    import synth
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    q = vb.make_params(s.params)
+    mutate(q)
+    with pytest.raises(vb.VbError) as e:
+        vb.vb_create(q, s.n, stream=ctypes.c_void_p(0))
+    assert e.value.code == vb.VB_EINVAL and words in str(e.value), str(e.value)
+    # in a batch the message names the system
+    good = vb.make_params(s.params)
+    with pytest.raises(vb.VbError) as e:
+        vb.vb_batch_create([good, q], [s.n, s.n], stream=ctypes.c_void_p(0))
+    assert e.value.code == vb.VB_EINVAL and "system 1" in str(e.value) and words in str(e.value)
+
+
+@pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")
+def test_create_refuses_negative_counts_and_batch_sizes():
+    import synth
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    with pytest.raises(vb.VbError) as e:
+        vb.vb_create(s.params, -1, stream=ctypes.c_void_p(0))
+    assert e.value.code == vb.VB_EINVAL and "n < 0" in str(e.value)
+    with pytest.raises(vb.VbError) as e:
+        vb.vb_batch_create([], [], stream=ctypes.c_void_p(0))
+    assert e.value.code == vb.VB_EINVAL and "n_sys" in str(e.value)
