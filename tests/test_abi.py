@@ -201,3 +201,37 @@ def test_create_refuses_negative_counts_and_batch_sizes():
     with pytest.raises(vb.VbError) as e:
         vb.vb_batch_create([], [], stream=ctypes.c_void_p(0))
     assert e.value.code == vb.VB_EINVAL and "n_sys" in str(e.value)
+
+
+@pytest.mark.skipif(not os.path.exists(vb.LIB_PATH), reason="libvbuf.so not built")
+def test_every_context_call_refuses_a_null_context():
+    """Every call that takes a context returns VB_EINVAL for a NULL one, with
+    vb_last_error(NULL) saying so; vb_destroy(NULL) does nothing; the create
+    calls refuse a NULL output handle.  No device call is made."""
+    L = vb.lib()
+    skip = {"vb_create", "vb_batch_create", "vb_last_error", "vb_destroy"}
+    called = []
+    for name, (res, args) in vb._SIGNATURES.items():
+        if name in skip:
+            continue
+        vals = []
+        for t in args:
+            if t is ctypes.c_double:
+                vals.append(0.0)
+            elif t in (ctypes.c_int32, ctypes.c_int64):
+                vals.append(0)
+            else:
+                vals.append(None)
+        assert getattr(L, name)(*vals) == vb.VB_EINVAL, name
+        assert L.vb_last_error(None) == b"ctx is NULL", name
+        called.append(name)
+    assert len(called) == 17
+    L.vb_destroy(None)
+    import synth
+    s = synth.lattice_system(4, 4, 4, 1, 1, 0.1, 0)
+    q = vb.make_params(s.params)
+    assert L.vb_create(ctypes.byref(q), s.n, None, None) == vb.VB_EINVAL
+    assert L.vb_last_error(None) == b"out is NULL"
+    n = (ctypes.c_int64 * 1)(s.n)
+    assert L.vb_batch_create(ctypes.byref(q), n, 1, None, None) == vb.VB_EINVAL
+    assert L.vb_last_error(None) == b"out is NULL"
