@@ -60,6 +60,12 @@ RECORD_DTYPE = np.dtype([
 _lib = None
 
 
+class Springs(ctypes.Structure):
+    """orc_springs: the tangential springs of the last step's contacts."""
+    _fields_ = [("off", ctypes.c_void_p), ("j", ctypes.c_void_p), ("xi", ctypes.c_void_p),
+                ("cap", ctypes.c_int64), ("n", ctypes.c_int64)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -86,6 +92,10 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.POINTER(Params), i64, dp, dp, dp, dp, i32, dp, dp, dp,
                               ip, i64, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_run_springs.restype = ctypes.c_int
+        L.orc_run_springs.argtypes = [ctypes.POINTER(Params), i64, dp, dp, dp, dp, i32, dp, dp,
+                                      dp, ip, i64, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(Springs)]
         _lib = L
     return _lib
 
@@ -219,3 +229,34 @@ def run(params: dict, x, v, rc, invm, n_steps, want_list=False):
             raise MemoryError("oracle out of memory")
         break
     return xo, vo, hist[:n_steps], (lst[: nl.value].copy() if want_list else None)
+
+
+def run_springs(params: dict, x, v, rc, invm, n_steps):
+    """run() that also returns the springs of the last step's contacts:
+    (x^S, v^{S-1/2}, records, (off, partner, spring)), where particle i's
+    contacts are entries off[i] .. off[i+1]-1, partners ascending, and spring
+    holds the pair's elongation as seen from i."""
+    x = _d(x, (-1, 3)); v = _d(v, (-1, 3)); rc = _d(rc); invm = _d(invm)
+    n = len(rc)
+    xo = np.zeros_like(x); vo = np.zeros_like(v)
+    hist = np.zeros(max(n_steps, 1), dtype=RECORD_DTYPE)
+    q = make_params(params)
+    off = np.zeros(n + 1, dtype=np.int64)
+    cap = 0
+    while True:
+        j = np.zeros(max(cap, 1), dtype=np.int32)
+        xi = np.zeros((max(cap, 1), 3))
+        spr = Springs(off.ctypes.data, j.ctypes.data, xi.ctypes.data, cap, 0)
+        rcode = lib().orc_run_springs(ctypes.byref(q), n, _ptr(x), _ptr(v), _ptr(rc), _ptr(invm),
+                                      int(n_steps), _ptr(xo), _ptr(vo),
+                                      hist.ctypes.data_as(ctypes.c_void_p), None, 0, None,
+                                      ctypes.byref(spr))
+        if rcode == -3:
+            cap = int(spr.n)
+            continue
+        if rcode == -1:
+            raise ValueError("oracle: invalid parameters")
+        if rcode == -2:
+            raise MemoryError("oracle out of memory")
+        break
+    return xo, vo, hist[:n_steps], (off.copy(), j[: spr.n].copy(), xi[: spr.n].copy())

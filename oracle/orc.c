@@ -501,6 +501,14 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
             const double *rc, const double *invm, int32_t n_steps, double *x_out,
             double *v_out, orc_record *hist, int32_t *list_out, int64_t list_cap,
             int64_t *list_n) {
+  return orc_run_springs(p, n, x_in, v_in, rc, invm, n_steps, x_out, v_out, hist, list_out,
+                         list_cap, list_n, NULL);
+}
+
+int orc_run_springs(const orc_params *p, int64_t n, const double *x_in, const double *v_in,
+                    const double *rc, const double *invm, int32_t n_steps, double *x_out,
+                    double *v_out, orc_record *hist, int32_t *list_out, int64_t list_cap,
+                    int64_t *list_n, orc_springs *spr) {
   if (n < 0 || n_steps < 0 || !(p->dt > 0.0) || !(p->cell_size > 0.0) || p->eps < 0.0) return -1;
   if (p->skin_mode == ORC_FIXED_INTERVAL && p->fixed_interval < 1) return -1;
   if (p->n_planes < 0 || p->n_planes > ORC_MAX_PLANES) return -1;
@@ -655,6 +663,18 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
   }
   memcpy(x_out, x, n3 * sizeof(double));
   memcpy(v_out, vh, n3 * sizeof(double));
+  if (spr) { /* the springs of the last step's contacts, as the next step would read them */
+    spr->n = fric ? H[cur_h].off[n] : 0;
+    if (spr->off) {
+      if (fric) memcpy(spr->off, H[cur_h].off, (size_t)(n + 1) * sizeof(int64_t));
+      else memset(spr->off, 0, (size_t)(n + 1) * sizeof(int64_t));
+    }
+    if (spr->n > spr->cap) ret = -3;
+    else if (spr->n > 0 && spr->j && spr->xi) {
+      memcpy(spr->j, H[cur_h].j, (size_t)spr->n * sizeof(int32_t));
+      memcpy(spr->xi, H[cur_h].xi, (size_t)spr->n * 3 * sizeof(double));
+    }
+  }
   if (list_n) {
     *list_n = L.n;
     if (list_out) {

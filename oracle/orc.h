@@ -122,4 +122,23 @@ int orc_run(const orc_params *p, int64_t n, const double *x_in, const double *v_
             double *v_out, orc_record *hist, int32_t *list_out, int64_t list_cap,
             int64_t *list_n);
 
+/* Tangential springs of the last step's contacts (friction on): for particle i,
+ * entries off[i] .. off[i+1]-1 hold its partners j (ascending) and the spring
+ * xi (3 doubles each) of the pair as seen from i.  off has n + 1 entries; j and
+ * xi hold cap entries; n is set to the number of entries. */
+typedef struct {
+  int64_t *off;
+  int32_t *j;
+  double *xi;
+  int64_t cap;
+  int64_t n;
+} orc_springs;
+
+/* orc_run that also exports the springs (spr may be NULL); -3 when they do
+ * not fit in spr->cap entries (spr->n then holds the count). */
+int orc_run_springs(const orc_params *p, int64_t n, const double *x_in, const double *v_in,
+                    const double *rc, const double *invm, int32_t n_steps, double *x_out,
+                    double *v_out, orc_record *hist, int32_t *list_out, int64_t list_cap,
+                    int64_t *list_n, orc_springs *spr);
+
 #endif

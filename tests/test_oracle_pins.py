@@ -448,6 +448,24 @@ def test_fixed_interval_misses_contacts(orc):
     assert np.array_equal(ha["contacts"], hn["contacts"])
 
 
+def test_fixed_interval_rebuilds_on_its_schedule_and_is_exact_with_a_safe_skin(orc):
+    """The conventional scheme the paper compares with (Sec. 1): the list is
+    rebuilt at step 0 and every I steps, whatever happens in between; with a
+    skin no particle outruns in I steps it misses no contact and gives results
+    identical to the contacts of all pairs at every step."""
+    s = colliding(0)
+    x, v, rc, invm = arrays(s)
+    p = dict(s.params, check_superset=1)
+    steps, I = 300, 5
+    fixed = dict(p, skin_mode=orc.FIXED_INTERVAL, fixed_interval=I, skin_uniform=float(rc.max()))
+    xf, vf, hf, _ = orc.run(fixed, x, v, rc, invm, steps)
+    xn, vn, hn, _ = orc.run(dict(p, skin_mode=orc.NAIVE), x, v, rc, invm, steps)
+    assert hn["contacts"].sum() > 100
+    assert np.array_equal(hf["rebuilt"] != 0, np.arange(steps) % I == 0)
+    assert hf["missed"].sum() == 0
+    assert np.array_equal(xf, xn) and np.array_equal(vf, vn)
+
+
 def test_uncapped_skin_in_validity_test_breaks_theorem(orc):
     """R4: Eq. update must use the skin left after the cap of Eq.
     skin_formulus_mincell.  Testing the displacement against the uncapped K|v|dt
@@ -870,6 +888,127 @@ def test_sticking_contact_is_an_elastic_tangential_rebound(orc):
     x, v, rc, invm, p = _collide(u_n, 0.3, {"mu": 0.3})
     _, vo, _, _ = orc.run(p, x, v, rc, invm, 400)
     assert 0.5 * (vo ** 2).sum() < 0.99 * 0.5 * (v ** 2).sum()
+
+
+def test_sticking_contact_with_tangential_damping_is_a_damped_oscillator(orc):
+    """A contact that sticks throughout (unbounded Coulomb limit), kt = kn, no
+    normal damping and a tangential dashpot gamma_t: the relative tangential
+    motion s'' + 2 gamma_t s' + 2 kt s = 0 (unit masses) is a damped oscillator
+    of w0 = sqrt(2 kt) and damping ratio z = gamma_t / w0, cut off when the
+    undamped normal contact ends at t_c = pi / w0.  Its textbook solution fixes
+    the relative tangential velocity the pair leaves with."""
+    k, z, u_n, u_t = 1e6, 0.2, 0.2, 0.01
+    w0 = np.sqrt(2 * k)
+    x, v, rc, invm, p = _collide(u_n, u_t, {"mu": 1e30, "gamma_t": z * w0}, k=k)
+    _, vo, h, _ = orc.run(p, x, v, rc, invm, 400)
+    assert h["contacts"][0] == 1 and h["contacts"][-1] == 0
+    wd, tc = w0 * np.sqrt(1 - z * z), np.pi / w0
+    expect = u_t * np.exp(-z * w0 * tc) * (np.cos(wd * tc) - z / np.sqrt(1 - z * z) * np.sin(wd * tc))
+    assert expect < -0.5 * u_t   # reversed, and damped to about half
+    rel = vo[0] - vo[1]
+    assert rel[1] == pytest.approx(expect, rel=2e-2)
+    assert rel[0] == pytest.approx(-u_n, rel=1e-3)   # the normal rebound is undamped
+
+
+def test_stored_springs_lie_in_the_tangent_plane_and_are_opposite(orc):
+    """The tangential spring is an elongation in the contact's tangent plane:
+    each step turns the previous spring into the plane normal to the current
+    contact normal before adding v_t dt, so the spring a step stores is normal
+    to the normal it was computed with (to rounding), however far the contact
+    has turned since it began; and the two particles of a pair hold opposite
+    springs.  A grazing collision that sticks (unbounded Coulomb limit, a soft
+    tangential spring) turns the normal by about 10^-2 rad in 100 steps."""
+    x, v, rc, invm, p = _collide(0.2, 0.5, {"mu": 1e30, "kt": 1e4})
+    for steps in (20, 60, 100):
+        xo, vo, h, (off, j, xi) = orc.run_springs(p, x, v, rc, invm, steps)
+        xr, vr, _, _ = orc.run(p, x, v, rc, invm, steps)
+        assert np.array_equal(xo, xr) and np.array_equal(vo, vr)
+        assert h["contacts"][-1] == 1 and list(off) == [0, 1, 2] and list(j) == [1, 0]
+        assert np.array_equal(xi[0], -xi[1])
+        # the last step's positions: the drift x^S = x^{S-1} + dt v^{S-1/2}, undone
+        xp = xo - p["dt"] * vo
+        nrm = (xp[0] - xp[1]) / np.linalg.norm(xp[0] - xp[1])
+        turned = np.arccos(np.clip(nrm @ (x[0] - x[1]) / np.linalg.norm(x[0] - x[1]), -1, 1))
+        assert turned > 1e-3 * steps / 20
+        assert abs(xi[0] @ nrm) <= 1e-12 * np.linalg.norm(xi[0])
+        assert np.linalg.norm(xi[0]) > 0.5 * 0.5 * steps * p["dt"]   # it did grow
+
+
+def _damped_normal_impulses(k, gamma_n, u_n):
+    """Positive and negative parts of the normal impulse of a linear
+    spring-dashpot collision of two unit masses: the overlap obeys
+    d'' + 2 gamma_n d' + 2 k d = 0 with d(0) = 0, d'(0) = u_n, the force is
+    k d + gamma_n d', and the contact lasts while d > 0 (t < pi / w_d)."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+    w0 = np.sqrt(2 * k)
+    z = gamma_n / w0
+    wd = w0 * np.sqrt(1 - z * z)
+    d = lambda t: u_n / wd * np.exp(-z * w0 * t) * np.sin(wd * t)
+    dp = lambda t: u_n * np.exp(-z * w0 * t) * (np.cos(wd * t) - z * w0 / wd * np.sin(wd * t))
+    f = lambda t: k * d(t) + gamma_n * dp(t)
+    end = np.pi / wd
+    t0 = brentq(f, 0.5 * end, end * (1 - 1e-12))   # the force turns attractive once
+    pos = quad(f, 0.0, t0, epsabs=0.0, epsrel=1e-12)[0]
+    neg = -quad(f, t0, end, epsabs=0.0, epsrel=1e-12)[0]
+    return pos, neg, np.exp(-z * np.pi / np.sqrt(1 - z * z))
+
+
+def test_sliding_limit_follows_the_compressive_part_of_the_normal_force(orc):
+    """Coulomb's limit is mu times the normal force where it compresses and zero
+    where the normal dashpot pulls the separating pair together: over a damped
+    collision that slides throughout, the tangential impulse is mu times the
+    positive part of the normal impulse, which the textbook solution of the
+    damped normal contact gives (here the pulling part is 5 % of it).  The
+    normal impulse itself gives the restitution coefficient exp(-z pi / sqrt(1 - z^2))."""
+    k, z, u_n, u_t, mu = 1e6, 0.3, 0.002, 0.005, 0.3
+    gamma_n = z * np.sqrt(2 * k)
+    # a stiff tangential spring: the contact slides from its first step on
+    x, v, rc, invm, p = _collide(u_n, u_t, {"mu": mu, "gamma_n": gamma_n, "kt": 1e8}, k=k)
+    _, vo, h, _ = orc.run(p, x, v, rc, invm, 400)
+    assert h["contacts"][0] == 1 and h["contacts"][-1] == 0
+    pos, neg, e = _damped_normal_impulses(k, gamma_n, u_n)
+    assert neg > 0.05 * pos
+    du = (vo[0] - vo[1]) - (v[0] - v[1])
+    # the dashpot's first-order time-step error: 1.4e-3 (normal) and 1.9e-3
+    # (tangential) at dt = 2^-17, 0.7e-3 and 1.2e-3 at half of it
+    assert abs(du[0]) == pytest.approx(2 * (pos - neg), rel=4e-3)
+    assert abs(du[0]) == pytest.approx(u_n * (1 + e), rel=4e-3)
+    assert du[1] < 0 and (vo[0] - vo[1])[1] > 0      # slowed, never reversed
+    assert abs(du[1]) == pytest.approx(2 * mu * pos, rel=1e-2)
+
+
+def test_slide_then_stick_settles_where_the_closed_form_puts_it(orc):
+    """Sphere B on sphere A on the (frictionless) floor under gravity g, both at
+    their static overlaps; B starts with a horizontal velocity u.  Unit masses,
+    normal force g.  While the contact slides, the relative velocity w falls at
+    2 mu g and the stored spring is the one that gives the force on the cone,
+    kt s = mu g - gamma_t w; the trial force of the next instant exceeds the cone
+    as long as kt w > 2 mu g gamma_t, so the contact sticks at
+    w* = 2 mu g gamma_t / kt, after sliding (u^2 - w*^2) / (4 mu g).  The damped
+    spring then relaxes to zero, which moves the pair back by its value at
+    sticking, (mu g - gamma_t w*) / kt, and both spheres end at u / 2.  Storing
+    the spring without its dashpot part would give u^2 / (4 mu g) - mu g / kt,
+    3 % less here; keeping the slid distance in it would undo the slide."""
+    R, g, kn, kt, mu, u = 2.0 ** -6, 1.0, 1e6, 1e6, 0.5, 4e-3
+    gamma_t = 0.5 * np.sqrt(2 * kt)
+    z_a = R - 2 * g / kn
+    x = np.array([[0.5, 0.5, z_a], [0.5, 0.5, z_a + 2 * R - g / kn]])
+    v = np.array([[0.0, 0.0, 0.0], [u, 0.0, 0.0]])
+    p = {"skin_mode": 0, "K": 200.0, "dt": 2.0 ** -17, "cell_size": 2.0 ** -3, "eps": 0.0,
+         "lo": (0, 0, 0), "hi": (1, 1, 1), "kn": kn, "gamma_n": 200.0, "g": (0, 0, -g),
+         "kt": kt, "gamma_t": gamma_t, "mu": mu}
+    xo, vo, h, _ = orc.run(p, x, v, np.full(2, R), np.ones(2), 2800)
+    assert (h["contacts"] == 1).all()          # B stays on A throughout (walls not counted)
+    w_stick = 2 * mu * g * gamma_t / kt
+    assert (u - w_stick) / (2 * mu * g) < 0.25 * 2800 * p["dt"]   # then 12 decay times
+    expect = (u * u - w_stick ** 2) / (4 * mu * g) - (mu * g - gamma_t * w_stick) / kt
+    without_dashpot_part = u * u / (4 * mu * g) - mu * g / kt
+    assert abs(without_dashpot_part - expect) > 0.03 * expect
+    offset = (xo[1, 0] - xo[0, 0]) - (x[1, 0] - x[0, 0])
+    # first-order time-step error: 8e-4 at dt = 2^-17, 6e-4 at half of it
+    assert offset == pytest.approx(expect, rel=5e-3)
+    assert vo[0, 0] == pytest.approx(0.5 * u, rel=1e-5) and vo[1, 0] == pytest.approx(0.5 * u, rel=1e-5)
 
 
 def test_friction_conserves_momentum_and_the_method_stays_exact(orc):
