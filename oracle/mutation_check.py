@@ -53,6 +53,13 @@ MUT = [
  ("history lookup past the partner", "while (h < h_end && old->j[h] < j) h++;", "while (h < h_end && old->j[h] <= j) h++;"),
  ("fixed interval offset", "rebuild = (step % p->fixed_interval) == 0;", "rebuild = ((step + 1) % p->fixed_interval) == 0;"),
  ("uniform skin from K", "case ORC_FIXED_INTERVAL: skin = p->skin_uniform; break;", "case ORC_FIXED_INTERVAL: skin = p->K * norm3(v + 3 * i) * p->dt; break;"),
+ ("force overlap from own radius", "double delta = rc[i] + rc[j] - d;", "double delta = 2.0 * rc[i] - d;"),
+ ("contact test from own radius", "  return ri + rj - dist3(xi, xj);", "  return 2.0 * ri - dist3(xi, xj);"),
+ ("broad phase from own radius", "if (dist3(x + 3 * pa, x + 3 * pb) <= r[pa] + r[pb] + eps) {", "if (dist3(x + 3 * pa, x + 3 * pb) <= 2.0 * r[pa] + eps) {"),
+ ("no rebuild at step 0", "else rebuild = (step == 0) || violated;", "else rebuild = violated;"),
+ ("second half-kick dropped", "vh[3 * i + a] = vfull[a] + hdt * acc;", "vh[3 * i + a] = vfull[a];"),
+ ("displacement from the current position", "double disp = dist3(x + 3 * i, x0 + 3 * i);", "double disp = dist3(x + 3 * i, x + 3 * i);"),
+ ("plane distance without offset", "double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2] - pl[3];", "double s = pl[0] * xi[0] + pl[1] * xi[1] + pl[2] * xi[2];"),
 ]
 dst = os.path.join(tempfile.mkdtemp(prefix='orc_mut_'), 'repo')
 results = []
