@@ -3,7 +3,8 @@
 The generators hold none of the method's arithmetic; both the oracle and the
 HIP path read their output.  These checks pin what the inputs are: the sizes of
 every named workload, the jittered lattice (spacing, jitter bound, radius, no
-initial overlap), the velocity regions and their Gaussian noise, and that a
+initial overlap), the velocity regions and their Gaussian noise, the walls and
+gravity of the stand-ins, and that a
 seed fixes every value (also when the systems of a batch are generated in a
 process pool).
 """
@@ -102,3 +103,42 @@ def test_velocity_regions_and_noise():
     assert noise.std() == pytest.approx(sd, rel=0.02)
     # Gaussian tails: about 0.27 % beyond three standard deviations
     assert (np.abs(noise) > 3 * sd).mean() == pytest.approx(0.0027, abs=0.001)
+
+
+def test_gravity_stand_in_geometries():
+    """The hopper's two walls are unit normals at 30 degrees from the vertical
+    (n_z = sin 30 degrees), acting above the outlet (11 spacings: a 10-site bin);
+    the silo's cylinder stands on the box's axis and acts above its 4-spacing gap;
+    the incline's gravity is tilted by 25 degrees about y.  No particle starts
+    overlapping a wall, and radii are polydisperse in [0.35 a, 0.45 a] with
+    mass proportional to volume."""
+    (h,) = synth.config_systems("H125")
+    a = h.meta["a"]
+    x = h.pos_r[:, :3].astype(np.float64)
+    r = h.pos_r[:, 3].astype(np.float64)
+    assert len(h.params["planes"]) == 2
+    for pl in h.params["planes"]:
+        n = np.array(pl[:3])
+        assert np.linalg.norm(n) == pytest.approx(1.0, abs=1e-15)
+        assert n[2] == pytest.approx(0.5, rel=1e-7) and abs(n[0]) == pytest.approx(np.sqrt(0.75), rel=1e-7)
+        assert pl[4] == pytest.approx(11 * a, rel=1e-6)
+        above = x[:, 2] > pl[4]
+        assert above.all() and ((x @ n - pl[3]) - r > 0).all()
+    assert r.min() >= 0.35 * a * (1 - 1e-6) and r.max() <= 0.45 * a * (1 + 1e-6)
+    m = 1.0 / h.vel_m[:, 3].astype(np.float64)
+    assert np.allclose(m, (r / (0.45 * a)) ** 3, rtol=1e-5)
+    assert h.params["g"][0] == 0 and h.params["g"][1] == 0 and h.params["g"][2] < 0
+
+    (s,) = synth.config_systems("SILO")
+    a = s.meta["a"]
+    x = s.pos_r[:, :3].astype(np.float64)
+    r = s.pos_r[:, 3].astype(np.float64)
+    (cx, cy, R, z_min), = s.params["cylinders"]
+    hi = np.array(s.params["hi"])
+    assert cx == pytest.approx(0.5 * hi[0], rel=1e-6) and cy == pytest.approx(0.5 * hi[1], rel=1e-6)
+    assert z_min == pytest.approx(4.5 * a, rel=1e-6)
+    assert ((R - np.hypot(x[:, 0] - cx, x[:, 1] - cy)) - r > 0).all()
+
+    (i,) = synth.config_systems("INCLINE")
+    g = np.array(i.params["g"])
+    assert np.degrees(np.arctan2(g[0], -g[2])) == pytest.approx(25.0, abs=1e-5) and g[1] == 0
