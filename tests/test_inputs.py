@@ -4,9 +4,8 @@ The generators hold none of the method's arithmetic; both the oracle and the
 HIP path read their output.  These checks pin what the inputs are: the sizes of
 every named workload, the jittered lattice (spacing, jitter bound, radius, no
 initial overlap), the velocity regions and their Gaussian noise, the walls and
-gravity of the stand-ins, and that a
-seed fixes every value (also when the systems of a batch are generated in a
-process pool).
+gravity of the stand-ins, and that a seed fixes every value (also when the
+systems of a batch are generated in a process pool).
 """
 import numpy as np
 import pytest
