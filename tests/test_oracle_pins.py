@@ -934,6 +934,30 @@ def test_stored_springs_lie_in_the_tangent_plane_and_are_opposite(orc):
         assert np.linalg.norm(xi[0]) > 0.5 * 0.5 * steps * p["dt"]   # it did grow
 
 
+def test_springs_of_a_frictional_cascade_are_tangent_and_opposite(orc):
+    """The same invariants over every contact of a frictional cascade: each
+    particle's contacts come in ascending partner order, the two springs of a
+    pair are exact opposites, and every spring is normal to its contact normal
+    to rounding."""
+    s = synth.config_systems("M1", seed=2, scale=0.4)[0]
+    x, v, rc, invm = arrays(s)
+    p = dict(s.params, kt=0.5 * s.params["kn"], gamma_t=0.5 * s.params["gamma_n"], mu=0.4,
+             lo=(-10, -10, -10), hi=(11, 11, 11))
+    xo, vo, h, (off, j, xi) = orc.run_springs(p, x, v, rc, invm, 150)
+    assert len(j) == 2 * h["contacts"][-1] > 20 and off[-1] == len(j)
+    xp = xo - p["dt"] * vo
+    where = {}
+    for i in range(len(rc)):
+        part = j[off[i]:off[i + 1]]
+        assert (np.diff(part) > 0).all()
+        for e, jj in zip(range(off[i], off[i + 1]), part):
+            where[(i, int(jj))] = e
+    for (i, jj), e in where.items():
+        assert np.array_equal(xi[e], -xi[where[(jj, i)]])
+        nrm = (xp[i] - xp[jj]) / np.linalg.norm(xp[i] - xp[jj])
+        assert abs(xi[e] @ nrm) <= 1e-12 * np.linalg.norm(xi[e]) + 1e-300
+
+
 def _damped_normal_impulses(k, gamma_n, u_n):
     """Positive and negative parts of the normal impulse of a linear
     spring-dashpot collision of two unit masses: the overlap obeys
