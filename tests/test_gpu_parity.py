@@ -1037,6 +1037,43 @@ def test_checkpoint_resume_with_friction_history_bitwise():
     assert not np.array_equal(xa, xc)
 
 
+def test_friction_history_equals_the_oracle_springs():
+    """The springs the step kernel carries from step to step are the oracle's, bit
+    for bit: after 150 frictional steps on M1, every particle's contacts
+    (vb_get_history: partners in ascending original index) and the elongation
+    vector of each equal the oracle's exported springs."""
+    import torch
+    import paper_2208_13770_amd as vb
+    s = synth.config_systems("M1", seed=1)[0]
+    fr = _frictional(s)
+    steps = 150
+    say(f"friction history against the oracle's springs: N={s.n}, {steps} steps")
+    x, v, rc, invm = host_arrays([s])
+    xo, vo, ho, (off, j, xi) = oracle.run_springs(dict(s.params, **fr), x, v, rc, invm, steps)
+    with GpuSession([s], fr) as g:
+        g.run(steps)
+        xg, vg, _ = g.state()
+        need = vb.vb_get_history(g.ctx)
+        partner = torch.empty((s.n, need), dtype=torch.int32, device="cuda")
+        spring = torch.empty((s.n, need, 3), dtype=torch.float64, device="cuda")
+        assert vb.vb_get_history(g.ctx, partner, spring) == need
+    assert_close(s, xg, vg, xo, vo, "M1 with friction")
+    cnt = np.diff(off)
+    assert need == cnt.max() and len(j) > 20
+    po = np.full((s.n, need), -1, dtype=np.int32)
+    so = np.zeros((s.n, need, 3))
+    row = np.repeat(np.arange(s.n), cnt)
+    col = np.arange(len(j)) - np.repeat(off[:-1], cnt)
+    po[row, col] = j
+    so[row, col] = xi
+    pg, sg = partner.cpu().numpy(), spring.cpu().numpy()
+    assert np.array_equal(pg, po)
+    used = po >= 0
+    nd = int((sg[used] != so[used]).sum())
+    say(f"  {len(j)} springs, {nd} components differ from the oracle's")
+    assert nd == 0
+
+
 def test_history_input_is_checked():
     import torch
     import paper_2208_13770_amd as vb
